@@ -1,0 +1,203 @@
+"""CPU oracle for LB_Enhanced-pruned NN-DTW (FP64, plain C via ctypes).
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` are the only code allowed to import this
+package.  The GPU library shares no code with it.
+
+Every function takes float32 numpy arrays (the same arrays the GPU path
+consumes) and computes in float64; see ``nndtw_oracle.c`` for the paper
+passage each routine follows.  ``paths.py`` adds a brute-force enumeration of
+warping paths for tiny series.
+
+Parity status: every routine here is pinned by ``tests/test_oracle_pins.py``
+(closed forms, theorems of the paper, brute force and library routines).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "nndtw_oracle.c")
+LIB = os.path.join(HERE, "_nndtw_oracle.so")
+# A planted-mistake build of the oracle (mutation tests only) may be loaded instead.
+_ALT = os.environ.get("NNDTW_ORACLE_LIB")
+
+CASCADE = {"none": 0, "keogh": 1, "keogh_enh": 2, "enh": 3}
+COUNT_NAMES = ("n", "pruned_keogh", "pruned_enh_bands", "pruned_enh", "dtw_started",
+               "dtw_abandoned", "cells", "fp64_rechecks")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, FP contraction off, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if _ALT:
+            L = ctypes.CDLL(_ALT)
+        else:
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+                build(force=True)
+            L = ctypes.CDLL(LIB)
+        d, i32, i64, p = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+        sig = {
+            "oracle_slack": (d, [i32]),
+            "oracle_envelopes": (None, [p, i64, i32, i32, p, p]),
+            "oracle_ed2": (d, [p, p, i32]),
+            "oracle_lb_keogh": (d, [p, p, p, i32]),
+            "oracle_band_cells": (i32, [i32, i32, i32, i32, p, p]),
+            "oracle_left_bands_sum": (d, [p, p, i32, i32]),
+            "oracle_right_bands_sum": (d, [p, p, i32, i32]),
+            "oracle_lb_enhanced_eq7": (d, [p, p, p, p, i32, i32, i32]),
+            "oracle_lb_enhanced_bands": (d, [p, p, i32, i32, i32]),
+            "oracle_lb_enhanced_alg1": (d, [p, p, p, p, i32, i32, i32, d]),
+            "oracle_dtw": (d, [p, p, i32, i32]),
+            "oracle_dtw_abandon": (d, [p, p, i32, i32, d]),
+            "oracle_ed2_batch": (None, [p, i64, p, i64, i32, i32, p]),
+            "oracle_lb_keogh_batch": (None, [p, i64, p, p, i64, i32, i32, p]),
+            "oracle_lb_enhanced_batch": (None, [p, i64, p, p, p, i64, i32, i32, i32, p, i32, i32, p]),
+            "oracle_dtw_batch": (None, [p, i64, p, i64, i32, i32, p, i32, p]),
+            "oracle_brute_nn": (None, [p, i64, p, i64, i32, i32, p, p]),
+            "oracle_search": (None, [p, i64, p, i64, i32, i32, i32, i32, i64, i32, p, p, p]),
+            "oracle_max_threads": (i32, []),
+            "oracle_set_threads": (None, [i32]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _f32(x):
+    return np.ascontiguousarray(x, dtype=np.float32)
+
+
+def _ptr(x):
+    return x.ctypes.data_as(ctypes.c_void_p) if x is not None else None
+
+
+def _one(x):
+    x = _f32(x)
+    return x.reshape(1, -1) if x.ndim == 1 else x
+
+
+def slack(L: int) -> float:
+    return lib().oracle_slack(int(L))
+
+
+def set_threads(n: int) -> None:
+    lib().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return lib().oracle_max_threads()
+
+
+def envelopes(B, W):
+    B = _one(B)
+    n, L = B.shape
+    U = np.empty_like(B)
+    Lo = np.empty_like(B)
+    lib().oracle_envelopes(_ptr(B), n, L, int(W), _ptr(U), _ptr(Lo))
+    return U, Lo
+
+
+def _pairing(A, B, zip_):
+    if zip_ and A.shape[0] != B.shape[0]:
+        raise ValueError("zip pairing needs equal counts")
+    return (A.shape[0],) if zip_ else (A.shape[0], B.shape[0])
+
+
+def ed2(A, B, zip_=False):
+    A, B = _one(A), _one(B)
+    out = np.empty(_pairing(A, B, zip_), np.float64)
+    lib().oracle_ed2_batch(_ptr(A), A.shape[0], _ptr(B), B.shape[0], A.shape[1], int(zip_), _ptr(out))
+    return out
+
+
+def lb_keogh(A, U, Lo, zip_=False):
+    A, U, Lo = _one(A), _one(U), _one(Lo)
+    out = np.empty(_pairing(A, U, zip_), np.float64)
+    lib().oracle_lb_keogh_batch(_ptr(A), A.shape[0], _ptr(U), _ptr(Lo), U.shape[0], A.shape[1],
+                                int(zip_), _ptr(out))
+    return out
+
+
+def lb_enhanced(A, B, U, Lo, W, V, cutoff=None, zip_=False, variant="alg1"):
+    """variant: 'eq7' (Equation 7), 'alg1' (Algorithm 1), 'bands' (Algorithm 1 bands part)."""
+    A, B, U, Lo = _one(A), _one(B), _one(U), _one(Lo)
+    out = np.empty(_pairing(A, B, zip_), np.float64)
+    cut = None if cutoff is None else np.ascontiguousarray(np.broadcast_to(
+        np.asarray(cutoff, np.float64), (A.shape[0],)))
+    v = {"eq7": 0, "alg1": 1, "bands": 2}[variant]
+    lib().oracle_lb_enhanced_batch(_ptr(A), A.shape[0], _ptr(B), _ptr(U), _ptr(Lo), B.shape[0],
+                                   A.shape[1], int(W), int(V), _ptr(cut), int(zip_), v, _ptr(out))
+    return out
+
+
+def dtw(A, B, W, cutoff=None, zip_=False):
+    A, B = _one(A), _one(B)
+    out = np.empty(_pairing(A, B, zip_), np.float64)
+    cut = None if cutoff is None else np.ascontiguousarray(np.broadcast_to(
+        np.asarray(cutoff, np.float64), (A.shape[0],)))
+    lib().oracle_dtw_batch(_ptr(A), A.shape[0], _ptr(B), B.shape[0], A.shape[1], int(W), _ptr(cut),
+                           int(zip_), _ptr(out))
+    return out
+
+
+def left_bands_sum(a, b, W):
+    a, b = _f32(a), _f32(b)
+    return lib().oracle_left_bands_sum(_ptr(a), _ptr(b), a.shape[0], int(W))
+
+
+def right_bands_sum(a, b, W):
+    a, b = _f32(a), _f32(b)
+    return lib().oracle_right_bands_sum(_ptr(a), _ptr(b), a.shape[0], int(W))
+
+
+def band_cells(L, W, side, i):
+    """Links (j, k) of the left (side 0), right (1) or vertical (2) band at i (0-based)."""
+    rows = np.zeros(2 * L + 2, np.int32)
+    cols = np.zeros(2 * L + 2, np.int32)
+    n = lib().oracle_band_cells(int(L), int(W), int(side), int(i), _ptr(rows), _ptr(cols))
+    return list(zip(rows[:n].tolist(), cols[:n].tolist()))
+
+
+def brute_nn(refs, queries, W):
+    refs, queries = _one(refs), _one(queries)
+    Q = queries.shape[0]
+    idx = np.empty(Q, np.int64)
+    dist = np.empty(Q, np.float64)
+    lib().oracle_brute_nn(_ptr(refs), refs.shape[0], _ptr(queries), Q, refs.shape[1], int(W),
+                          _ptr(idx), _ptr(dist))
+    return idx, dist
+
+
+def search(refs, queries, W, V, cascade="keogh_enh", R=1, init_ub=True):
+    """Round-based lower-bound search; returns (nn_idx, nn_dist, counts[Q][8])."""
+    refs, queries = _one(refs), _one(queries)
+    Q = queries.shape[0]
+    idx = np.empty(Q, np.int64)
+    dist = np.empty(Q, np.float64)
+    counts = np.zeros((Q, 8), np.int64)
+    lib().oracle_search(_ptr(refs), refs.shape[0], _ptr(queries), Q, refs.shape[1], int(W), int(V),
+                        CASCADE[cascade], int(R), int(bool(init_ub)), _ptr(idx), _ptr(dist),
+                        _ptr(counts))
+    return idx, dist, counts

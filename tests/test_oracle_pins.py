@@ -1,0 +1,390 @@
+"""Pins for the CPU oracle: checks against what the paper and mathematics fix.
+
+None of these re-type the oracle's formulas: they compare it with brute-force
+path enumeration, closed forms (Delannoy numbers, the W=0 and W>=L-1 special
+cases), the theorems of the paper (Theorems 1 and 2, Equation 6), library
+routines (numpy sliding windows) and a hand-derived worked example.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import paths
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _pairs(n, L, seed, kind="rw"):
+    x = synth.random_series(2 * n, L, seed, kind)
+    return x[:n], x[n:]
+
+
+# ---------------------------------------------------------------- paths / DTW
+def test_path_counts_delannoy():
+    rows = [l.split() for l in open(os.path.join(GOLD, "delannoy.txt")) if l.strip() and l[0] != "#"]
+    for L, cnt in rows:
+        assert paths.count_paths(int(L)) == int(cnt)
+
+
+def test_windowed_path_counts_small():
+    # W = 0 leaves only the diagonal; a window never adds paths.
+    for L in range(1, 8):
+        assert paths.count_paths(L, 0) == 1
+        counts = [paths.count_paths(L, w) for w in range(L)]
+        assert counts == sorted(counts)
+        assert counts[-1] == paths.count_paths(L)
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6, 7])
+def test_dtw_equals_min_over_enumerated_paths(orc, L):
+    A, B = _pairs(3, L, seed=L)
+    for a, b in zip(A, B):
+        for W in range(L):
+            want = paths.dtw_brute(a, b, W)
+            got = orc.dtw(a, b, W)[0, 0]
+            # The recurrence takes the min of left-to-right path sums; with
+            # monotone rounding that is bit-identical to the brute force.
+            assert got == want, (L, W, got, want)
+
+
+def test_dtw_equals_min_over_enumerated_paths_L8(orc):
+    a, b = _pairs(1, 8, seed=88, kind="normal")
+    for W in (1, 3, 7):
+        assert orc.dtw(a[0], b[0], W)[0, 0] == paths.dtw_brute(a[0], b[0], W)
+
+
+def test_worked_example(orc):
+    fx = {}
+    for line in open(os.path.join(GOLD, "worked_example.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        parts = line.split()
+        key = " ".join(p for p in parts if not _isnum(p))
+        fx[key] = [float(p) for p in parts if _isnum(p)]
+    a = np.array(fx["A"], np.float32)
+    b = np.array(fx["B"], np.float32)
+    assert orc.dtw(a, b, 10)[0, 0] == fx["dtw W=inf"][0]
+    assert orc.dtw(a, b, 1)[0, 0] == fx["dtw W=1"][0]
+    assert orc.dtw(a, b, 0)[0, 0] == fx["dtw W=0"][0]
+    U, Lo = orc.envelopes(b, 1)
+    assert U[0].tolist() == fx["U W=1"]
+    assert Lo[0].tolist() == fx["Lo W=1"]
+    assert orc.lb_keogh(a, U, Lo)[0, 0] == fx["lb_keogh W=1"][0]
+    assert orc.lb_enhanced(a, b, U, Lo, 1, 1)[0, 0] == fx["lb_enhanced W=1 V=1"][0]
+    assert orc.lb_enhanced(a, b, U, Lo, 1, 2)[0, 0] == fx["lb_enhanced W=1 V=2"][0]
+    U0, L0 = orc.envelopes(b, 0)
+    assert orc.lb_keogh(a, U0, L0)[0, 0] == fx["lb_keogh W=0"][0]
+    assert orc.lb_enhanced(a, b, U0, L0, 0, 1)[0, 0] == fx["lb_enhanced W=0 V=1"][0]
+
+
+def _isnum(s):
+    try:
+        float(s)
+        return True
+    except ValueError:
+        return False
+
+
+def test_dtw_special_cases(orc):
+    A, B = _pairs(6, 37, seed=5)
+    ed = orc.ed2(A, B, zip_=True)
+    d0 = orc.dtw(A, B, 0, zip_=True)
+    assert np.array_equal(d0, ed)                                   # DTW_0 = squared ED
+    assert np.array_equal(ed, ((A.astype(np.float64) - B) ** 2).sum(1)) or np.allclose(
+        ed, ((A.astype(np.float64) - B) ** 2).sum(1), rtol=1e-14)
+    for W in (0, 2, 9, 36, 50):
+        dab = orc.dtw(A, B, W, zip_=True)
+        dba = orc.dtw(B, A, W, zip_=True)
+        assert np.array_equal(dab, dba)                             # symmetric
+        assert np.all(orc.dtw(A, A, W, zip_=True) == 0.0)           # DTW(A,A) = 0
+        # exact scaling by powers of two
+        assert np.array_equal(orc.dtw(2 * A, 2 * B, W, zip_=True), 4 * dab)
+    full = orc.dtw(A, B, 36, zip_=True)
+    assert np.array_equal(full, orc.dtw(A, B, 37, zip_=True))        # W >= L-1 unconstrained
+    assert np.array_equal(full, orc.dtw(A, B, 10 ** 6, zip_=True))
+    prev = None
+    for W in range(0, 37):
+        d = orc.dtw(A, B, W, zip_=True)
+        if prev is not None:
+            assert np.all(d <= prev)                                # nonincreasing in W
+        prev = d
+
+
+def test_dtw_abandon(orc):
+    A, B = _pairs(20, 48, seed=6)
+    full = orc.dtw(A, B, 5, zip_=True)
+    for f in (0.3, 0.9, 1.0, 1.1):
+        cut = full * f
+        got = orc.dtw(A, B, 5, cutoff=cut, zip_=True)
+        for g, d, c in zip(got, full, cut):
+            if math.isinf(g):
+                assert d > c                        # abandoned only when above the cutoff
+            else:
+                assert g == d
+
+
+# ---------------------------------------------------------------- envelopes
+def _np_envelopes(b, W):
+    L = b.shape[-1]
+    w = min(W, L - 1)
+    hi = np.pad(b, (w, w), constant_values=-np.inf)
+    lo = np.pad(b, (w, w), constant_values=np.inf)
+    win_hi = np.lib.stride_tricks.sliding_window_view(hi, 2 * w + 1)
+    win_lo = np.lib.stride_tricks.sliding_window_view(lo, 2 * w + 1)
+    return win_hi.max(-1), win_lo.min(-1)
+
+
+@pytest.mark.parametrize("L", [2, 3, 17, 64, 257])
+def test_envelopes_vs_sliding_window(orc, L):
+    B = synth.random_series(5, L, seed=L)
+    for W in sorted({0, 1, 2, 5, L // 3, L - 2, L - 1, L, 3 * L}):
+        if W < 0:
+            continue
+        U, Lo = orc.envelopes(B, W)
+        for s in range(B.shape[0]):
+            u, l = _np_envelopes(B[s], W)
+            assert np.array_equal(U[s], u.astype(np.float32))
+            assert np.array_equal(Lo[s], l.astype(np.float32))
+        assert np.all(Lo <= B) and np.all(B <= U)
+    U0, L0 = orc.envelopes(B, 0)
+    assert np.array_equal(U0, B) and np.array_equal(L0, B)
+    Uf, Lf = orc.envelopes(B, L - 1)
+    assert np.array_equal(Uf, np.repeat(B.max(1, keepdims=True), L, 1))
+    assert np.array_equal(Lf, np.repeat(B.min(1, keepdims=True), L, 1))
+
+
+# ---------------------------------------------------------------- LB_Keogh
+def test_lb_keogh_properties(orc):
+    A, B = _pairs(40, 64, seed=11)
+    ed = orc.ed2(A, B, zip_=True)
+    prev = None
+    for W in (0, 1, 3, 6, 12, 32, 63):
+        U, Lo = orc.envelopes(B, W)
+        lbk = orc.lb_keogh(A, U, Lo, zip_=True)
+        d = orc.dtw(A, B, W, zip_=True)
+        assert np.all(lbk <= d)                                     # lower bound
+        assert np.all(lbk >= 0)
+        assert np.all(orc.lb_keogh(B, U, Lo, zip_=True) == 0.0)      # B inside its own envelope
+        if W == 0:
+            assert np.array_equal(lbk, ed)                          # W=0: squared ED
+        if prev is not None:
+            assert np.all(lbk <= prev)                              # nonincreasing in W
+        prev = lbk
+
+
+# ---------------------------------------------------------------- band sets
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6])
+def test_bands_are_crossed_by_every_path(orc, L):
+    """Theorem 1 (and its mirror for Equation 6): every warping path inside the
+    window contains at least one link of every left band and every right band."""
+    for W in range(L):
+        P = [set(p) for p in paths.enumerate_paths(L, W)]
+        for i in range(L):
+            left = set(orc.band_cells(L, W, 0, i))
+            right = set(orc.band_cells(L, W, 1, i))
+            assert len(left) == 2 * min(i, W) + 1
+            assert len(right) == 2 * min(L - 1 - i, W) + 1
+            for p in P:
+                assert p & left and p & right
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 7, 10, 11])
+def test_band_partition_is_disjoint(orc, L):
+    """Proof of Theorem 2: L_1..L_V, V_{V+1}..V_{L-V} and R_{L-V+1}..R_L are
+    mutually exclusive, and their union covers every link a path may use in
+    the first V columns, the middle columns and the last V columns."""
+    for W in range(L):
+        for V in range(1, L // 2 + 1):
+            sets = [set(orc.band_cells(L, W, 0, i)) for i in range(V)]
+            sets += [set(orc.band_cells(L, W, 2, i)) for i in range(V, L - V)]
+            sets += [set(orc.band_cells(L, W, 1, i)) for i in range(L - V, L)]
+            for s, t in itertools.combinations(sets, 2):
+                assert not (s & t)
+            for i in range(L):
+                vert = set(orc.band_cells(L, W, 2, i))
+                assert len(vert) == min(L - 1, i + W) - max(0, i - W) + 1
+
+
+def test_band_sums_are_lower_bounds(orc):
+    A, B = _pairs(30, 40, seed=21)
+    for W in (0, 1, 4, 10, 39):
+        d = orc.dtw(A, B, W, zip_=True)
+        for a, b, dd in zip(A, B, d):
+            assert orc.left_bands_sum(a, b, W) <= dd * (1 + 1e-12)       # Theorem 1
+            assert orc.right_bands_sum(a, b, W) <= dd * (1 + 1e-12)      # Equation 6
+
+
+# ---------------------------------------------------------------- LB_Enhanced
+@pytest.mark.parametrize("L", [2, 3, 8, 33, 64])
+def test_lb_enhanced_properties(orc, L):
+    A, B = _pairs(25, L, seed=100 + L)
+    ed = orc.ed2(A, B, zip_=True)
+    for W in sorted({0, 1, 2, 5, L // 2, L - 1}):
+        U, Lo = orc.envelopes(B, W)
+        d = orc.dtw(A, B, W, zip_=True)
+        lbk = orc.lb_keogh(A, U, Lo, zip_=True)
+        for V in sorted({1, 2, 3, 5, L // 2, L // 2 + 3}):
+            eq7 = orc.lb_enhanced(A, B, U, Lo, W, V, zip_=True, variant="eq7")
+            alg = orc.lb_enhanced(A, B, U, Lo, W, V, zip_=True, variant="alg1")
+            bands = orc.lb_enhanced(A, B, U, Lo, W, V, zip_=True, variant="bands")
+            np.testing.assert_allclose(alg, eq7, rtol=1e-12, atol=0)    # Eq 7 = Algorithm 1
+            assert np.all(alg <= d * (1 + 1e-12))                       # Theorem 2
+            assert np.all(bands <= alg)
+            if W == 0:
+                np.testing.assert_allclose(alg, ed, rtol=1e-12)         # W=0: squared ED
+            if V == 1:
+                assert np.all(alg >= lbk * (1 - 1e-12))                 # uniformly tighter than Keogh
+            if V > L // 2:
+                clamp = orc.lb_enhanced(A, B, U, Lo, W, L // 2, zip_=True)
+                assert np.array_equal(alg, clamp)                      # V clamped to floor(L/2)
+
+
+def test_lb_enhanced_cutoff(orc):
+    A, B = _pairs(30, 50, seed=31)
+    W, V = 5, 4
+    U, Lo = orc.envelopes(B, W)
+    full = orc.lb_enhanced(A, B, U, Lo, W, V, zip_=True)
+    bands = orc.lb_enhanced(A, B, U, Lo, W, V, zip_=True, variant="bands")
+    cut = np.median(bands)
+    got = [orc.lb_enhanced(a, b, u, l, W, V, cutoff=cut)[0, 0] for a, b, u, l in zip(A, B, U, Lo)]
+    for g, f, bd in zip(got, full, bands):
+        assert (math.isinf(g) and bd > cut) or (g == f and bd <= cut)
+
+
+def test_lb_enhanced_asymmetric(orc):
+    A, B = _pairs(20, 32, seed=41)
+    W, V = 4, 3
+    Ub, Lb = orc.envelopes(B, W)
+    Ua, La = orc.envelopes(A, W)
+    ab = orc.lb_enhanced(A, B, Ub, Lb, W, V, zip_=True)
+    ba = orc.lb_enhanced(B, A, Ua, La, W, V, zip_=True)
+    assert np.any(ab != ba)
+
+
+def test_lb_le_dtw_on_generated_workload_pairs(orc):
+    """LB <= DTW_W on every pair of a generated workload (truncated sizes)."""
+    wl = synth.workload("nndtw-small")
+    W = wl.windows[0]
+    U, Lo = orc.envelopes(wl.refs, W)
+    d = orc.dtw(wl.queries, wl.refs, W)
+    lbk = orc.lb_keogh(wl.queries, U, Lo)
+    assert np.all(lbk <= d)
+    for V in (1, 2, 5, 32):
+        lbe = orc.lb_enhanced(wl.queries, wl.refs, U, Lo, W, V)
+        assert np.all(lbe <= d * (1 + 1e-12))
+
+
+# ---------------------------------------------------------------- search
+def _closed_form_counts(orc, refs, queries, W, V, cascade, R, init_ub):
+    """Stage counts from full matrices: the best-so-far after each round is the
+    lexicographic min of (DTW, index) over the candidates visited so far."""
+    L = refs.shape[1]
+    eps = orc.slack(L)
+    U, Lo = orc.envelopes(refs, W)
+    ed = orc.ed2(queries, refs)
+    d = orc.dtw(queries, refs, W)
+    lbk = orc.lb_keogh(queries, U, Lo)
+    lbb = orc.lb_enhanced(queries, refs, U, Lo, W, V, variant="bands")
+    lbe = orc.lb_enhanced(queries, refs, U, Lo, W, V)
+    out = []
+    for q in range(queries.shape[0]):
+        order = sorted(range(refs.shape[0]), key=lambda k: (ed[q, k], k))
+        ub = ed[q, order[0]] if init_ub else math.inf
+        best = (math.inf, -1)
+        c = [refs.shape[0], 0, 0, 0, 0]
+        for r0 in range(0, len(order), R):
+            thr = min(best[0], ub) * (1.0 + eps)
+            rnd = order[r0:r0 + R]
+            for k in rnd:
+                if cascade in ("keogh", "keogh_enh") and lbk[q, k] > thr:
+                    c[1] += 1
+                elif cascade in ("keogh_enh", "enh") and lbb[q, k] > thr:
+                    c[2] += 1
+                elif cascade in ("keogh_enh", "enh") and lbe[q, k] > thr:
+                    c[3] += 1
+                else:
+                    c[4] += 1
+            for k in rnd:
+                if d[q, k] <= thr and (best[1] < 0 or (d[q, k], k) < best):
+                    best = (d[q, k], k)
+        out.append((best, c))
+    return out
+
+
+@pytest.mark.parametrize("cascade", ["none", "keogh", "keogh_enh", "enh"])
+@pytest.mark.parametrize("R", [1, 3, 16])
+def test_search_equals_brute_force(orc, cascade, R):
+    refs = synth.random_series(60, 32, seed=7, kind="sin5")
+    queries = synth.random_series(8, 32, seed=8, kind="sin5")
+    for W in (0, 3, 31):
+        bi, bd = orc.brute_nn(refs, queries, W)
+        for V in (1, 3):
+            for init_ub in (False, True):
+                si, sd, cnt = orc.search(refs, queries, W, V, cascade, R, init_ub)
+                assert np.array_equal(si, bi) and np.array_equal(sd, bd)
+                assert np.all(cnt[:, 1:5].sum(1) == cnt[:, 0])              # stages sum to N
+                cf = _closed_form_counts(orc, refs, queries, W, V, cascade, R, init_ub)
+                for q, (best, c) in enumerate(cf):
+                    assert best == (bd[q], bi[q])
+                    assert cnt[q, :5].tolist() == c, (q, cnt[q], c)
+
+
+def test_search_r1_independent_of_initial_bound(orc):
+    refs = synth.random_series(80, 48, seed=9)
+    queries = synth.random_series(10, 48, seed=10)
+    a = orc.search(refs, queries, 5, 2, "keogh_enh", 1, False)
+    b = orc.search(refs, queries, 5, 2, "keogh_enh", 1, True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x[..., :5] if x.ndim == 2 else x, y[..., :5] if y.ndim == 2 else y)
+
+
+def test_search_dominance_enh1_over_keogh(orc):
+    wl = synth.workload("nndtw-small")
+    W = wl.windows[0]
+    for R in (1, 8):
+        _, _, ck = orc.search(wl.refs, wl.queries, W, 1, "keogh", R)
+        _, _, ce = orc.search(wl.refs, wl.queries, W, 1, "enh", R)
+        assert np.all(ce[:, 4] <= ck[:, 4])
+
+
+def test_search_ties_go_to_lowest_index(orc):
+    base = synth.random_series(30, 24, seed=12)
+    refs = np.concatenate([base, base[[3, 7, 3]]], 0)       # duplicates at 30, 31, 32
+    refs = np.ascontiguousarray(refs[::-1])                 # now duplicates at low indices too
+    queries = np.ascontiguousarray(base[[3, 7, 11]])        # exact copies: distance 0
+    for R in (1, 4, 33):
+        idx, dist, _ = orc.search(refs, queries, 4, 2, "keogh_enh", R)
+        bi, bd = orc.brute_nn(refs, queries, 4)
+        assert np.array_equal(idx, bi) and np.all(dist == 0.0)
+        for q, i in zip(queries, idx):
+            same = [k for k in range(refs.shape[0]) if np.array_equal(refs[k], q)]
+            assert i == min(same)
+    # all candidates identical
+    refs = np.repeat(base[:1], 9, 0)
+    idx, dist, cnt = orc.search(refs, base[1:3], 3, 1, "keogh_enh", 2)
+    assert np.all(idx == 0)
+
+
+def test_search_equal_ed_visited_by_index(orc):
+    """Two references at the same squared ED (exact small integers) but with
+    different DTW: the lower index is visited first (ascending (ED^2, index)),
+    which decides whether the other one is pruned."""
+    A = np.arange(8, dtype=np.float32)
+    B1 = A.copy(); B1[0] = 3.0                  # ED^2 = 9; the forced (1,1) link costs 9
+    B2 = A.copy(); B2[3] = 6.0                  # ED^2 = 9; warping absorbs most of it
+    d1, d2 = orc.dtw(A, B1, 1)[0, 0], orc.dtw(A, B2, 1)[0, 0]
+    assert d1 == 9.0 and d2 < d1
+    assert orc.ed2(A, B1)[0, 0] == orc.ed2(A, B2)[0, 0] == 9.0
+    U, Lo = orc.envelopes(B1, 1)
+    assert orc.lb_enhanced(A, B1, U, Lo, 1, 1, variant="bands")[0, 0] > d2 * (1 + orc.slack(8))
+    refs = np.stack([B2, B1])                   # B2 at index 0: visited first, B1 then pruned
+    idx, dist, cnt = orc.search(refs, A, 1, 1, "enh", 1)
+    assert idx[0] == 0 and dist[0] == d2
+    assert cnt[0, 2] == 1 and cnt[0, 4] == 1
+    refs = np.stack([B1, B2])                   # B1 first: both need DTW
+    idx, dist, cnt = orc.search(refs, A, 1, 1, "enh", 1)
+    assert idx[0] == 1 and cnt[0, 4] == 2
