@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark of the NN-DTW hot path on one MI355X.
+
+A step is one pass of the whole path over one batch: build the reference set
+(copy, envelopes, point-major copies), then the search (fused bound pass,
+visiting order, round-based pruned search with DTW_W).  The workload is the
+1000 x 1000, L=256, W=26 (0.1 L) class-sinusoid configuration with the
+paper's recommended V=5 and the LB_Keogh -> LB_Enhanced cascade.  Inputs are
+resident in HBM before timing starts.
+
+Prints ONE JSON line (see the design doc for every field).
+"""
+import argparse
+import ctypes
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+VALU_PEAK_OPS = 256 * 64 * 2.4e9      # non-packed VALU lane operations per second (fp32 or fp64)
+HBM_PEAK = 8.0e12
+METRIC = "NN-DTW queries/sec and DTW cells/sec (% VALU peak); pruning rate; p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Hip:
+    """Minimal HIP event API through ctypes (events on torch's current stream)."""
+
+    def __init__(self):
+        self.h = ctypes.CDLL("libamdhip64.so")
+        self.h.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.h.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self.h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.h.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def events(self, n):
+        arr = (ctypes.c_void_p * n)()
+        for i in range(n):
+            assert self.h.hipEventCreate(ctypes.byref(arr, i * ctypes.sizeof(ctypes.c_void_p))) == 0
+        return arr
+
+    def record(self, ev, stream):
+        assert self.h.hipEventRecord(ev, stream) == 0
+
+    def ms(self, a, b):
+        f = ctypes.c_float(0)
+        assert self.h.hipEventElapsedTime(ctypes.byref(f), a, b) == 0
+        return float(f.value)
+
+
+def cpu_baseline(wl, W, V, target_s):
+    import numpy as np
+    import oracle
+    threads = oracle.max_threads()
+    n = 8
+    t = time.perf_counter()
+    oracle.search(wl.refs, wl.queries[:n], W, V, "keogh_enh", 1, True)
+    dt = time.perf_counter() - t
+    want = int(min(wl.queries.shape[0], max(n, n * target_s / max(dt, 1e-3))))
+    t = time.perf_counter()
+    oracle.search(wl.refs, wl.queries[:want], W, V, "keogh_enh", 1, True)
+    dt = time.perf_counter() - t
+    return {"value": want / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {want} of {wl.queries.shape[0]} queries, full reference set, paper-mode "
+                      f"sequential search (R=1), LB_Keogh->LB_Enhanced^{V}, FP64, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--V", type=int, default=5)
+    ap.add_argument("--R", type=int, default=0)
+    ap.add_argument("--cpl", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the per-query arm and tightness")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py measures one GPU only (the search shards with no exchange; see DESIGN.md); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1808_09617_amd as nd
+    import synth
+
+    wl = synth.workload("nndtw-sin256")
+    W, V = wl.windows[0], args.V
+    N, Q, L = wl.refs.shape[0], wl.queries.shape[0], wl.L
+    dev = torch.device("cuda:0")
+    refs = torch.from_numpy(wl.refs).to(dev)
+    qs = torch.from_numpy(wl.queries).to(dev)
+    hip = Hip()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    rs = nd.RefSet(refs, W)
+    srch = nd.Searcher(rs, Q, V=V, cascade="keogh_enh", R=args.R, init_ub=True, cpl=args.cpl)
+    log(f"workload nndtw-sin256 N={N} Q={Q} L={L} W={W} V={V}")
+
+    def step(ev=None, stage_ev=None):
+        if ev is not None:
+            hip.record(ev[0], stream)
+        rs.rebuild(refs)
+        srch.set_events(stage_ev)
+        out = srch(qs)
+        if ev is not None:
+            hip.record(ev[1], stream)
+        return out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    K = args.steps
+    step_ev = [hip.events(2) for _ in range(K)]
+    stage_ev = [hip.events(5) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        idx, dist, counts = step(step_ev[k], stage_ev[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"timed {K} steps")
+    ms_step = (t1 - t0) * 1e3 / K
+    lat = sorted(hip.ms(e[0], e[1]) for e in step_ev)
+    st = {name: [hip.ms(e[i], e[i + 1]) for e in stage_ev] for i, name in
+          enumerate(["bounds", "cells_prefix", "order", "search"])}
+    st_avg = {k: sum(v) / len(v) for k, v in st.items()}
+
+    c = counts.cpu().numpy()
+    cells = int(c[:, 6].sum())
+    started = int(c[:, 4].sum())
+    pairs = N * Q
+    # roofline of the dominant kernel
+    cells_ops = 3.0 * cells                              # sub, min3, fma per cell
+    bounds_ops = 9.0 * Q * N * L                         # FP64 per (query, reference, point)
+    if st_avg["search"] >= st_avg["bounds"]:
+        t = st_avg["search"] / 1e3
+        ach = cells_ops / t
+        roof = {"kernel": "search_kernel", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                "unit": "Tops/s", "frac": ach / VALU_PEAK_OPS, "traffic": None}
+    else:
+        t = st_avg["bounds"] / 1e3
+        ach = bounds_ops / t
+        roof = {"kernel": "cascade_bounds_kernel", "bound": "alu", "achieved": ach / 1e12,
+                "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s", "frac": ach / VALU_PEAK_OPS, "traffic": None}
+    bytes_bounds = 12.0 * N * L * math.ceil(Q / 8) + 32.0 * Q * N
+    res = {
+        "metric": METRIC, "value": Q / (ms_step / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "nndtw-sin256", "N": N, "Q": Q, "L": L, "W": W, "V": V, "cascade": "keogh_enh",
+                   "R": srch.R, "cpl": srch.cpl, "init_ub": True},
+        "roofline": roof,
+        "dtw_cells_per_s": cells / (ms_step / 1e3),
+        "search_kernel_cells_per_s": cells / (st_avg["search"] / 1e3),
+        "valu_frac_dtw": cells_ops / (st_avg["search"] / 1e3) / VALU_PEAK_OPS,
+        "pruning_rate": 1.0 - started / pairs,
+        "pruned": {"keogh": int(c[:, 1].sum()) / pairs, "enh_bands": int(c[:, 2].sum()) / pairs,
+                   "enh": int(c[:, 3].sum()) / pairs},
+        "dtw_started": started, "dtw_abandoned": int(c[:, 5].sum()), "fp64_rechecks": int(c[:, 7].sum()),
+        "latency_ms": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
+                       "max": lat[-1]},
+        "stage_ms": st_avg,
+        "bounds_kernel_gbps_algorithmic": bytes_bounds / (st_avg["bounds"] / 1e3) / 1e9,
+    }
+
+    if not args.no_extras:
+        # arm B: plain per-query LB_Keogh -> DTW, one query per launch sequence
+        nq = 100
+        one = [nd.Searcher(rs, 1, V=V, cascade="keogh", R=0, init_ub=False)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(nq):
+            one[0](qs[i:i + 1])
+        torch.cuda.synchronize()
+        per_q = nq / (time.perf_counter() - t)
+        res["per_query_keogh_qps"] = per_q
+        res["speedup_vs_per_query_keogh"] = res["value"] / per_q
+        # LB tightness on independent class-sinusoid pairs (LB / DTW, un-rooted)
+        a, b = synth.tightness_pairs(250_000)
+        A, B = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+        U, Lo = nd.envelopes(B, W)
+        d = nd.dtw_w(A, B, W, zip_=True).double()
+        keep = d > 0
+        tight = {"pairs": int(keep.sum()), "keogh": float((nd.lb_keogh(A, U, Lo, zip_=True)[keep] / d[keep]).mean())}
+        for v in (1, 2, 5):
+            tight[f"enhanced{v}"] = float((nd.lb_enhanced(A, B, U, Lo, W, v, zip_=True)[keep] / d[keep]).mean())
+        res["tightness"] = tight
+        log("extras done")
+
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(wl, W, V, args.cpu_seconds)
+        log("cpu baseline done")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

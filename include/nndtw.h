@@ -1,0 +1,239 @@
+/*
+ * nndtw.h -- C ABI of the MI355X (gfx950) library for nearest-neighbour search
+ * under window-constrained dynamic time warping with the LB_Keogh /
+ * LB_Enhanced lower-bound cascade of Tan, Petitjean & Webb, "Elastic bands
+ * across the path: A new framework and method to lower bound DTW" (SDM 2019).
+ *
+ * Conventions for every entry point
+ *  - Returns an int status: NNDTW_OK (0) or a negative NNDTW_E* code; the
+ *    text of the last error of the calling thread is nndtw_last_error().
+ *    Nothing throws, nothing aborts.
+ *  - All arguments are validated on the host before anything is enqueued;
+ *    an invalid call enqueues nothing.
+ *  - Work is enqueued asynchronously on the caller's HIP stream (a
+ *    hipStream_t passed as void*; NULL is the default stream).  Results are
+ *    valid after the caller synchronises that stream.  The library never
+ *    synchronises, never allocates device memory and never normalises data.
+ *  - Array arguments are caller-owned DEVICE pointers unless stated
+ *    otherwise, row-major and contiguous: a set of n series of length L is
+ *    float[n][L].  Pointers must be 4-byte aligned (8 for doubles).
+ *  - Series values must be finite with magnitude below 1e15.  Lengths must
+ *    satisfy 2 <= L <= NNDTW_MAX_L.
+ *  - W is the integer half-width of the Sakoe-Chiba window (Section 2.1):
+ *    A_i may be aligned with B_j only if |i - j| <= W.  W >= 0; any
+ *    W >= L-1 means unconstrained (W = L is accepted).
+ *  - Distances and lower bounds are un-rooted sums of point costs
+ *    delta(x, y) = (x - y)^2 (Section 2.1, Equation 2 without the root, as in
+ *    the proofs of Theorems 1 and 2).
+ *  - V (Section 3.1) is the number of left and right bands; V >= 1, and it is
+ *    clamped to floor(L/2) as in Algorithm 1.
+ *  - pairing: NNDTW_CROSS computes out[a][b] for every a < nA, b < nB;
+ *    NNDTW_ZIP requires nA == nB and computes out[p] for the pair (A_p, B_p).
+ */
+#ifndef NNDTW_H
+#define NNDTW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NNDTW_VERSION_MAJOR 0
+#define NNDTW_VERSION_MINOR 1
+
+#define NNDTW_OK      0
+#define NNDTW_EINVAL (-1)   /* invalid argument                        */
+#define NNDTW_EHIP   (-2)   /* a HIP runtime call failed               */
+#define NNDTW_EUNSUP (-3)   /* valid but unsupported size or option    */
+
+#define NNDTW_CROSS 0
+#define NNDTW_ZIP   1
+
+#define NNDTW_MAX_L 2048
+/* Largest reference-set size nndtw_search accepts (its visiting order is
+ * sorted in on-chip memory). */
+#define NNDTW_SEARCH_MAX_N 8192
+
+/* Lower-bound cascades for nndtw_search. */
+#define NNDTW_CASCADE_NONE      0  /* DTW_W of every candidate (with abandon)        */
+#define NNDTW_CASCADE_KEOGH     1  /* LB_Keogh                                        */
+#define NNDTW_CASCADE_KEOGH_ENH 2  /* LB_Keogh, then LB_Enhanced^V bands, then full   */
+#define NNDTW_CASCADE_ENH       3  /* LB_Enhanced^V bands, then full                  */
+
+/* Layout of the per-query counts written by nndtw_search (int64 each). */
+#define NNDTW_COUNT_N              0  /* references visited (= n)                        */
+#define NNDTW_COUNT_PRUNED_KEOGH   1  /* pruned by LB_Keogh                              */
+#define NNDTW_COUNT_PRUNED_BANDS   2  /* pruned by the band part of LB_Enhanced          */
+#define NNDTW_COUNT_PRUNED_ENH     3  /* pruned by full LB_Enhanced                      */
+#define NNDTW_COUNT_DTW_STARTED    4  /* DTW_W started (not pruned)                      */
+#define NNDTW_COUNT_DTW_ABANDONED  5  /* implementation-defined: DTWs stopped early      */
+#define NNDTW_COUNT_CELLS          6  /* implementation-defined: band cells evaluated    */
+#define NNDTW_COUNT_RECHECKS       7  /* implementation-defined: FP64 recomputations     */
+#define NNDTW_NCOUNTS              8
+
+/* ---------------------------------------------------------------------------
+ * Library information.
+ */
+/* Returns NNDTW_VERSION_MAJOR * 100 + NNDTW_VERSION_MINOR. */
+int nndtw_version(void);
+/* Static text for a status code (never NULL). */
+const char *nndtw_status_string(int status);
+/* Text of the last error raised by the calling thread ("" if none); the
+ * pointer stays valid until the thread's next call into the library. */
+const char *nndtw_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Envelopes, Equations (3) and (4):
+ *   U[s][i]  = max B[s][j],  Lo[s][i] = min B[s][j]
+ *   over max(0, i-W) <= j <= min(L-1, i+W)   (0-based).
+ * B: float[n][L]; U, Lo: float[n][L] outputs (exact: comparisons only).
+ * n >= 0 (n = 0 enqueues nothing).  EINVAL for L, W or null pointers out of
+ * range.
+ */
+int nndtw_envelopes(const float *B, int64_t n, int32_t L, int32_t W,
+                    float *U, float *Lo, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Squared Euclidean distance sum_i (A_i - B_i)^2, accumulated in FP64 with i
+ * ascending.  It equals DTW_0 (Section 2.1) and is the key of the visiting
+ * order of the search (Section 4: candidates sorted by Euclidean distance).
+ * A: float[nA][L], B: float[nB][L]; out: double[nA][nB] (CROSS) or [nA] (ZIP).
+ */
+int nndtw_ed2(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L,
+              int32_t pairing, double *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * LB_Keogh (Section 2.2): sum over i of (A_i - U_i)^2 if A_i > U_i,
+ * (A_i - Lo_i)^2 if A_i < Lo_i, else 0, with U/Lo the envelopes of B
+ * (from nndtw_envelopes with the intended W).  FP64, i ascending.
+ * A: float[nA][L]; U, Lo: float[nB][L]; out: double (CROSS [nA][nB] / ZIP [nA]).
+ */
+int nndtw_lb_keogh(const float *A, int64_t nA, const float *U, const float *Lo,
+                   int64_t nB, int32_t L, int32_t pairing, double *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * LB_Enhanced^V_W (Equation 7), evaluated as Algorithm 1: the point costs of
+ * the two corners, then for band index i = 2..n_bands (n_bands =
+ * min(floor(L/2), V)) the minimum over the left band L^W_i and over its
+ * mirror image at (L, L), accumulated res <- (res + min_left) + min_right;
+ * then the LB_Keogh terms of the points n_bands+1 .. L-n_bands added in
+ * ascending order.  FP64 throughout.
+ * cutoff: NULL, or a device double[nA]; when given, the result for a pair
+ * whose band part already exceeds cutoff[a] (strictly) is +inf, the early
+ * exit of Algorithm 1.
+ * A: float[nA][L]; B, U, Lo: float[nB][L]; out: double (CROSS/ZIP).
+ */
+int nndtw_lb_enhanced(const float *A, int64_t nA, const float *B, const float *U,
+                      const float *Lo, int64_t nB, int32_t L, int32_t W, int32_t V,
+                      const double *cutoff, int32_t pairing, double *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * DTW_W (Equation 1 over the window of Section 2.1), FP32 cost matrix:
+ *   D(i,j) = (A_i - B_j)^2 + min(D(i-1,j-1), D(i,j-1), D(i-1,j)),
+ * result D(L,L) (un-rooted).  FP32 error is at most gamma_{2L+1} of float32
+ * relative to the exact value.
+ * cutoff: NULL, or device double[nA]: the computation of a pair may stop
+ * with +inf once every cell of two consecutive anti-diagonals exceeds
+ * cutoff[a] (every warping path crosses them and costs only grow); a
+ * finite result is always the full DTW_W (possibly above the cutoff).
+ * out: float (CROSS [nA][nB] / ZIP [nA]).
+ */
+int nndtw_dtw_w(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L,
+                int32_t W, const double *cutoff, int32_t pairing, float *out, void *stream);
+
+/* As nndtw_dtw_w in FP64 with each cell computed as a product then a sum
+ * (no fused multiply-add): bit-identical to a sequential FP64 evaluation of
+ * the recurrence.  out: double. */
+int nndtw_dtw_w_f64(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L,
+                    int32_t W, const double *cutoff, int32_t pairing, double *out,
+                    void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Reference sets.  A reference set is the training set of the search with
+ * its envelopes for one window W, precomputed once ("at training time",
+ * Section 4.1) in caller-provided device memory.  The descriptor below is a
+ * plain host struct filled by nndtw_refset_build; it refers into `mem`,
+ * which the caller keeps alive and unmodified while the set is used.
+ */
+#define NNDTW_REFSET_MAGIC 0x4E444157u
+typedef struct nndtw_refset {
+    uint32_t magic;      /* NNDTW_REFSET_MAGIC once built                  */
+    int32_t  L;
+    int64_t  n;
+    int32_t  W;          /* window the envelopes were built for             */
+    int32_t  reserved0;
+    int64_t  pitch;      /* row pitch (elements) of the point-major arrays  */
+    float   *B;          /* float[n][L]      the series                      */
+    float   *U;          /* float[n][L]      upper envelopes                 */
+    float   *Lo;         /* float[n][L]      lower envelopes                 */
+    float   *Bt;         /* float[L][pitch]  point-major copies              */
+    float   *Ut;
+    float   *Lt;
+} nndtw_refset;
+
+/* Device bytes needed for a reference set of n series of length L. */
+int nndtw_refset_bytes(int64_t n, int32_t L, size_t *bytes);
+/* Copy B (device float[n][L]) into mem and build its envelopes and
+ * point-major copies for window W.  n >= 1.  EINVAL if bytes is too small. */
+int nndtw_refset_build(const float *B, int64_t n, int32_t L, int32_t W, void *mem,
+                       size_t bytes, nndtw_refset *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Nearest-neighbour search (Sections 1 and 4): for each query, the
+ * references are visited in ascending (squared Euclidean distance, index)
+ * order, cut into rounds of R consecutive candidates.  Every candidate of a
+ * round is tested against
+ *     thr = min(bsf, ub) * (1 + eps)
+ * where bsf is the current nearest-neighbour distance (+inf at first) and ub
+ * is +inf, or with init_ub the squared Euclidean distance of the first
+ * visited candidate (an upper bound on its DTW_W).  A bound prunes iff it is
+ * > thr; the cascade's bounds are tested in order and the first one that
+ * prunes is counted.  Survivors get DTW_W (FP32, abandoned above thr); after
+ * the round the record becomes the lexicographic minimum of (DTW_W, index)
+ * over the round's DTWs that end <= thr (values decided in FP64).  R = 1 is
+ * the paper's sequential search; with init_ub the results at R = 1 equal
+ * those without it.  The nearest neighbour returned is always the
+ * lexicographic argmin over all references of (DTW_W, index), i.e. ties go
+ * to the lowest index, and its distance is the FP64 DTW_W.
+ */
+typedef struct nndtw_search_opts {
+    int32_t V;        /* LB_Enhanced tightness parameter (>= 1)                      */
+    int32_t cascade;  /* NNDTW_CASCADE_*                                              */
+    int64_t R;        /* round size; 0 = library default; on return: the value used  */
+    double  eps;      /* relative slack; <= 0 selects 2 * (2L + 2) * 2^-24           */
+    int32_t init_ub;  /* 1: bound the first round by the first candidate's ED^2      */
+    int32_t cpl;      /* engine shape (diagonal pairs per lane); 0 = default; out    */
+    void *const *events; /* optional hipEvent_t[5] (caller-created), recorded on the
+                          * stream before the bound pass, after it, after the
+                          * cells table, after the ordering and after the search
+                          * kernel; NULL records nothing                              */
+    int64_t reserved[3];
+} nndtw_search_opts;
+
+/* Workspace bytes nndtw_search needs for nQ queries against refset. */
+int nndtw_search_workspace_bytes(const nndtw_refset *refset, int64_t nQ,
+                                 const nndtw_search_opts *opts, size_t *bytes);
+
+/* Q: device float[nQ][L] (L of the reference set); outputs: nn_idx int64[nQ],
+ * nn_dist double[nQ], counts int64[nQ][NNDTW_NCOUNTS] (NULL allowed).
+ * ws: device workspace of at least nndtw_search_workspace_bytes() bytes.
+ * EUNSUP if refset->n > NNDTW_SEARCH_MAX_N. */
+int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ,
+                 nndtw_search_opts *opts, int64_t *nn_idx, double *nn_dist,
+                 int64_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/* The fused bound pass the search runs first, exposed on its own: for every
+ * query q and reference k of the set, ed2 = squared Euclidean distance,
+ * lbk = LB_Keogh, lbe_bands = Algorithm 1 bands part, lbe = LB_Enhanced^V
+ * (values identical to nndtw_ed2 / nndtw_lb_keogh / nndtw_lb_enhanced).
+ * Each output is a device double[nQ][n]; any of them may be NULL. */
+int nndtw_cascade_bounds(const nndtw_refset *refset, const float *Q, int64_t nQ,
+                         int32_t V, double *ed2, double *lbk, double *lbe_bands,
+                         double *lbe, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNDTW_H */

@@ -1,0 +1,308 @@
+// extern "C" entry points of libnndtw: argument validation on the host, then
+// asynchronous launches on the caller's stream.  Nothing here allocates
+// device memory or synchronises.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "common.hpp"
+
+namespace nndtw {
+
+static thread_local char g_err[512];
+
+int fail(int status, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(NNDTW_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool bad_len(int L) { return L < 2 || L > NNDTW_MAX_L; }
+static bool misaligned(const void *p, size_t a) { return ((uintptr_t)p % a) != 0; }
+
+#define REQUIRE(cond, ...)                                       \
+    do {                                                         \
+        if (!(cond)) return ::nndtw::fail(NNDTW_EINVAL, __VA_ARGS__); \
+    } while (0)
+
+static int check_len_w(int L, int W)
+{
+    if (bad_len(L)) {
+        if (L > NNDTW_MAX_L) return fail(NNDTW_EUNSUP, "L=%d exceeds NNDTW_MAX_L=%d", L, NNDTW_MAX_L);
+        return fail(NNDTW_EINVAL, "L=%d: series length must be >= 2", L);
+    }
+    REQUIRE(W >= 0, "W=%d: window must be >= 0", W);
+    return NNDTW_OK;
+}
+
+static int check_pairing(int pairing, int64_t nA, int64_t nB)
+{
+    REQUIRE(pairing == NNDTW_CROSS || pairing == NNDTW_ZIP, "pairing=%d: expected NNDTW_CROSS or NNDTW_ZIP", pairing);
+    REQUIRE(nA >= 0 && nB >= 0, "negative series count (nA=%lld, nB=%lld)", (long long)nA, (long long)nB);
+    REQUIRE(pairing != NNDTW_ZIP || nA == nB, "zip pairing needs nA == nB (nA=%lld, nB=%lld)", (long long)nA,
+            (long long)nB);
+    return NNDTW_OK;
+}
+
+static int check_ptr(const void *p, size_t align, const char *name, bool needed)
+{
+    if (!needed) return NNDTW_OK;
+    REQUIRE(p != nullptr, "%s is NULL", name);
+    REQUIRE(!misaligned(p, align), "%s is not %zu-byte aligned", name, align);
+    return NNDTW_OK;
+}
+
+#define TRY(x)                    \
+    do {                          \
+        int r_ = (x);             \
+        if (r_ != NNDTW_OK) return r_; \
+    } while (0)
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace nndtw
+
+using namespace nndtw;
+
+extern "C" {
+
+int nndtw_version(void) { return NNDTW_VERSION_MAJOR * 100 + NNDTW_VERSION_MINOR; }
+
+const char *nndtw_status_string(int status)
+{
+    switch (status) {
+    case NNDTW_OK: return "ok";
+    case NNDTW_EINVAL: return "invalid argument";
+    case NNDTW_EHIP: return "HIP runtime error";
+    case NNDTW_EUNSUP: return "unsupported size or option";
+    default: return "unknown status";
+    }
+}
+
+const char *nndtw_last_error(void) { return g_err; }
+
+int nndtw_envelopes(const float *B, int64_t n, int32_t L, int32_t W, float *U, float *Lo, void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_len_w(L, W));
+    REQUIRE(n >= 0, "n=%lld must be >= 0", (long long)n);
+    TRY(check_ptr(B, 4, "B", n > 0));
+    TRY(check_ptr(U, 4, "U", n > 0));
+    TRY(check_ptr(Lo, 4, "Lo", n > 0));
+    return launch_envelopes(B, n, L, W, U, Lo, (hipStream_t)stream);
+}
+
+int nndtw_ed2(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L, int32_t pairing, double *out,
+              void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_len_w(L, 0));
+    TRY(check_pairing(pairing, nA, nB));
+    const bool any = nA > 0 && nB > 0;
+    TRY(check_ptr(A, 4, "A", any));
+    TRY(check_ptr(B, 4, "B", any));
+    TRY(check_ptr(out, 8, "out", any));
+    return launch_pair_bounds(0, A, nA, B, nullptr, nullptr, nB, L, 0, 1, nullptr, pairing, out,
+                              (hipStream_t)stream);
+}
+
+int nndtw_lb_keogh(const float *A, int64_t nA, const float *U, const float *Lo, int64_t nB, int32_t L,
+                   int32_t pairing, double *out, void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_len_w(L, 0));
+    TRY(check_pairing(pairing, nA, nB));
+    const bool any = nA > 0 && nB > 0;
+    TRY(check_ptr(A, 4, "A", any));
+    TRY(check_ptr(U, 4, "U", any));
+    TRY(check_ptr(Lo, 4, "Lo", any));
+    TRY(check_ptr(out, 8, "out", any));
+    return launch_pair_bounds(1, A, nA, nullptr, U, Lo, nB, L, 0, 1, nullptr, pairing, out, (hipStream_t)stream);
+}
+
+int nndtw_lb_enhanced(const float *A, int64_t nA, const float *B, const float *U, const float *Lo, int64_t nB,
+                      int32_t L, int32_t W, int32_t V, const double *cutoff, int32_t pairing, double *out,
+                      void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_len_w(L, W));
+    REQUIRE(V >= 1, "V=%d: the number of bands must be >= 1", V);
+    TRY(check_pairing(pairing, nA, nB));
+    const bool any = nA > 0 && nB > 0;
+    TRY(check_ptr(A, 4, "A", any));
+    TRY(check_ptr(B, 4, "B", any));
+    TRY(check_ptr(U, 4, "U", any));
+    TRY(check_ptr(Lo, 4, "Lo", any));
+    TRY(check_ptr(out, 8, "out", any));
+    if (cutoff) TRY(check_ptr(cutoff, 8, "cutoff", any));
+    return launch_pair_bounds(2, A, nA, B, U, Lo, nB, L, W, V, cutoff, pairing, out, (hipStream_t)stream);
+}
+
+static int dtw_common(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int32_t L, int32_t W,
+                      const double *cutoff, int32_t pairing, void *out, void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_len_w(L, W));
+    TRY(check_pairing(pairing, nA, nB));
+    const bool any = nA > 0 && nB > 0;
+    TRY(check_ptr(A, 4, "A", any));
+    TRY(check_ptr(B, 4, "B", any));
+    TRY(check_ptr(out, f64 ? 8 : 4, "out", any));
+    if (cutoff) TRY(check_ptr(cutoff, 8, "cutoff", any));
+    return launch_dtw_pairs(f64, A, nA, B, nB, L, W, cutoff, pairing, out, (hipStream_t)stream);
+}
+
+int nndtw_dtw_w(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L, int32_t W,
+                const double *cutoff, int32_t pairing, float *out, void *stream)
+{
+    return dtw_common(false, A, nA, B, nB, L, W, cutoff, pairing, out, stream);
+}
+
+int nndtw_dtw_w_f64(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L, int32_t W,
+                    const double *cutoff, int32_t pairing, double *out, void *stream)
+{
+    return dtw_common(true, A, nA, B, nB, L, W, cutoff, pairing, out, stream);
+}
+
+// ----------------------------------------------------------- reference sets
+static size_t refset_layout(int64_t n, int L, int64_t *pitch, size_t off[6])
+{
+    const int64_t p = (n + 63) / 64 * 64;
+    const size_t rowb = (size_t)n * L * sizeof(float);
+    const size_t colb = (size_t)L * p * sizeof(float);
+    size_t o = 0;
+    for (int i = 0; i < 3; ++i) { off[i] = o; o = al256(o + rowb); }
+    for (int i = 3; i < 6; ++i) { off[i] = o; o = al256(o + colb); }
+    *pitch = p;
+    return o;
+}
+
+int nndtw_refset_bytes(int64_t n, int32_t L, size_t *bytes)
+{
+    g_err[0] = 0;
+    TRY(check_len_w(L, 0));
+    REQUIRE(n >= 1, "n=%lld: a reference set needs at least one series", (long long)n);
+    REQUIRE(bytes != nullptr, "bytes is NULL");
+    int64_t pitch;
+    size_t off[6];
+    *bytes = refset_layout(n, L, &pitch, off);
+    return NNDTW_OK;
+}
+
+int nndtw_refset_build(const float *B, int64_t n, int32_t L, int32_t W, void *mem, size_t bytes,
+                       nndtw_refset *out, void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_len_w(L, W));
+    REQUIRE(n >= 1, "n=%lld: a reference set needs at least one series", (long long)n);
+    TRY(check_ptr(B, 4, "B", true));
+    TRY(check_ptr(mem, 256, "mem", true));
+    REQUIRE(out != nullptr, "out is NULL");
+    int64_t pitch;
+    size_t off[6];
+    const size_t need = refset_layout(n, L, &pitch, off);
+    REQUIRE(bytes >= need, "refset memory too small: %zu bytes given, %zu needed", bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char *m = (unsigned char *)mem;
+    nndtw_refset r;
+    memset(&r, 0, sizeof r);
+    r.L = L;
+    r.n = n;
+    r.W = W;
+    r.pitch = pitch;
+    r.B = (float *)(m + off[0]);
+    r.U = (float *)(m + off[1]);
+    r.Lo = (float *)(m + off[2]);
+    r.Bt = (float *)(m + off[3]);
+    r.Ut = (float *)(m + off[4]);
+    r.Lt = (float *)(m + off[5]);
+    hipError_t e = hipMemcpyAsync(r.B, B, (size_t)n * L * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "refset copy");
+    TRY(launch_envelopes(r.B, n, L, W, r.U, r.Lo, st));
+    TRY(launch_transpose3(r.B, r.U, r.Lo, n, L, pitch, r.Bt, r.Ut, r.Lt, st));
+    r.magic = NNDTW_REFSET_MAGIC;
+    *out = r;
+    return NNDTW_OK;
+}
+
+static int check_refset(const nndtw_refset *rs)
+{
+    REQUIRE(rs != nullptr, "refset is NULL");
+    REQUIRE(rs->magic == NNDTW_REFSET_MAGIC, "refset was not built by nndtw_refset_build");
+    TRY(check_len_w(rs->L, rs->W));
+    REQUIRE(rs->n >= 1, "refset has no series");
+    return NNDTW_OK;
+}
+
+static int check_opts(const nndtw_search_opts *o)
+{
+    REQUIRE(o != nullptr, "opts is NULL");
+    REQUIRE(o->V >= 1, "V=%d: the number of bands must be >= 1", o->V);
+    REQUIRE(o->cascade >= NNDTW_CASCADE_NONE && o->cascade <= NNDTW_CASCADE_ENH, "cascade=%d unknown", o->cascade);
+    REQUIRE(o->R >= 0, "R=%lld must be >= 0", (long long)o->R);
+    REQUIRE(o->cpl >= 0, "cpl=%d must be >= 0", o->cpl);
+    return NNDTW_OK;
+}
+
+int nndtw_search_workspace_bytes(const nndtw_refset *refset, int64_t nQ, const nndtw_search_opts *opts,
+                                 size_t *bytes)
+{
+    g_err[0] = 0;
+    TRY(check_refset(refset));
+    TRY(check_opts(opts));
+    REQUIRE(nQ >= 0, "nQ=%lld must be >= 0", (long long)nQ);
+    REQUIRE(bytes != nullptr, "bytes is NULL");
+    *bytes = search_ws_bytes(nQ, refset->n, refset->L);
+    return NNDTW_OK;
+}
+
+int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ, nndtw_search_opts *opts,
+                 int64_t *nn_idx, double *nn_dist, int64_t *counts, void *ws, size_t ws_bytes, void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_refset(refset));
+    TRY(check_opts(opts));
+    REQUIRE(nQ >= 0, "nQ=%lld must be >= 0", (long long)nQ);
+    if (refset->n > NNDTW_SEARCH_MAX_N)
+        return fail(NNDTW_EUNSUP, "reference set of %lld series exceeds NNDTW_SEARCH_MAX_N=%d",
+                    (long long)refset->n, NNDTW_SEARCH_MAX_N);
+    const bool any = nQ > 0;
+    TRY(check_ptr(Q, 4, "Q", any));
+    TRY(check_ptr(nn_idx, 8, "nn_idx", any));
+    TRY(check_ptr(nn_dist, 8, "nn_dist", any));
+    if (counts) TRY(check_ptr(counts, 8, "counts", any));
+    TRY(check_ptr(ws, 256, "ws", any));
+    const size_t need = search_ws_bytes(nQ, refset->n, refset->L);
+    REQUIRE(!any || ws_bytes >= need, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    SearchPlan plan;
+    TRY(plan_search(refset, opts, &plan));
+    opts->R = plan.R;
+    opts->cpl = plan.C;
+    return launch_search(refset, Q, nQ, opts, plan, nn_idx, nn_dist, counts, ws, (hipStream_t)stream);
+}
+
+int nndtw_cascade_bounds(const nndtw_refset *refset, const float *Q, int64_t nQ, int32_t V, double *ed2,
+                         double *lbk, double *lbe_bands, double *lbe, void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_refset(refset));
+    REQUIRE(V >= 1, "V=%d: the number of bands must be >= 1", V);
+    REQUIRE(nQ >= 0, "nQ=%lld must be >= 0", (long long)nQ);
+    const bool any = nQ > 0;
+    TRY(check_ptr(Q, 4, "Q", any));
+    if (ed2) TRY(check_ptr(ed2, 8, "ed2", any));
+    if (lbk) TRY(check_ptr(lbk, 8, "lbk", any));
+    if (lbe_bands) TRY(check_ptr(lbe_bands, 8, "lbe_bands", any));
+    if (lbe) TRY(check_ptr(lbe, 8, "lbe", any));
+    return launch_cascade_bounds(refset, Q, nQ, V, ed2, lbk, lbe_bands, lbe, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,191 @@
+// Lower bounds of Sections 2.2 and 3 and the visiting-order key of Section 4,
+// all in FP64 from float32 inputs, each sum accumulated in ascending point
+// order so that the values are reproducible bit for bit.
+//
+//  * squared Euclidean distance  sum_i (A_i - B_i)^2
+//  * LB_Keogh                    sum_i dist(A_i, [Lo_i, U_i])^2
+//  * LB_Enhanced^V (Algorithm 1) corner costs, then per band index the left
+//    band minimum and its mirror at (L, L), then the Keogh terms of the
+//    middle points.
+//
+// Two kernels: a generic one over (A, B) pairs in row-major layout (one
+// thread per pair), and the fused pass of the search over a reference set,
+// where lanes index references and read the point-major copies (coalesced),
+// each thread carrying TQ queries so every reference value loaded from memory
+// is reused TQ times.  The query values are staged in LDS as doubles.
+#include "common.hpp"
+
+namespace nndtw {
+
+__device__ __forceinline__ double sqd(float x, float y)
+{
+    double d = (double)x - (double)y;
+    return d * d;
+}
+
+// Distance of a to the interval [lo, u], squared (0 inside).  a - clamp(a)
+// is exactly a - u above, a - lo below and 0 inside.
+__device__ __forceinline__ double keogh_term(double a, double u, double lo)
+{
+    double c = __builtin_fmin(__builtin_fmax(a, lo), u);
+    double t = a - c;
+    return t * t;
+}
+
+// Bands part of Algorithm 1 (corners and band indices 2..nb, 1-based).
+// av(i) / bv(j) fetch A_i and B_j (0-based).
+template <typename FA, typename FB>
+__device__ __forceinline__ double enh_bands(FA av, FB bv, int L, int W, int nb)
+{
+    double res = sqd(av(0), bv(0)) + sqd(av(L - 1), bv(L - 1));
+    for (int i = 1; i < nb; ++i) {
+        const int r = L - 1 - i;
+        const float ai = av(i), bi = bv(i), ar = av(r), br = bv(r);
+        double mL = sqd(ai, bi), mR = sqd(ar, br);
+        for (int j = max(0, i - W); j < i; ++j) {
+            const int rj = L - 1 - j;
+            mL = __builtin_fmin(mL, sqd(ai, bv(j)));
+            mL = __builtin_fmin(mL, sqd(av(j), bi));
+            mR = __builtin_fmin(mR, sqd(ar, bv(rj)));
+            mR = __builtin_fmin(mR, sqd(av(rj), br));
+        }
+        res = res + mL + mR;
+    }
+    return res;
+}
+
+enum { PB_ED2 = 0, PB_KEOGH = 1, PB_ENH = 2 };
+
+__global__ void __launch_bounds__(256)
+pair_bounds_kernel(int what, const float *__restrict__ A, int64_t nA, const float *__restrict__ B,
+                   const float *__restrict__ U, const float *__restrict__ Lo, int64_t nB, int L, int W,
+                   int nb, const double *__restrict__ cutoff, int pairing, double *__restrict__ out)
+{
+    const int64_t np = pairing ? nA : nA * nB;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ia = pairing ? p : p / nB, ib = pairing ? p : p % nB;
+        const float *a = A + ia * L;
+        double s = 0.0;
+        if (what == PB_ED2) {
+            const float *b = B + ib * L;
+            for (int i = 0; i < L; ++i) s += sqd(a[i], b[i]);
+        } else if (what == PB_KEOGH) {
+            const float *u = U + ib * L, *l = Lo + ib * L;
+            for (int i = 0; i < L; ++i) s += keogh_term(a[i], u[i], l[i]);
+        } else {
+            const float *b = B + ib * L, *u = U + ib * L, *l = Lo + ib * L;
+            s = enh_bands([&](int i) { return a[i]; }, [&](int j) { return b[j]; }, L, W, nb);
+            if (cutoff && s > cutoff[ia]) {
+                s = __builtin_inf();
+            } else {
+                for (int i = nb; i < L - nb; ++i) s += keogh_term(a[i], u[i], l[i]);
+            }
+        }
+        out[p] = s;
+    }
+}
+
+int launch_pair_bounds(int what, const float *A, int64_t nA, const float *B, const float *U,
+                       const float *Lo, int64_t nB, int L, int W, int V, const double *cutoff,
+                       int pairing, double *out, hipStream_t st)
+{
+    const int64_t np = pairing ? nA : nA * nB;
+    if (np == 0) return NNDTW_OK;
+    const int nb = V < L / 2 ? V : L / 2;
+    const int64_t blocks = ceil_div(np, 256) < 65536 ? ceil_div(np, 256) : 65536;
+    hipLaunchKernelGGL(pair_bounds_kernel, dim3((unsigned)blocks), dim3(256), 0, st, what, A, nA, B, U,
+                       Lo, nB, L, W, nb, cutoff, pairing, out);
+    NNDTW_LAUNCH_CHECK("bounds kernel launch");
+    return NNDTW_OK;
+}
+
+// ------------------------------------------------------------------ fused
+constexpr int CB_THREADS = 256;
+constexpr int CB_CHUNK = 128;   // points of the query tile staged per pass
+
+template <int TQ>
+__global__ void __launch_bounds__(CB_THREADS)
+cascade_bounds_kernel(const float *__restrict__ Bt, const float *__restrict__ Ut,
+                      const float *__restrict__ Lt, int64_t pitch, int64_t n,
+                      const float *__restrict__ Q, int64_t nQ, int L, int W, int nb,
+                      double *__restrict__ ed2, double *__restrict__ lbk,
+                      double *__restrict__ lbeb, double *__restrict__ lbe)
+{
+    __shared__ double qa[CB_CHUNK][TQ];
+    const int64_t k = (int64_t)blockIdx.x * CB_THREADS + threadIdx.x;
+    const int64_t q0 = (int64_t)blockIdx.y * TQ;
+    const bool live = k < n;
+    const int64_t kk = live ? k : 0;
+    const int nq = (int)((nQ - q0) < TQ ? (nQ - q0) : TQ);
+
+    double e[TQ], kg[TQ], en[TQ];
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) {
+        e[t] = 0.0;
+        kg[t] = 0.0;
+        en[t] = 0.0;
+        if (t < nq) {
+            const float *a = Q + (q0 + t) * L;
+            en[t] = enh_bands([&](int i) { return a[i]; },
+                              [&](int j) { return Bt[(int64_t)j * pitch + kk]; }, L, W, nb);
+        }
+    }
+    const double *lbebv = en;   // bands part, kept before the middle terms are added
+    double band[TQ];
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) band[t] = lbebv[t];
+
+    for (int c0 = 0; c0 < L; c0 += CB_CHUNK) {
+        const int cn = (L - c0) < CB_CHUNK ? (L - c0) : CB_CHUNK;
+        __syncthreads();
+        for (int x = threadIdx.x; x < CB_CHUNK * TQ; x += CB_THREADS) {
+            const int i = x / TQ, t = x % TQ;
+            qa[i][t] = (i < cn && t < nq) ? (double)Q[(q0 + t) * L + c0 + i] : 0.0;
+        }
+        __syncthreads();
+        for (int ii = 0; ii < cn; ++ii) {
+            const int i = c0 + ii;
+            const double b = (double)Bt[(int64_t)i * pitch + kk];
+            const double u = (double)Ut[(int64_t)i * pitch + kk];
+            const double lo = (double)Lt[(int64_t)i * pitch + kk];
+            const bool mid = i >= nb && i < L - nb;
+#pragma unroll
+            for (int t = 0; t < TQ; ++t) {
+                const double a = qa[ii][t];
+                const double d = a - b;
+                e[t] += d * d;
+                const double kt = keogh_term(a, u, lo);
+                kg[t] += kt;
+                if (mid) en[t] += kt;
+            }
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) {
+        if (t < nq) {
+            const int64_t o = (q0 + t) * n + k;
+            if (ed2) ed2[o] = e[t];
+            if (lbk) lbk[o] = kg[t];
+            if (lbeb) lbeb[o] = band[t];
+            if (lbe) lbe[o] = en[t];
+        }
+    }
+}
+
+int launch_cascade_bounds(const nndtw_refset *rs, const float *Q, int64_t nQ, int V, double *ed2,
+                          double *lbk, double *lbeb, double *lbe, hipStream_t st)
+{
+    if (nQ == 0 || rs->n == 0) return NNDTW_OK;
+    constexpr int TQ = 8;
+    const int L = rs->L;
+    const int nb = V < L / 2 ? V : L / 2;
+    dim3 grid((unsigned)ceil_div(rs->n, CB_THREADS), (unsigned)ceil_div(nQ, TQ));
+    hipLaunchKernelGGL(cascade_bounds_kernel<TQ>, grid, dim3(CB_THREADS), 0, st, rs->Bt, rs->Ut, rs->Lt,
+                       rs->pitch, rs->n, Q, nQ, L, rs->W, nb, ed2, lbk, lbeb, lbe);
+    NNDTW_LAUNCH_CHECK("cascade bounds kernel launch");
+    return NNDTW_OK;
+}
+
+}  // namespace nndtw

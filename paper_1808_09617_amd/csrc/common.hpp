@@ -1,0 +1,70 @@
+// Internal definitions shared by the HIP translation units of libnndtw.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nndtw.h"
+
+namespace nndtw {
+
+// Status plumbing (host side, api.hip).
+int fail(int status, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
+#define NNDTW_LAUNCH_CHECK(what)                                  \
+    do {                                                          \
+        hipError_t e_ = hipGetLastError();                        \
+        if (e_ != hipSuccess) return ::nndtw::hip_fail(e_, what); \
+    } while (0)
+
+// Padding value outside a series: its square overflows to +inf, and the
+// difference of two pads is exactly 0 (see the DTW engine).
+template <typename T> struct Pad;
+template <> struct Pad<float> { static __host__ __device__ constexpr float big() { return 1e30f; } };
+template <> struct Pad<double> { static __host__ __device__ constexpr double big() { return 1e200; } };
+
+constexpr int WAVE = 64;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- launchers
+// envelopes.hip
+int launch_envelopes(const float *B, int64_t n, int L, int W, float *U, float *Lo, hipStream_t s);
+int launch_transpose3(const float *B, const float *U, const float *Lo, int64_t n, int L,
+                      int64_t pitch, float *Bt, float *Ut, float *Lt, hipStream_t s);
+// bounds.hip
+int launch_pair_bounds(int what, const float *A, int64_t nA, const float *B, const float *U,
+                       const float *Lo, int64_t nB, int L, int W, int V, const double *cutoff,
+                       int pairing, double *out, hipStream_t s);
+int launch_cascade_bounds(const nndtw_refset *rs, const float *Q, int64_t nQ, int V,
+                          double *ed2, double *lbk, double *lbeb, double *lbe, hipStream_t s);
+// dtw.hip
+int launch_dtw_pairs(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L,
+                     int W, const double *cutoff, int pairing, void *out, hipStream_t s);
+// search.hip
+struct SearchPlan {
+    int Wp, C, G, P, exact, T, LEN;
+    int64_t R;
+    double eps;
+    size_t lds_bytes;
+};
+int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan);
+size_t search_ws_bytes(int64_t nQ, int64_t n, int L);
+int launch_search(const nndtw_refset *rs, const float *Q, int64_t nQ, const nndtw_search_opts *o,
+                  const SearchPlan &plan, int64_t *nn_idx, double *nn_dist, int64_t *counts,
+                  void *ws, hipStream_t s);
+
+// Engine geometry shared by the DTW kernels (see dtw_engine.hpp).
+struct EngineGeom {
+    int L, Wp, C, G, P, exact;
+    int T;      // super-steps (multiple of C + 1)
+    int base0;  // series index of the first super-step's base
+    int LEN;    // elements per staged series in LDS (with padding)
+};
+// Choose the diagonal-pairs-per-lane C for a window (cmax bounds latency).
+int choose_cpl(int Wp, int cmax, int prefer, int chard = 16);
+EngineGeom make_geom(int L, int W, int C);
+bool cpl_supported(int C);
+
+}  // namespace nndtw

@@ -1,0 +1,159 @@
+// DTW_W over (A, B) pairs with the anti-diagonal engine, FP32 or FP64, and
+// the engine geometry helpers shared with the search.
+#include "dtw_engine.hpp"
+
+namespace nndtw {
+
+// Diagonal pairs per lane that the kernels are instantiated for.
+#define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16)
+
+bool cpl_supported(int C)
+{
+    switch (C) {
+#define X(c) case c:
+        NNDTW_FOR_EACH_CPL(X)
+#undef X
+        return true;
+    default:
+        return false;
+    }
+}
+
+// Modelled VALU efficiency of a shape: lanes in use times useful operations
+// per cell (3: sub, min3, fma) over issued ones.
+static double cpl_score(int Wp, int C)
+{
+    const int G = (int)ceil_div(Wp + 1, C);
+    if (G > 63) return -1.0;
+    const bool exact = G * C == Wp + 1;
+    const int P = 63 / G;
+    const double ops = exact ? 3.0 + 1.5 / C : 3.5 + 1.0 / C;
+    return (double)(P * G) / 64.0 * 3.0 / ops;
+}
+
+int choose_cpl(int Wp, int cmax, int prefer, int chard)
+{
+    if (prefer > 0)
+        return (cpl_supported(prefer) && prefer <= chard && cpl_score(Wp, prefer) > 0) ? prefer : -1;
+    int best = -1;
+    double bs = -1.0;
+    const int cands[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    for (int pass = 0; pass < 2 && best < 0; ++pass) {
+        for (int C : cands) {
+            if (C > chard || (pass == 0 && C > cmax)) continue;
+            double s = cpl_score(Wp, C);
+            if (s > bs * 1.02) {   // a larger C must pay for its latency
+                bs = s;
+                best = C;
+            }
+        }
+    }
+    return best;
+}
+
+EngineGeom make_geom(int L, int W, int C)
+{
+    EngineGeom g;
+    g.L = L;
+    g.Wp = W < L - 1 ? W : L - 1;
+    g.C = C;
+    g.G = (int)ceil_div(g.Wp + 1, C);
+    g.exact = g.G * C == g.Wp + 1;
+    g.P = 63 / g.G;
+    const int T0 = L + (g.Wp + 2) / 2;
+    const int epad = (C + 1 - T0 % (C + 1)) % (C + 1);
+    g.T = T0 + epad;
+    g.base0 = -g.Wp - 1 - epad;
+    g.LEN = g.T + g.Wp + 2 * C + 2;
+    return g;
+}
+
+template <typename T, int C, bool EXACT>
+__global__ void __launch_bounds__(WAVE)
+dtw_pairs_kernel(EngineGeom geo, int Pw, const float *__restrict__ A, int64_t nA,
+                 const float *__restrict__ B, int64_t nB, const double *__restrict__ cutoff,
+                 int pairing, T *__restrict__ out)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *aR = reinterpret_cast<T *>(smem);
+    T *bR = aR + (size_t)Pw * geo.LEN;
+    T *res = bR + (size_t)Pw * geo.LEN;
+    int *trun = reinterpret_cast<int *>(res + Pw);
+    const int lane = threadIdx.x;
+    const int L = geo.L;
+    const int64_t np = pairing ? nA : nA * nB;
+    EngineGeom gw = geo;
+    gw.P = Pw;
+    for (int64_t base = (int64_t)blockIdx.x * Pw; base < np; base += (int64_t)gridDim.x * Pw) {
+        const int nact = (int)((np - base) < Pw ? (np - base) : Pw);
+        for (int g = 0; g < nact; ++g) {
+            const int64_t p = base + g;
+            const int64_t ia = pairing ? p : p / nB, ib = pairing ? p : p % nB;
+            stage_row<T, C>(aR + (size_t)g * geo.LEN, A + ia * L, geo, lane);
+            stage_row<T, C>(bR + (size_t)g * geo.LEN, B + ib * L, geo, lane);
+        }
+        __syncthreads();
+        // per-lane threshold of the lane's group
+        const int gi = lane >= 1 ? (lane - 1) / geo.G : 0;
+        T thr = inf_of<T>();
+        if (cutoff && lane >= 1 && gi < nact) {
+            const int64_t p = base + gi;
+            const double c = cutoff[pairing ? p : p / nB];
+            thr = sizeof(T) == 4 ? (T)round_up_f32(c) : (T)c;
+        }
+        engine_pass<T, C, EXACT>(gw, aR, geo.LEN, bR, geo.LEN, nact, thr, PassOut<T>{res, trun});
+        __syncthreads();
+        if (lane < nact) out[base + lane] = res[lane];
+        __syncthreads();
+    }
+}
+
+static size_t pairs_lds(const EngineGeom &g, int Pw, size_t esz)
+{
+    return (size_t)2 * Pw * g.LEN * esz + (size_t)Pw * (esz + sizeof(int)) + 16;
+}
+
+template <typename T>
+static int launch_pairs_t(const float *A, int64_t nA, const float *B, int64_t nB, int L, int W,
+                          const double *cutoff, int pairing, T *out, hipStream_t st)
+{
+    const int64_t np = pairing ? nA : nA * nB;
+    if (np == 0) return NNDTW_OK;
+    const int Wp = W < L - 1 ? W : L - 1;
+    const int C = choose_cpl(Wp, 16, 0);
+    if (C < 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
+    EngineGeom g = make_geom(L, W, C);
+    int Pw = g.P;
+    const size_t budget = 64 * 1024;
+    while (Pw > 1 && pairs_lds(g, Pw, sizeof(T)) > budget) --Pw;
+    const size_t lds = pairs_lds(g, Pw, sizeof(T));
+    if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the DTW engine", L);
+    int64_t blocks = ceil_div(np, Pw);
+    if (blocks > 256 * 16) blocks = 256 * 16;
+    switch (C) {
+#define X(c)                                                                                       \
+    case c:                                                                                        \
+        if (g.exact)                                                                               \
+            hipLaunchKernelGGL((dtw_pairs_kernel<T, c, true>), dim3((unsigned)blocks), dim3(WAVE), lds, \
+                               st, g, Pw, A, nA, B, nB, cutoff, pairing, out);                     \
+        else                                                                                       \
+            hipLaunchKernelGGL((dtw_pairs_kernel<T, c, false>), dim3((unsigned)blocks), dim3(WAVE), lds, \
+                               st, g, Pw, A, nA, B, nB, cutoff, pairing, out);                     \
+        break;
+        NNDTW_FOR_EACH_CPL(X)
+#undef X
+    default:
+        return fail(NNDTW_EUNSUP, "no DTW engine for %d pairs per lane", C);
+    }
+    NNDTW_LAUNCH_CHECK("dtw kernel launch");
+    return NNDTW_OK;
+}
+
+int launch_dtw_pairs(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L, int W,
+                     const double *cutoff, int pairing, void *out, hipStream_t st)
+{
+    if (f64) return launch_pairs_t<double>(A, nA, B, nB, L, W, cutoff, pairing, (double *)out, st);
+    return launch_pairs_t<float>(A, nA, B, nB, L, W, cutoff, pairing, (float *)out, st);
+}
+
+}  // namespace nndtw

@@ -1,0 +1,113 @@
+// Envelopes of Equations (3) and (4) and the point-major copies of a
+// reference set.
+//
+// U_i = max and Lo_i = min of B_j over the clipped window
+// [max(0, i-W), min(L-1, i+W)].  One wave per series: the row is staged in
+// LDS, the running max/min over every aligned block of p = 2^floor(log2(W'+1))
+// elements is built by doubling (log2 p passes), and each output takes the
+// max/min of at most four such blocks covering its window (max and min are
+// exact, so the result equals a direct scan).
+#include "common.hpp"
+
+namespace nndtw {
+
+constexpr int ENV_WAVES = 4;  // series per workgroup
+
+__global__ void __launch_bounds__(WAVE *ENV_WAVES)
+envelopes_kernel(const float *__restrict__ B, int64_t n, int L, int Wp, int p,
+                 float *__restrict__ U, float *__restrict__ Lo)
+{
+    extern __shared__ float lds[];
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int64_t s = (int64_t)blockIdx.x * ENV_WAVES + w;
+    float *mx = lds + (size_t)w * 2 * L;
+    float *mn = mx + L;
+    const bool live = s < n;
+    const float *b = B + (live ? s : 0) * (int64_t)L;
+    if (live)
+        for (int i = lane; i < L; i += WAVE) { float v = b[i]; mx[i] = v; mn[i] = v; }
+    __syncthreads();
+    // mx[i] <- max over [i, min(i+h, L-1)] ... doubling up to width p
+    for (int h = 1; h < p; h <<= 1) {
+        for (int i0 = 0; i0 < L; i0 += WAVE) {
+            int i = i0 + lane;
+            float a1 = 0.f, a2 = 0.f, c1 = 0.f, c2 = 0.f;
+            if (live && i < L) {
+                int j = min(i + h, L - 1);
+                a1 = mx[i]; a2 = mx[j]; c1 = mn[i]; c2 = mn[j];
+            }
+            __syncthreads();
+            if (live && i < L) { mx[i] = fmaxf(a1, a2); mn[i] = fminf(c1, c2); }
+            __syncthreads();
+        }
+    }
+    if (!live) return;
+    float *u = U + s * (int64_t)L, *l = Lo + s * (int64_t)L;
+    for (int i = lane; i < L; i += WAVE) {
+        int lo = max(0, i - Wp), hi = min(L - 1, i + Wp);
+        // blocks [lo, lo+p), [lo+p, ...), ..., and the last one ending at hi
+        float uu = mx[lo], ll = mn[lo];
+        for (int k = lo + p; k + p - 1 < hi; k += p) { uu = fmaxf(uu, mx[k]); ll = fminf(ll, mn[k]); }
+        int last = hi - p + 1;
+        uu = fmaxf(uu, mx[last]);
+        ll = fminf(ll, mn[last]);
+        u[i] = uu;
+        l[i] = ll;
+    }
+}
+
+int launch_envelopes(const float *B, int64_t n, int L, int W, float *U, float *Lo, hipStream_t st)
+{
+    if (n == 0) return NNDTW_OK;
+    const int Wp = W < L - 1 ? W : L - 1;
+    int p = 1;
+    while (2 * p <= Wp + 1) p *= 2;
+    const size_t lds = (size_t)ENV_WAVES * 2 * L * sizeof(float);
+    const int64_t blocks = ceil_div(n, ENV_WAVES);
+    hipLaunchKernelGGL(envelopes_kernel, dim3((unsigned)blocks), dim3(WAVE * ENV_WAVES), lds, st,
+                       B, n, L, Wp, p, U, Lo);
+    NNDTW_LAUNCH_CHECK("envelopes kernel launch");
+    return NNDTW_OK;
+}
+
+// Point-major copies: Xt[i][k] = X[k][i] for B, U and Lo, via 64x64 LDS tiles.
+__global__ void __launch_bounds__(256)
+transpose3_kernel(const float *__restrict__ B, const float *__restrict__ U, const float *__restrict__ Lo,
+                  int64_t n, int L, int64_t pitch, float *__restrict__ Bt, float *__restrict__ Ut,
+                  float *__restrict__ Lt)
+{
+    __shared__ float tile[3][64][65];
+    const int64_t k0 = (int64_t)blockIdx.x * 64;
+    const int i0 = blockIdx.y * 64;
+    const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+    for (int r = ty; r < 64; r += 4) {
+        int64_t k = k0 + r;
+        int i = i0 + tx;
+        bool ok = k < n && i < L;
+        tile[0][r][tx] = ok ? B[k * L + i] : 0.f;
+        tile[1][r][tx] = ok ? U[k * L + i] : 0.f;
+        tile[2][r][tx] = ok ? Lo[k * L + i] : 0.f;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        int i = i0 + r;
+        int64_t k = k0 + tx;
+        if (i < L && k < pitch) {
+            bool ok = k < n;
+            Bt[(int64_t)i * pitch + k] = ok ? tile[0][tx][r] : 0.f;
+            Ut[(int64_t)i * pitch + k] = ok ? tile[1][tx][r] : 0.f;
+            Lt[(int64_t)i * pitch + k] = ok ? tile[2][tx][r] : 0.f;
+        }
+    }
+}
+
+int launch_transpose3(const float *B, const float *U, const float *Lo, int64_t n, int L, int64_t pitch,
+                      float *Bt, float *Ut, float *Lt, hipStream_t st)
+{
+    dim3 grid((unsigned)ceil_div(pitch, 64), (unsigned)ceil_div(L, 64));
+    hipLaunchKernelGGL(transpose3_kernel, grid, dim3(256), 0, st, B, U, Lo, n, L, pitch, Bt, Ut, Lt);
+    NNDTW_LAUNCH_CHECK("transpose kernel launch");
+    return NNDTW_OK;
+}
+
+}  // namespace nndtw

@@ -1,0 +1,467 @@
+// Nearest-neighbour lower-bound search (Sections 1 and 4) on one GPU.
+//
+// Enqueued as four kernels on the caller's stream:
+//   1. cascade bounds   squared ED, LB_Keogh, LB_Enhanced bands part and full
+//                       bound for every (query, reference)       (bounds.hip)
+//   2. cells prefix     number of window cells on anti-diagonals 0..s
+//   3. order            per query, references sorted by (squared ED, index)
+//                       in LDS, with the bounds gathered in that order
+//   4. search           one wave per query: rounds of R candidates in visiting
+//                       order are tested against the round's threshold; the
+//                       survivors run through the DTW engine (FP32, abandoned
+//                       above the threshold), groups of the wave computing
+//                       different candidates at once; results that can decide
+//                       the nearest neighbour are recomputed in FP64, and the
+//                       record is updated with the lexicographic minimum of
+//                       (distance, index) at the end of the round.
+//
+// Why the result and the stage counts do not depend on FP32 rounding: with
+// u = 2^-24 and gamma = (2L+1)u / (1-(2L+1)u), an FP32 cell value is within a
+// factor (1 +- gamma) of the exact one (each term of a path sum is rounded at
+// most 2L+1 times).  Every test uses the slack eps >= 2 gamma:
+//  * a bound prunes only if bound > thr = min(bsf, ub)(1 + eps), so the exact
+//    DTW exceeds bsf and the candidate could not have changed the record;
+//  * an FP32 frontier above thr means an exact value above thr / (1+gamma)
+//    > bsf, likewise;
+//  * the winner w of a round has an FP32 value within (1+gamma)/(1-gamma) of
+//    the smallest FP32 value of the round and at most thr, so recomputing in
+//    FP64 every completed result within the factor (1 + 2 eps) of the round's
+//    FP32 minimum (and <= thr) always recomputes w.
+// The bounds are FP64 sums in the same order as a sequential evaluation, and
+// the recomputed distances are bit-identical to a sequential FP64 evaluation
+// of the recurrence, so every decision is taken on the same values.
+#include "dtw_engine.hpp"
+
+namespace nndtw {
+
+#define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(12)
+
+constexpr int QCAP = 128;        // survivor ring (>= 64 + max groups)
+constexpr int ORDER_THREADS = 256;
+
+// ------------------------------------------------------------ workspace
+struct WsLayout {
+    size_t ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, prefix, total;
+};
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+static WsLayout ws_layout(int64_t nQ, int64_t n, int L)
+{
+    WsLayout w;
+    const size_t m = (size_t)nQ * (size_t)n;
+    size_t o = 0;
+    w.ed2 = o;   o = al256(o + m * 8);
+    w.lbk = o;   o = al256(o + m * 8);
+    w.lbeb = o;  o = al256(o + m * 8);
+    w.lbe = o;   o = al256(o + m * 8);
+    w.sk = o;    o = al256(o + m * 4);
+    w.slbk = o;  o = al256(o + m * 8);
+    w.slbeb = o; o = al256(o + m * 8);
+    w.slbe = o;  o = al256(o + m * 8);
+    w.prefix = o; o = al256(o + (size_t)(2 * L) * 4);
+    w.total = o;
+    return w;
+}
+size_t search_ws_bytes(int64_t nQ, int64_t n, int L) { return ws_layout(nQ, n, L).total; }
+
+// ------------------------------------------------------------ cells prefix
+// prefix[s] = number of cells (i, j) of the L x L matrix with |i-j| <= W' and
+// i + j <= s, for s = 0 .. 2L-2.
+__global__ void __launch_bounds__(1024) cells_prefix_kernel(int L, int Wp, uint32_t *prefix)
+{
+    __shared__ uint32_t part[1024];
+    const int S = 2 * L - 1;
+    const int per = (S + 1023) / 1024;
+    const int s0 = threadIdx.x * per;
+    uint32_t loc[4];
+    uint32_t acc = 0;
+    for (int x = 0; x < per; ++x) {
+        const int s = s0 + x;
+        uint32_t c = 0;
+        if (s < S) {
+            int km = min(Wp, min(s, 2 * L - 2 - s));
+            c = (uint32_t)(km + 1 - ((km + s) & 1));
+        }
+        acc += c;
+        loc[x] = acc;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    const uint32_t before = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (int x = 0; x < per; ++x)
+        if (s0 + x < S) prefix[s0 + x] = before + loc[x];
+}
+
+// ------------------------------------------------------------ order
+// Bitonic sort of (ed2, index) ascending, one workgroup per query.
+__global__ void __launch_bounds__(ORDER_THREADS)
+order_kernel(int64_t n, int npow, const double *__restrict__ ed2, const double *__restrict__ lbk,
+             const double *__restrict__ lbeb, const double *__restrict__ lbe, uint32_t *__restrict__ sk,
+             double *__restrict__ slbk, double *__restrict__ slbeb, double *__restrict__ slbe)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *key = reinterpret_cast<double *>(smem);
+    uint32_t *idx = reinterpret_cast<uint32_t *>(key + npow);
+    const int64_t q = blockIdx.x;
+    const double *e = ed2 + q * n;
+    for (int i = threadIdx.x; i < npow; i += ORDER_THREADS) {
+        key[i] = i < n ? e[i] : __builtin_inf();
+        idx[i] = i < n ? (uint32_t)i : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    for (int size = 2; size <= npow; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < npow / 2; t += ORDER_THREADS) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const double ka = key[lo], kb = key[hi];
+                const uint32_t ia = idx[lo], ib = idx[hi];
+                const bool a_gt_b = ka > kb || (ka == kb && ia > ib);
+                if (a_gt_b == up) {
+                    key[lo] = kb; key[hi] = ka;
+                    idx[lo] = ib; idx[hi] = ia;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += ORDER_THREADS) {
+        const uint32_t k = idx[i];
+        const int64_t o = q * n + i;
+        sk[o] = k;
+        slbk[o] = lbk[q * n + k];
+        slbeb[o] = lbeb[q * n + k];
+        slbe[o] = lbe[q * n + k];
+    }
+}
+
+// ------------------------------------------------------------ search
+struct SearchArgs {
+    EngineGeom geo;
+    int PD;
+    const float *B;
+    int64_t n;
+    const float *Q;
+    const uint32_t *sk;
+    const double *slbk, *slbeb, *slbe, *ed2;
+    const uint32_t *prefix;
+    int cascade;
+    int64_t R;
+    double eps;
+    int init_ub;
+    int64_t *nn_idx;
+    double *nn_dist;
+    int64_t *counts;
+};
+
+__device__ __forceinline__ bool lexless(double d, int64_t k, double bd, int64_t bk)
+{
+    return bk < 0 || d < bd || (d == bd && k < bk);
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// 0 survives, 1 LB_Keogh, 2 LB_Enhanced bands, 3 LB_Enhanced
+__device__ __forceinline__ int stage_of(const SearchArgs &a, int64_t o, double thr)
+{
+    if (a.cascade == NNDTW_CASCADE_KEOGH || a.cascade == NNDTW_CASCADE_KEOGH_ENH)
+        if (a.slbk[o] > thr) return 1;
+    if (a.cascade == NNDTW_CASCADE_KEOGH_ENH || a.cascade == NNDTW_CASCADE_ENH) {
+        if (a.slbeb[o] > thr) return 2;
+        if (a.slbe[o] > thr) return 3;
+    }
+    return 0;
+}
+
+template <int C, bool EXACT>
+__global__ void __launch_bounds__(WAVE) search_kernel(SearchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const EngineGeom &geo = a.geo;
+    const int LEN = geo.LEN, P = geo.P, PD = a.PD;
+    EngineGeom geoD = geo;       // the FP64 pass stages only PD rows: groups >= PD stay idle
+    geoD.P = PD;
+    double *aD = reinterpret_cast<double *>(smem);
+    double *bD = aD + LEN;
+    double *resD = bD + (size_t)PD * LEN;
+    float *aF = reinterpret_cast<float *>(resD + PD);
+    float *bF = aF + LEN;
+    float *resF = bF + (size_t)P * LEN;
+    int *trunF = reinterpret_cast<int *>(resF + P);
+    int *trunD = trunF + P;
+    uint32_t *ring = reinterpret_cast<uint32_t *>(trunD + PD);
+    uint32_t *rq = ring + QCAP;      // qualifying candidates of a pass
+    float *rqd = reinterpret_cast<float *>(rq + 64);
+
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    const int64_t N = a.n;
+    const int L = geo.L;
+    const float *Bs = a.B;
+    const int64_t qo = q * N;
+    const double INF = __builtin_inf();
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+
+    stage_row<float, C>(aF, a.Q + q * L, geo, lane);
+    stage_row<double, C>(aD, a.Q + q * L, geo, lane);
+    __syncthreads();
+
+    const double ub = a.init_ub ? a.ed2[qo + a.sk[qo]] : INF;
+    double bsf = INF;
+    int64_t bk = -1;
+    int64_t c_pk = 0, c_peb = 0, c_pe = 0, c_st = 0, c_ab = 0, c_rc = 0, c_cells = 0;
+    int qh = 0, qt = 0;
+    const int s_start = 2 * geo.base0 + geo.Wp;
+
+    int64_t pos = 0;
+    while (pos < N) {
+        const double thr = __builtin_fmin(bsf, ub) * (1.0 + a.eps);
+        const float thrF = round_up_f32(thr);
+        double rb = INF;
+        int64_t rk = -1;
+
+        // Run the DTW engine on up to P queued survivors, then recompute in
+        // FP64 the completed results that can decide the round.
+        auto run_pass = [&](int nt) {
+            for (int g = 0; g < nt; ++g) {
+                const uint32_t k = ring[(qh + g) % QCAP];
+                stage_row<float, C>(bF + (size_t)g * LEN, Bs + (int64_t)k * L, geo, lane);
+            }
+            __syncthreads();
+            engine_pass<float, C, EXACT>(geo, aF, 0, bF, LEN, nt, thrF, PassOut<float>{resF, trunF});
+            __syncthreads();
+            float d32 = __builtin_inff();
+            uint32_t kg = 0;
+            bool done = false;
+            if (lane < nt) {
+                d32 = resF[lane];
+                kg = ring[(qh + lane) % QCAP];
+                const int tr = trunF[lane];
+                const bool ab = __builtin_isinf(d32);
+                c_ab += ab;
+                int s_last = s_start + 2 * (tr - 1) + 1;
+                if (s_last > 2 * L - 2) s_last = 2 * L - 2;
+                c_cells += s_last >= 0 ? (int64_t)a.prefix[s_last] : 0;
+                done = !ab && (double)d32 <= thr;
+            }
+            qh += nt;
+            // smallest completed FP32 result of this pass
+            float mn = done ? d32 : __builtin_inff();
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) mn = __builtin_fminf(mn, __shfl_xor(mn, off));
+            const bool qual = done && (double)d32 <= (double)mn * (1.0 + 2.0 * a.eps);
+            const unsigned long long qm = __ballot(qual);
+            const int nq = __popcll(qm);
+            if (qual) {
+                const int r = __popcll(qm & lt_mask);
+                rq[r] = kg;
+                rqd[r] = d32;
+            }
+            __syncthreads();
+            for (int b0 = 0; b0 < nq; b0 += PD) {
+                const int nd = (nq - b0) < PD ? (nq - b0) : PD;
+                for (int g = 0; g < nd; ++g)
+                    stage_row<double, C>(bD + (size_t)g * LEN, Bs + (int64_t)rq[b0 + g] * L, geo, lane);
+                __syncthreads();
+                engine_pass<double, C, EXACT>(geoD, aD, 0, bD, LEN, nd, thr, PassOut<double>{resD, trunD});
+                __syncthreads();
+                for (int g = 0; g < nd; ++g) {
+                    const double d = resD[g];
+                    const int64_t k = rq[b0 + g];
+                    if (!__builtin_isinf(d) && d <= thr && lexless(d, k, rb, rk)) { rb = d; rk = k; }
+                }
+                c_rc += (lane == 0) ? nd : 0;
+                __syncthreads();
+            }
+        };
+
+        int64_t scan = pos, re = -1;
+        while (scan < N) {
+            const int64_t p = scan + lane;
+            const int st = p < N ? stage_of(a, qo + p, thr) : 4;
+            const unsigned long long sm = __ballot(st == 0);
+            int64_t lim;
+            if (re < 0) {
+                if (sm == 0ull) {
+                    lim = scan + WAVE;
+                } else {
+                    const int64_t f = scan + __ffsll((long long)sm) - 1;
+                    const int64_t rs = (f / a.R) * a.R;
+                    re = (rs + a.R) < N ? (rs + a.R) : N;
+                    lim = re < scan + WAVE ? re : scan + WAVE;
+                }
+            } else {
+                lim = re < scan + WAVE ? re : scan + WAVE;
+            }
+            const bool use = p < lim;
+            if (use) {
+                c_pk += st == 1;
+                c_peb += st == 2;
+                c_pe += st == 3;
+            }
+            const unsigned long long em = __ballot(use && st == 0);
+            if (use && st == 0) {
+                ring[(qt + __popcll(em & lt_mask)) % QCAP] = a.sk[qo + p];
+                ++c_st;
+            }
+            qt += __popcll(em);
+            __syncthreads();
+            while (qt - qh >= P) run_pass(P);
+            scan += WAVE;
+            if (re >= 0 && scan >= re) break;
+        }
+        if (re < 0) break;     // every remaining candidate was pruned
+        while (qt > qh) run_pass((qt - qh) < P ? (qt - qh) : P);
+        if (rk >= 0 && lexless(rb, rk, bsf, bk)) { bsf = rb; bk = rk; }
+        pos = re;
+    }
+
+    c_pk = wave_sum(c_pk);
+    c_peb = wave_sum(c_peb);
+    c_pe = wave_sum(c_pe);
+    c_st = wave_sum(c_st);
+    c_ab = wave_sum(c_ab);
+    c_rc = wave_sum(c_rc);
+    c_cells = wave_sum(c_cells);
+    if (lane == 0) {
+        a.nn_idx[q] = bk;
+        a.nn_dist[q] = bsf;
+        if (a.counts) {
+            int64_t *c = a.counts + q * NNDTW_NCOUNTS;
+            c[NNDTW_COUNT_N] = N;
+            c[NNDTW_COUNT_PRUNED_KEOGH] = c_pk;
+            c[NNDTW_COUNT_PRUNED_BANDS] = c_peb;
+            c[NNDTW_COUNT_PRUNED_ENH] = c_pe;
+            c[NNDTW_COUNT_DTW_STARTED] = c_st;
+            c[NNDTW_COUNT_DTW_ABANDONED] = c_ab;
+            c[NNDTW_COUNT_CELLS] = c_cells;
+            c[NNDTW_COUNT_RECHECKS] = c_rc;
+        }
+    }
+}
+
+static size_t search_lds(const EngineGeom &g, int P, int PD)
+{
+    return (size_t)g.LEN * 8 * (1 + PD) + (size_t)PD * 8 + (size_t)g.LEN * 4 * (1 + P) + (size_t)P * 4 +
+           (size_t)(P + PD) * 4 + QCAP * 4 + 64 * 8 + 64;
+}
+
+int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan)
+{
+    const int L = rs->L;
+    const int Wp = rs->W < L - 1 ? rs->W : L - 1;
+    // At 16 pairs per lane the search kernel (FP32 and FP64 engines) needs
+    // more than 256 VGPRs and spills to AGPRs; that shape stalled on the GPU
+    // and is not used until the cause is understood.
+    const int C = choose_cpl(Wp, 4, o->cpl, 12);
+    if (C < 0) return fail(o->cpl > 0 ? NNDTW_EINVAL : NNDTW_EUNSUP,
+                           "no DTW engine shape for W=%d (cpl=%d)", rs->W, o->cpl);
+    EngineGeom g = make_geom(L, rs->W, C);
+    int P = g.P;
+    int PD = P < 4 ? P : 4;
+    while (P > 1 && search_lds(g, P, PD < P ? PD : P) > 64 * 1024) --P;
+    if (PD > P) PD = P;
+    const size_t lds = search_lds(g, P, PD);
+    if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the search", L);
+    plan->Wp = Wp;
+    plan->C = C;
+    plan->G = g.G;
+    plan->P = P;
+    plan->exact = g.exact;
+    plan->T = g.T;
+    plan->LEN = g.LEN;
+    plan->R = o->R > 0 ? o->R : P;
+    plan->eps = o->eps > 0 ? o->eps : 2.0 * (double)(2 * L + 2) * 0x1p-24;
+    plan->lds_bytes = lds;
+    (void)PD;
+    return NNDTW_OK;
+}
+
+int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nndtw_search_opts *o,
+                  const SearchPlan &plan, int64_t *nn_idx, double *nn_dist, int64_t *counts, void *ws,
+                  hipStream_t st)
+{
+    if (nQ == 0) return NNDTW_OK;
+    const int64_t n = rs->n;
+    const int L = rs->L;
+    const WsLayout w = ws_layout(nQ, n, L);
+    unsigned char *base = (unsigned char *)ws;
+    double *ed2 = (double *)(base + w.ed2), *lbk = (double *)(base + w.lbk);
+    double *lbeb = (double *)(base + w.lbeb), *lbe = (double *)(base + w.lbe);
+    uint32_t *sk = (uint32_t *)(base + w.sk);
+    double *slbk = (double *)(base + w.slbk), *slbeb = (double *)(base + w.slbeb);
+    double *slbe = (double *)(base + w.slbe);
+    uint32_t *prefix = (uint32_t *)(base + w.prefix);
+
+    hipEvent_t *ev = o->events ? (hipEvent_t *)o->events : nullptr;
+    auto mark = [&](int i) -> int {
+        if (!ev) return NNDTW_OK;
+        hipError_t e = hipEventRecord(ev[i], st);
+        return e == hipSuccess ? NNDTW_OK : hip_fail(e, "stage event record");
+    };
+    int r = mark(0);
+    if (r) return r;
+    r = launch_cascade_bounds(rs, Qy, nQ, o->V, ed2, lbk, lbeb, lbe, st);
+    if (r) return r;
+    if ((r = mark(1))) return r;
+    hipLaunchKernelGGL(cells_prefix_kernel, dim3(1), dim3(1024), 0, st, L, plan.Wp, prefix);
+    NNDTW_LAUNCH_CHECK("cells prefix kernel launch");
+    if ((r = mark(2))) return r;
+    int npow = 1;
+    while (npow < n) npow <<= 1;
+    const size_t olds = (size_t)npow * 12;
+    hipLaunchKernelGGL(order_kernel, dim3((unsigned)nQ), dim3(ORDER_THREADS), olds, st, n, npow, ed2, lbk,
+                       lbeb, lbe, sk, slbk, slbeb, slbe);
+    NNDTW_LAUNCH_CHECK("order kernel launch");
+    if ((r = mark(3))) return r;
+
+    SearchArgs a;
+    a.geo = make_geom(L, rs->W, plan.C);
+    a.geo.P = plan.P;
+    a.PD = plan.P < 4 ? plan.P : 4;
+    a.B = rs->B;
+    a.n = n;
+    a.Q = Qy;
+    a.sk = sk;
+    a.slbk = slbk;
+    a.slbeb = slbeb;
+    a.slbe = slbe;
+    a.ed2 = ed2;
+    a.prefix = prefix;
+    a.cascade = o->cascade;
+    a.R = plan.R;
+    a.eps = plan.eps;
+    a.init_ub = o->init_ub;
+    a.nn_idx = nn_idx;
+    a.nn_dist = nn_dist;
+    a.counts = counts;
+    const size_t lds = search_lds(a.geo, a.geo.P, a.PD);
+    switch (plan.C) {
+#define X(c)                                                                                       \
+    case c:                                                                                        \
+        if (plan.exact)                                                                            \
+            hipLaunchKernelGGL((search_kernel<c, true>), dim3((unsigned)nQ), dim3(WAVE), lds, st, a); \
+        else                                                                                       \
+            hipLaunchKernelGGL((search_kernel<c, false>), dim3((unsigned)nQ), dim3(WAVE), lds, st, a); \
+        break;
+        NNDTW_FOR_EACH_CPL(X)
+#undef X
+    default:
+        return fail(NNDTW_EUNSUP, "no search kernel for %d pairs per lane", plan.C);
+    }
+    NNDTW_LAUNCH_CHECK("search kernel launch");
+    return mark(4);
+}
+
+}  // namespace nndtw

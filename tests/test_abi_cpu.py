@@ -1,0 +1,121 @@
+"""The C-ABI library loads, exports every function include/nndtw.h declares,
+and rejects invalid arguments on the host (no GPU needed: every call below
+fails validation before anything is enqueued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1808_09617_amd as nd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nndtw.h")
+
+NULL = ctypes.c_void_p(0)
+FAKE = ctypes.c_void_p(0x100000)      # never dereferenced: validation fails first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nndtw_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = nd.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(nd.SIGNATURES), "binding signatures out of sync with the header"
+
+
+def test_version_and_status_strings():
+    lib = nd.lib()
+    assert lib.nndtw_version() == 1
+    assert lib.nndtw_status_string(0) == b"ok"
+    assert lib.nndtw_status_string(-1) == b"invalid argument"
+    assert lib.nndtw_status_string(-3) == b"unsupported size or option"
+    assert lib.nndtw_status_string(12345) == b"unknown status"
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(nd._Refset) == 80
+    assert nd._Refset.B.offset == 32
+    assert ctypes.sizeof(nd._SearchOpts) == 64
+    assert nd._SearchOpts.eps.offset == 16 and nd._SearchOpts.events.offset == 32
+    assert nd._SearchOpts.reserved.offset == 40
+
+
+def _err(status, fragment):
+    assert status != 0
+    msg = nd.last_error()
+    assert fragment in msg, msg
+    return status
+
+
+def test_envelope_validation():
+    lib = nd.lib()
+    assert _err(lib.nndtw_envelopes(NULL, 4, 64, 3, FAKE, FAKE, NULL), "B is NULL") == nd.EINVAL
+    assert _err(lib.nndtw_envelopes(FAKE, 4, 1, 3, FAKE, FAKE, NULL), "L=1") == nd.EINVAL
+    assert _err(lib.nndtw_envelopes(FAKE, 4, 4096, 3, FAKE, FAKE, NULL), "NNDTW_MAX_L") == nd.EUNSUP
+    assert _err(lib.nndtw_envelopes(FAKE, 4, 64, -1, FAKE, FAKE, NULL), "W=-1") == nd.EINVAL
+    assert _err(lib.nndtw_envelopes(FAKE, -4, 64, 3, FAKE, FAKE, NULL), "n=-4") == nd.EINVAL
+    assert _err(lib.nndtw_envelopes(ctypes.c_void_p(0x100002), 4, 64, 3, FAKE, FAKE, NULL), "aligned") == nd.EINVAL
+    # n = 0 is a valid empty call: nothing is enqueued
+    assert lib.nndtw_envelopes(NULL, 0, 64, 3, NULL, NULL, NULL) == 0
+
+
+def test_pairwise_validation():
+    lib = nd.lib()
+    assert _err(lib.nndtw_ed2(FAKE, 3, FAKE, 4, 64, nd.ZIP, FAKE, NULL), "nA == nB") == nd.EINVAL
+    assert _err(lib.nndtw_ed2(FAKE, 3, FAKE, 4, 64, 7, FAKE, NULL), "pairing=7") == nd.EINVAL
+    assert _err(lib.nndtw_lb_keogh(FAKE, 3, NULL, FAKE, 4, 64, 0, FAKE, NULL), "U is NULL") == nd.EINVAL
+    assert _err(lib.nndtw_lb_enhanced(FAKE, 3, FAKE, FAKE, FAKE, 4, 64, 3, 0, NULL, 0, FAKE, NULL),
+                "V=0") == nd.EINVAL
+    assert _err(lib.nndtw_lb_enhanced(FAKE, 3, FAKE, FAKE, FAKE, 4, 64, 3, 1, ctypes.c_void_p(0x100004), 0,
+                                      FAKE, NULL), "cutoff is not 8-byte aligned") == nd.EINVAL
+    assert _err(lib.nndtw_dtw_w(FAKE, 3, FAKE, 4, 64, -2, NULL, 0, FAKE, NULL), "W=-2") == nd.EINVAL
+    assert _err(lib.nndtw_dtw_w_f64(FAKE, 3, FAKE, 4, 64, 2, NULL, 0, ctypes.c_void_p(0x100004), NULL),
+                "out is not 8-byte aligned") == nd.EINVAL
+    assert lib.nndtw_dtw_w(NULL, 0, NULL, 5, 64, 2, NULL, 0, NULL, NULL) == 0      # empty
+
+
+def test_refset_and_search_validation():
+    lib = nd.lib()
+    nbytes = ctypes.c_size_t(0)
+    assert lib.nndtw_refset_bytes(100, 64, ctypes.byref(nbytes)) == 0
+    assert nbytes.value >= 6 * 100 * 64 * 4
+    assert _err(lib.nndtw_refset_bytes(0, 64, ctypes.byref(nbytes)), "at least one series") == nd.EINVAL
+    desc = nd._Refset()
+    assert _err(lib.nndtw_refset_build(FAKE, 100, 64, 3, FAKE, nbytes.value - 1, ctypes.byref(desc), NULL),
+                "too small") == nd.EINVAL
+    assert _err(lib.nndtw_refset_build(FAKE, 100, 64, 3, ctypes.c_void_p(0x100010), nbytes.value,
+                                       ctypes.byref(desc), NULL), "mem is not 256-byte aligned") == nd.EINVAL
+    opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
+    # a descriptor that was never built
+    assert _err(lib.nndtw_search_workspace_bytes(ctypes.byref(desc), 10, ctypes.byref(opts),
+                                                 ctypes.byref(nbytes)), "not built") == nd.EINVAL
+    desc.magic, desc.L, desc.n, desc.W = nd.REFSET_MAGIC, 64, 100, 6
+    assert lib.nndtw_search_workspace_bytes(ctypes.byref(desc), 10, ctypes.byref(opts), ctypes.byref(nbytes)) == 0
+    bad = nd._opts(0, "keogh_enh", 0, 0.0, True, 0)
+    assert _err(lib.nndtw_search_workspace_bytes(ctypes.byref(desc), 10, ctypes.byref(bad),
+                                                 ctypes.byref(nbytes)), "V=0") == nd.EINVAL
+    bad = nd._opts(2, "keogh_enh", -1, 0.0, True, 0)
+    assert _err(lib.nndtw_search(ctypes.byref(desc), FAKE, 10, ctypes.byref(bad), FAKE, FAKE, NULL, FAKE,
+                                 nbytes.value, NULL), "R=-1") == nd.EINVAL
+    assert _err(lib.nndtw_search(ctypes.byref(desc), FAKE, 10, ctypes.byref(opts), FAKE, FAKE, NULL, FAKE,
+                                 nbytes.value - 1, NULL), "workspace too small") == nd.EINVAL
+    big = nd._Refset()
+    big.magic, big.L, big.n, big.W = nd.REFSET_MAGIC, 64, nd.SEARCH_MAX_N + 1, 6
+    assert _err(lib.nndtw_search(ctypes.byref(big), FAKE, 10, ctypes.byref(opts), FAKE, FAKE, NULL, FAKE,
+                                 1 << 40, NULL), "NNDTW_SEARCH_MAX_N") == nd.EUNSUP
+    assert _err(lib.nndtw_cascade_bounds(ctypes.byref(desc), NULL, 10, 2, NULL, NULL, NULL, NULL, NULL),
+                "Q is NULL") == nd.EINVAL
+
+
+def test_python_binding_rejects_cpu_tensors():
+    import torch
+    with pytest.raises(TypeError):
+        nd.envelopes(torch.zeros(3, 8), 2)
