@@ -44,7 +44,9 @@ class Hip:
     def events(self, n):
         arr = (ctypes.c_void_p * n)()
         for i in range(n):
-            assert self.h.hipEventCreate(ctypes.byref(arr, i * ctypes.sizeof(ctypes.c_void_p))) == 0
+            e = ctypes.c_void_p()
+            assert self.h.hipEventCreate(ctypes.byref(e)) == 0
+            arr[i] = e.value
         return arr
 
     def record(self, ev, stream):
@@ -81,6 +83,7 @@ def main():
     ap.add_argument("--V", type=int, default=5)
     ap.add_argument("--R", type=int, default=0)
     ap.add_argument("--cpl", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the per-query arm and tightness")
@@ -106,7 +109,7 @@ def main():
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
     rs = nd.RefSet(refs, W)
-    srch = nd.Searcher(rs, Q, V=V, cascade="keogh_enh", R=args.R, init_ub=True, cpl=args.cpl)
+    srch = nd.Searcher(rs, Q, V=V, cascade="keogh_enh", R=args.R, init_ub=True, cpl=args.cpl, waves=args.waves)
     log(f"workload nndtw-sin256 N={N} Q={Q} L={L} W={W} V={V}")
 
     def step(ev=None, stage_ev=None):
@@ -161,7 +164,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "nndtw-sin256", "N": N, "Q": Q, "L": L, "W": W, "V": V, "cascade": "keogh_enh",
-                   "R": srch.R, "cpl": srch.cpl, "init_ub": True},
+                   "R": srch.R, "cpl": srch.cpl, "waves_per_query": srch.waves, "init_ub": True},
         "roofline": roof,
         "dtw_cells_per_s": cells / (ms_step / 1e3),
         "search_kernel_cells_per_s": cells / (st_avg["search"] / 1e3),

@@ -209,7 +209,9 @@ typedef struct nndtw_search_opts {
                           * stream before the bound pass, after it, after the
                           * cells table, after the ordering and after the search
                           * kernel; NULL records nothing                              */
-    int64_t reserved[3];
+    int32_t waves;    /* waves per query (1..4); 0 = default; on return: the value used */
+    int32_t reserved32;
+    int64_t reserved[2];
 } nndtw_search_opts;
 
 /* Workspace bytes nndtw_search needs for nQ queries against refset. */

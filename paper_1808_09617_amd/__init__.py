@@ -44,7 +44,8 @@ class _Refset(ctypes.Structure):
 class _SearchOpts(ctypes.Structure):
     _fields_ = [("V", ctypes.c_int32), ("cascade", ctypes.c_int32), ("R", ctypes.c_int64),
                 ("eps", ctypes.c_double), ("init_ub", ctypes.c_int32), ("cpl", ctypes.c_int32),
-                ("events", ctypes.c_void_p), ("reserved", ctypes.c_int64 * 3)]
+                ("events", ctypes.c_void_p), ("waves", ctypes.c_int32), ("reserved32", ctypes.c_int32),
+                ("reserved", ctypes.c_int64 * 2)]
 
 
 _P, _I32, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -219,10 +220,10 @@ class RefSet:
         return self._view(which, (self.L, self.desc.pitch))[:, : self.n]
 
 
-def _opts(V, cascade, R, eps, init_ub, cpl):
+def _opts(V, cascade, R, eps, init_ub, cpl, waves=0):
     o = _SearchOpts()
     o.V, o.cascade, o.R, o.eps = int(V), CASCADES[cascade], int(R), float(eps)
-    o.init_ub, o.cpl = int(bool(init_ub)), int(cpl)
+    o.init_ub, o.cpl, o.waves = int(bool(init_ub)), int(cpl), int(waves)
     return o
 
 
@@ -230,10 +231,10 @@ class Searcher:
     """Preallocated workspace for repeated nndtw_search calls on one RefSet."""
 
     def __init__(self, refset: RefSet, nQ: int, V: int = 5, cascade: str = "keogh_enh", R: int = 0,
-                 eps: float = 0.0, init_ub: bool = True, cpl: int = 0):
+                 eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0):
         self.refset = refset
         self.nQ = int(nQ)
-        self.opts = _opts(V, cascade, R, eps, init_ub, cpl)
+        self.opts = _opts(V, cascade, R, eps, init_ub, cpl, waves)
         nbytes = ctypes.c_size_t(0)
         _check(lib().nndtw_search_workspace_bytes(ctypes.byref(refset.desc), self.nQ, ctypes.byref(self.opts),
                                                   ctypes.byref(nbytes)))
@@ -265,12 +266,16 @@ class Searcher:
     def cpl(self):
         return int(self.opts.cpl)
 
+    @property
+    def waves(self):
+        return int(self.opts.waves)
+
 
 def search(refset: RefSet, Q: torch.Tensor, V: int = 5, cascade: str = "keogh_enh", R: int = 0,
-           eps: float = 0.0, init_ub: bool = True, cpl: int = 0):
+           eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0):
     """One-shot NN-DTW search: returns (nn_idx int64, nn_dist float64, counts int64[nQ][8], R used)."""
     Q = _series(Q, "Q")
-    s = Searcher(refset, Q.shape[0], V, cascade, R, eps, init_ub, cpl)
+    s = Searcher(refset, Q.shape[0], V, cascade, R, eps, init_ub, cpl, waves)
     idx, dist, counts = s(Q)
     return idx.clone(), dist.clone(), counts.clone(), s.R
 

@@ -249,6 +249,7 @@ static int check_opts(const nndtw_search_opts *o)
     REQUIRE(o->cascade >= NNDTW_CASCADE_NONE && o->cascade <= NNDTW_CASCADE_ENH, "cascade=%d unknown", o->cascade);
     REQUIRE(o->R >= 0, "R=%lld must be >= 0", (long long)o->R);
     REQUIRE(o->cpl >= 0, "cpl=%d must be >= 0", o->cpl);
+    REQUIRE(o->waves >= 0 && o->waves <= 4, "waves=%d must be in 0..4", o->waves);
     return NNDTW_OK;
 }
 
@@ -286,6 +287,7 @@ int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ, nndtw_s
     TRY(plan_search(refset, opts, &plan));
     opts->R = plan.R;
     opts->cpl = plan.C;
+    opts->waves = plan.NW;
     return launch_search(refset, Q, nQ, opts, plan, nn_idx, nn_dist, counts, ws, (hipStream_t)stream);
 }
 

@@ -44,7 +44,7 @@ int launch_dtw_pairs(bool f64, const float *A, int64_t nA, const float *B, int64
                      int W, const double *cutoff, int pairing, void *out, hipStream_t s);
 // search.hip
 struct SearchPlan {
-    int Wp, C, G, P, exact, T, LEN;
+    int Wp, C, G, P, PD, SLOTS, NW, exact, T, LEN;
     int64_t R;
     double eps;
     size_t lds_bytes;
@@ -55,10 +55,14 @@ int launch_search(const nndtw_refset *rs, const float *Q, int64_t nQ, const nndt
                   const SearchPlan &plan, int64_t *nn_idx, double *nn_dist, int64_t *counts,
                   void *ws, hipStream_t s);
 
+// LDS prefetch distance (super-steps) of the DTW engine for C diagonal pairs
+// per lane: enough super-steps to cover the LDS read latency.
+__host__ __device__ constexpr int prefetch_of(int C) { return C == 1 ? 4 : (C <= 6 ? 2 : 1); }
+
 // Engine geometry shared by the DTW kernels (see dtw_engine.hpp).
 struct EngineGeom {
     int L, Wp, C, G, P, exact;
-    int T;      // super-steps (multiple of C + 1)
+    int T;      // super-steps (multiple of C + prefetch_of(C))
     int base0;  // series index of the first super-step's base
     int LEN;    // elements per staged series in LDS (with padding)
 };

@@ -5,7 +5,7 @@
 namespace nndtw {
 
 // Diagonal pairs per lane that the kernels are instantiated for.
-#define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16)
+#define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(9) X(12) X(16)
 
 bool cpl_supported(int C)
 {
@@ -37,7 +37,7 @@ int choose_cpl(int Wp, int cmax, int prefer, int chard)
         return (cpl_supported(prefer) && prefer <= chard && cpl_score(Wp, prefer) > 0) ? prefer : -1;
     int best = -1;
     double bs = -1.0;
-    const int cands[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    const int cands[] = {1, 2, 3, 4, 6, 8, 9, 12, 16};
     for (int pass = 0; pass < 2 && best < 0; ++pass) {
         for (int C : cands) {
             if (C > chard || (pass == 0 && C > cmax)) continue;
@@ -60,57 +60,57 @@ EngineGeom make_geom(int L, int W, int C)
     g.G = (int)ceil_div(g.Wp + 1, C);
     g.exact = g.G * C == g.Wp + 1;
     g.P = 63 / g.G;
+    const int M = C + prefetch_of(C);
     const int T0 = L + (g.Wp + 2) / 2;
-    const int epad = (C + 1 - T0 % (C + 1)) % (C + 1);
+    const int epad = (M - T0 % M) % M;
     g.T = T0 + epad;
     g.base0 = -g.Wp - 1 - epad;
-    g.LEN = g.T + g.Wp + 2 * C + 2;
+    g.LEN = g.T + g.Wp + 2 * C + prefetch_of(C) + 2;
     return g;
 }
 
 template <typename T, int C, bool EXACT>
 __global__ void __launch_bounds__(WAVE)
-dtw_pairs_kernel(EngineGeom geo, int Pw, const float *__restrict__ A, int64_t nA,
+dtw_pairs_kernel(EngineGeom geo, int NB, const float *__restrict__ A, int64_t nA,
                  const float *__restrict__ B, int64_t nB, const double *__restrict__ cutoff,
                  int pairing, T *__restrict__ out)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     T *aR = reinterpret_cast<T *>(smem);
-    T *bR = aR + (size_t)Pw * geo.LEN;
-    T *res = bR + (size_t)Pw * geo.LEN;
-    int *trun = reinterpret_cast<int *>(res + Pw);
+    T *bR = aR + (size_t)NB * geo.LEN;
+    T *res = bR + (size_t)NB * geo.LEN;
+    int *trun = reinterpret_cast<int *>(res + NB);
+    int *next_task = trun + NB;
     const int lane = threadIdx.x;
-    const int L = geo.L;
+    const int LEN = geo.LEN;
     const int64_t np = pairing ? nA : nA * nB;
-    EngineGeom gw = geo;
-    gw.P = Pw;
-    for (int64_t base = (int64_t)blockIdx.x * Pw; base < np; base += (int64_t)gridDim.x * Pw) {
-        const int nact = (int)((np - base) < Pw ? (np - base) : Pw);
-        for (int g = 0; g < nact; ++g) {
-            const int64_t p = base + g;
-            const int64_t ia = pairing ? p : p / nB, ib = pairing ? p : p % nB;
-            stage_row<T, C>(aR + (size_t)g * geo.LEN, A + ia * L, geo, lane);
-            stage_row<T, C>(bR + (size_t)g * geo.LEN, B + ib * L, geo, lane);
-        }
+    for (int64_t base = (int64_t)blockIdx.x * NB; base < np; base += (int64_t)gridDim.x * NB) {
+        const int nt = (int)((np - base) < NB ? (np - base) : NB);
+        stage_rows<T, C>(aR, A, [&](int i) { const int64_t p = base + i; return pairing ? p : p / nB; }, nt, geo,
+                         lane);
+        stage_rows<T, C>(bR, B, [&](int i) { const int64_t p = base + i; return pairing ? p : p % nB; }, nt, geo,
+                         lane);
+        if (lane == 0) *next_task = 0;
         __syncthreads();
-        // per-lane threshold of the lane's group
-        const int gi = lane >= 1 ? (lane - 1) / geo.G : 0;
-        T thr = inf_of<T>();
-        if (cutoff && lane >= 1 && gi < nact) {
-            const int64_t p = base + gi;
-            const double c = cutoff[pairing ? p : p / nB];
-            thr = sizeof(T) == 4 ? (T)round_up_f32(c) : (T)c;
-        }
-        engine_pass<T, C, EXACT>(gw, aR, geo.LEN, bR, geo.LEN, nact, thr, PassOut<T>{res, trun});
+        engine_run<T, C, EXACT>(
+            geo, nt, next_task, [&](int i) { return (const T *)(aR + (size_t)i * LEN); },
+            [&](int i) { return (const T *)(bR + (size_t)i * LEN); },
+            [&](int i) -> T {
+                if (!cutoff) return inf_of<T>();
+                const int64_t p = base + i;
+                const double c = cutoff[pairing ? p : p / nB];
+                return sizeof(T) == 4 ? (T)round_up_f32(c) : (T)c;
+            },
+            TaskOut<T>{res, trun});
         __syncthreads();
-        if (lane < nact) out[base + lane] = res[lane];
+        if (lane < nt) out[base + lane] = res[lane];
         __syncthreads();
     }
 }
 
-static size_t pairs_lds(const EngineGeom &g, int Pw, size_t esz)
+static size_t pairs_lds(const EngineGeom &g, int NB, size_t esz)
 {
-    return (size_t)2 * Pw * g.LEN * esz + (size_t)Pw * (esz + sizeof(int)) + 16;
+    return (size_t)2 * NB * g.LEN * esz + (size_t)NB * (esz + sizeof(int)) + 32;
 }
 
 template <typename T>
@@ -123,22 +123,24 @@ static int launch_pairs_t(const float *A, int64_t nA, const float *B, int64_t nB
     const int C = choose_cpl(Wp, 16, 0);
     if (C < 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
     EngineGeom g = make_geom(L, W, C);
-    int Pw = g.P;
-    const size_t budget = 64 * 1024;
-    while (Pw > 1 && pairs_lds(g, Pw, sizeof(T)) > budget) --Pw;
-    const size_t lds = pairs_lds(g, Pw, sizeof(T));
+    // Tasks staged per batch: two per group so that groups refill, within
+    // 64 KB of LDS (at least one).
+    int NB = 2 * g.P < 64 ? 2 * g.P : 64;
+    while (NB > 1 && pairs_lds(g, NB, sizeof(T)) > 64 * 1024) --NB;
+    if (NB < g.P) g.P = NB;
+    const size_t lds = pairs_lds(g, NB, sizeof(T));
     if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the DTW engine", L);
-    int64_t blocks = ceil_div(np, Pw);
+    int64_t blocks = ceil_div(np, NB);
     if (blocks > 256 * 16) blocks = 256 * 16;
     switch (C) {
 #define X(c)                                                                                       \
     case c:                                                                                        \
         if (g.exact)                                                                               \
             hipLaunchKernelGGL((dtw_pairs_kernel<T, c, true>), dim3((unsigned)blocks), dim3(WAVE), lds, \
-                               st, g, Pw, A, nA, B, nB, cutoff, pairing, out);                     \
+                               st, g, NB, A, nA, B, nB, cutoff, pairing, out);                     \
         else                                                                                       \
             hipLaunchKernelGGL((dtw_pairs_kernel<T, c, false>), dim3((unsigned)blocks), dim3(WAVE), lds, \
-                               st, g, Pw, A, nA, B, nB, cutoff, pairing, out);                     \
+                               st, g, NB, A, nA, B, nB, cutoff, pairing, out);                     \
         break;
         NNDTW_FOR_EACH_CPL(X)
 #undef X

@@ -101,6 +101,14 @@ template <> __device__ __forceinline__ double inf_of<double>() { return __builti
 // Padding left of the first series element inside a staged LDS row (elements).
 template <int C> struct Stage { static constexpr int PADL = C; };
 
+// Window registers of a lane: C+1 values are in use at a super-step and the
+// LDS reads for super-step t+D are issued at the end of super-step t, so the
+// windows hold M = C + D values and rotate with period M.
+template <int C> struct Win {
+    static constexpr int D = prefetch_of(C);
+    static constexpr int M = C + D;
+};
+
 // Stage series `src` (float[L], global) into LDS row `dst` of geo.LEN
 // elements with PAD outside [0, L).  Whole-wave cooperative.
 template <typename T, int C>
@@ -113,72 +121,162 @@ __device__ __forceinline__ void stage_row(T *dst, const float *__restrict__ src,
     }
 }
 
-// Result of one pass, per group (written to LDS by the group's result lane).
-template <typename T> struct PassOut {
-    T *res;    // DTW_W, or +inf if abandoned
-    int *trun; // super-steps executed
+// Stage `nrows` series (row r is src + krow(r) * L) into consecutive LDS rows
+// of geo.LEN elements.  Flattened over all rows, each thread keeps U global
+// loads in flight before its LDS stores.  Cooperative over `nthreads`
+// threads (tid = 0 .. nthreads-1).
+template <typename T, int C, typename KF>
+__device__ __forceinline__ void stage_rows(T *dst, const float *__restrict__ src, KF krow, int nrows,
+                                           const EngineGeom &geo, int tid, int nthreads = WAVE)
+{
+    constexpr int U = 16;
+    const int LEN = geo.LEN, L = geo.L;
+    const int first = geo.base0 - Stage<C>::PADL;
+    const int total = nrows * LEN;
+    int g = 0, x = tid;
+    while (x >= LEN) { x -= LEN; ++g; }
+    for (int e0 = 0; e0 < total; e0 += nthreads * U) {
+        T v[U];
+        int gg[U], xx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            gg[u] = g;
+            xx[u] = x;
+            const int idx = first + x;
+            v[u] = Pad<T>::big();
+            if (g < nrows && idx >= 0 && idx < L) v[u] = (T)src[(int64_t)krow(g) * L + idx];
+            x += nthreads;
+            while (x >= LEN) { x -= LEN; ++g; }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (gg[u] < nrows) dst[(size_t)gg[u] * LEN + xx[u]] = v[u];
+    }
+}
+
+// Per-task outputs (LDS), written by the result lane of the group that ran
+// the task.
+template <typename T> struct TaskOut {
+    T *res;     // DTW_W, or +inf if abandoned
+    int *trun;  // super-steps executed
 };
 
-// One pass: groups 0..nact-1 each compute DTW_W of the pair staged at
-// aRow(g) / bRow(g).  thr: abandon threshold (+inf: never).  Must be called
-// by the whole wave with uniform arguments.
-template <typename T, int C, bool EXACT>
-__device__ __forceinline__ void engine_pass(const EngineGeom &geo, const T *aRows, int aStride,
-                                            const T *bRows, int bStride, int nact, T thr,
-                                            PassOut<T> out)
+// Run `ntasks` DTW tasks on the P groups of each calling wave.  Tasks are
+// dealt from the LDS counter *next_task (0 before the call, shared by every
+// wave of the workgroup that takes part).  Task i compares the
+// staged rows arow(i) and brow(i) (LDS, geo.LEN elements each) and is
+// abandoned once its frontier exceeds thr_of(i).  A group takes the next
+// task as soon as its current one ends (completed or abandoned), at the next
+// block boundary (every M super-steps), so abandoned candidates free their
+// lanes early.  Every task starts at super-step 0 of its own sweep; block
+// boundaries are multiples of M in every group, which keeps the register
+// rotation of the windows the same in all groups.  Whole-wave call with
+// uniform arguments; ntasks >= 1.
+template <typename T, int C, bool EXACT, typename ARow, typename BRow, typename Thr>
+__device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, int *next_task, ARow arow, BRow brow,
+                                           Thr thr_of, TaskOut<T> out)
 {
+    constexpr int D = Win<C>::D, M = Win<C>::M;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int G = geo.G, Wp = geo.Wp;
+    const int G = geo.G, Wp = geo.Wp, T_ = geo.T;
     const int gi = lane >= 1 ? (lane - 1) / G : 0;
     const int gl = lane >= 1 ? (lane - 1) - gi * G : 0;
     const bool in_group = lane >= 1 && gi < geo.P;
-    const bool has_task = in_group && gi < nact;
     const int g = in_group ? gi : 0;                 // sentinel / idle lanes shadow group 0
     const int glc = in_group ? gl * C : 0;
+    const int lane0 = 1 + g * G;                     // first lane of the group
     const T INF = inf_of<T>();
+    const unsigned long long gmask = (1ull << G) - 1ull;
+    // D(L-1, L-1) lies on diagonal 0: pair W'/2, bottom diagonal if W' is even.
+    const int p0 = Wp >> 1, m0 = p0 % C;
+    const bool rlane = in_group && gl == p0 / C;
 
-    const T *aP = aRows + (size_t)g * aStride + Stage<C>::PADL + glc;
-    const T *bP = bRows + (size_t)g * bStride + Stage<C>::PADL + Wp - glc;
-
-    T X0[C], X1[C], Aw[C + 1], Bw[C + 1];
     // Forced-infinite slots: the out-of-window diagonal W'+1 and the last
     // top diagonal of each group (and the sentinel's, which lane 1 reads).
-    bool force_last = (lane == 0) || (in_group && gl == G - 1);
+    const bool force_last = (lane == 0) || (in_group && gl == G - 1);
     T tm[EXACT ? 1 : C];
 #pragma unroll
-    for (int m = 0; m < C; ++m) {
-        const int p = glc + m;                       // global pair index
-        X0[m] = (!EXACT && in_group && p > Wp) ? INF : (T)0;
-        X1[m] = (!EXACT && in_group && p >= Wp) ? INF : (T)0;
-        if (!EXACT) tm[m] = ((m == C - 1 && force_last) || (in_group && p == Wp)) ? INF : (T)0;
-    }
-    if (EXACT && force_last) X1[C - 1] = INF;
-#pragma unroll
-    for (int m = 0; m <= C; ++m) Aw[m] = aP[m];
-    Bw[1 % (C + 1)] = (T)0;                          // b-slot C: unused until refilled
-#pragma unroll
-    for (int m = 0; m < C; ++m) Bw[(C + 1 - m) % (C + 1)] = bP[-m];
+    for (int m = 0; m < C; ++m)
+        if (!EXACT) tm[m] = ((m == C - 1 && force_last) || (in_group && glc + m == Wp)) ? INF : (T)0;
 
-    bool dead = !has_task;
-    int trun = geo.T;
-    for (int t0 = 0; t0 < geo.T; t0 += C + 1) {
+    T X0[C], X1[C], Aw[M], Bw[M];
+    const T *aP = arow(0) + Stage<C>::PADL + glc;
+    const T *bP = brow(0) + Stage<C>::PADL + Wp - glc;
 #pragma unroll
-        for (int u = 0; u <= C; ++u) {
-            const int t = t0 + u;
+    for (int m = 0; m < C; ++m) { X0[m] = (T)0; X1[m] = (T)0; }
+#pragma unroll
+    for (int m = 0; m < M; ++m) { Aw[m] = (T)0; Bw[m] = (T)0; }
+    if (force_last) X1[C - 1] = INF;
+
+    int task = -1, tl = 0;
+    bool dead = true, exhausted = false;
+    T thr = INF;
+    while (true) {
+        // retire the tasks that ended
+        if (__ballot(task >= 0 && (dead || tl >= T_)) != 0ull && task >= 0 && (dead || tl >= T_)) {
+            if (rlane) {
+                T r = INF;
+#pragma unroll
+                for (int m = 0; m < C; ++m)
+                    if (m == m0) r = (Wp & 1) ? X1[m] : X0[m];
+                out.res[task] = dead ? INF : r;
+                out.trun[task] = dead ? tl : T_;
+            }
+            task = -1;
+            tl = 0;
+        }
+        // hand the next tasks to free groups, in group order
+        const unsigned long long freem = __ballot(in_group && gl == 0 && task < 0);
+        const int nfree = __popcll(freem);
+        if (nfree > 0 && !exhausted) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(next_task, nfree);
+            base = __shfl(base, 0);
+            const int left = ntasks - base;
+            const int nassign = left < nfree ? (left > 0 ? left : 0) : nfree;
+            exhausted = left <= nfree;
+            const int rank = __popcll(freem & ((1ull << lane0) - 1ull));
+            if (in_group && task < 0 && rank < nassign) {
+                task = base + rank;
+                thr = thr_of(task);
+                dead = false;
+                aP = arow(task) + Stage<C>::PADL + glc;
+                bP = brow(task) + Stage<C>::PADL + Wp - glc;
+#pragma unroll
+                for (int m = 0; m < C; ++m) {
+                    const int p = glc + m;           // global pair index
+                    X0[m] = (!EXACT && p > Wp) ? INF : (T)0;
+                    X1[m] = (!EXACT && p >= Wp) ? INF : (T)0;
+                }
+                if (EXACT && force_last) X1[C - 1] = INF;
+                // a-slot m at super-step t is aP[t + m] in Aw[(t + m) % M];
+                // b-slot m is bP[t - m] in Bw[(t - m) mod M]: preload what
+                // super-steps 0..D-1 read.
+#pragma unroll
+                for (int r = 0; r < C + D; ++r) Aw[r % M] = aP[r];
+#pragma unroll
+                for (int r = 1 - C; r <= D - 1; ++r) Bw[((r % M) + M) % M] = bP[r];
+            }
+        }
+        if (__ballot(task >= 0) == 0ull) break;
+
+        const T *aC = aP + tl, *bC = bP + tl;
+#pragma unroll
+        for (int u = 0; u < M; ++u) {
             // bottom diagonals: anti-diagonal s_b(t)
-            T nb = from_lower(X1[C - 1]);
+            const T nb = from_lower(X1[C - 1]);
 #pragma unroll
             for (int m = 0; m < C; ++m) {
-                T lo = (m == 0) ? nb : X1[m - 1];
-                T d = Aw[(u + m) % (C + 1)] - Bw[(u - m + C + 1) % (C + 1)];
+                const T lo = (m == 0) ? nb : X1[m - 1];
+                const T d = Aw[(u + m) % M] - Bw[(u - m + M) % M];
                 X0[m] = cell(d, min3(X0[m], lo, X1[m]));
             }
             // top diagonals: anti-diagonal s_b(t) + 1
-            T nt = from_upper(X0[0]);
+            const T nt = from_upper(X0[0]);
 #pragma unroll
             for (int m = 0; m < C; ++m) {
-                T hi = (m == C - 1) ? nt : X0[m + 1];
-                T d = Aw[(u + m + 1) % (C + 1)] - Bw[(u - m + C + 1) % (C + 1)];
+                const T hi = (m == C - 1) ? nt : X0[m + 1];
+                const T d = Aw[(u + m + 1) % M] - Bw[(u - m + M) % M];
                 X1[m] = cell(d, min3(X1[m], X0[m], hi));
             }
             if (EXACT) {
@@ -187,34 +285,17 @@ __device__ __forceinline__ void engine_pass(const EngineGeom &geo, const T *aRow
 #pragma unroll
                 for (int m = 0; m < C; ++m) X1[m] = vmax(X1[m], tm[m]);
             }
-            // windows for super-step t+1
-            Aw[u] = aP[t + 1 + C];
-            Bw[(u + 1) % (C + 1)] = bP[t + 1];
+            // windows for super-step t+D
+            Aw[(u + D + C) % M] = aC[u + D + C];
+            Bw[(u + D) % M] = bC[u + D];
         }
+        if (task >= 0) tl += M;
         // early abandon on the frontier (two consecutive anti-diagonals)
         T lm = vmin(X0[0], X1[0]);
 #pragma unroll
         for (int m = 1; m < C; ++m) lm = min3(lm, X0[m], X1[m]);
-        unsigned long long ok = __ballot(lm <= thr);
-        unsigned long long gmask = (G >= 64) ? ~0ull : ((1ull << G) - 1ull);
-        bool alive = ((ok >> (1 + g * G)) & gmask) != 0ull;
-        if (!dead && !alive) {
-            dead = true;
-            trun = t0 + C + 1;
-        }
-        if (__ballot(!dead) == 0ull) break;
-    }
-    // D(L-1, L-1) lies on diagonal 0: pair W'/2, bottom if W' is even.
-    const int p0 = Wp >> 1;
-    const int rlane = 1 + g * G + p0 / C;
-    if (has_task && lane == rlane) {
-        const int m0 = p0 % C;
-        T r = INF;
-#pragma unroll
-        for (int m = 0; m < C; ++m)
-            if (m == m0) r = (Wp & 1) ? X1[m] : X0[m];
-        out.res[gi] = dead ? INF : r;
-        out.trun[gi] = trun;
+        const unsigned long long ok = __ballot(lm <= thr);
+        if (task >= 0 && ((ok >> lane0) & gmask) == 0ull) dead = true;
     }
 }
 

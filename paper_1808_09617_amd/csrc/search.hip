@@ -34,9 +34,10 @@
 
 namespace nndtw {
 
-#define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(12)
+#define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(9) X(12)
 
-constexpr int QCAP = 128;        // survivor ring (>= 64 + max groups)
+constexpr int QCAP = 128;        // survivor ring (>= 64 + max staged rows)
+constexpr int SEARCH_MAX_WAVES = 4;
 constexpr int ORDER_THREADS = 256;
 
 // ------------------------------------------------------------ workspace
@@ -144,7 +145,8 @@ order_kernel(int64_t n, int npow, const double *__restrict__ ed2, const double *
 // ------------------------------------------------------------ search
 struct SearchArgs {
     EngineGeom geo;
-    int PD;
+    int PD;        // staged rows of the FP64 recheck
+    int SLOTS;     // staged candidate rows per FP32 batch (<= 64)
     const float *B;
     int64_t n;
     const float *Q;
@@ -173,38 +175,42 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v)
 }
 
 // 0 survives, 1 LB_Keogh, 2 LB_Enhanced bands, 3 LB_Enhanced
-__device__ __forceinline__ int stage_of(const SearchArgs &a, int64_t o, double thr)
+__device__ __forceinline__ int stage_of(int cascade, double lbk, double lbb, double lbe, double thr)
 {
-    if (a.cascade == NNDTW_CASCADE_KEOGH || a.cascade == NNDTW_CASCADE_KEOGH_ENH)
-        if (a.slbk[o] > thr) return 1;
-    if (a.cascade == NNDTW_CASCADE_KEOGH_ENH || a.cascade == NNDTW_CASCADE_ENH) {
-        if (a.slbeb[o] > thr) return 2;
-        if (a.slbe[o] > thr) return 3;
+    if (cascade == NNDTW_CASCADE_KEOGH || cascade == NNDTW_CASCADE_KEOGH_ENH)
+        if (lbk > thr) return 1;
+    if (cascade == NNDTW_CASCADE_KEOGH_ENH || cascade == NNDTW_CASCADE_ENH) {
+        if (lbb > thr) return 2;
+        if (lbe > thr) return 3;
     }
     return 0;
 }
 
+// One workgroup of NW waves per query.  All waves run the same control flow
+// on identical values (the scan, the thresholds, the record); only wave 0
+// writes shared LDS state and counts.  Staging and DTW tasks are spread over
+// all waves (tasks dealt from an LDS counter).
 template <int C, bool EXACT>
-__global__ void __launch_bounds__(WAVE) search_kernel(SearchArgs a)
+__global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const EngineGeom &geo = a.geo;
-    const int LEN = geo.LEN, P = geo.P, PD = a.PD;
-    EngineGeom geoD = geo;       // the FP64 pass stages only PD rows: groups >= PD stay idle
-    geoD.P = PD;
+    const int LEN = geo.LEN, PD = a.PD, SLOTS = a.SLOTS;
     double *aD = reinterpret_cast<double *>(smem);
     double *bD = aD + LEN;
     double *resD = bD + (size_t)PD * LEN;
     float *aF = reinterpret_cast<float *>(resD + PD);
     float *bF = aF + LEN;
-    float *resF = bF + (size_t)P * LEN;
-    int *trunF = reinterpret_cast<int *>(resF + P);
-    int *trunD = trunF + P;
+    float *resF = bF + (size_t)SLOTS * LEN;
+    int *trunF = reinterpret_cast<int *>(resF + SLOTS);
+    int *trunD = trunF + SLOTS;
     uint32_t *ring = reinterpret_cast<uint32_t *>(trunD + PD);
-    uint32_t *rq = ring + QCAP;      // qualifying candidates of a pass
-    float *rqd = reinterpret_cast<float *>(rq + 64);
+    uint32_t *rq = ring + QCAP;      // qualifying candidates of a batch
+    int *next_task = reinterpret_cast<int *>(rq + 64);
 
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & (WAVE - 1);
+    const bool w0 = tid < WAVE;
     const int64_t q = blockIdx.x;
     const int64_t N = a.n;
     const int L = geo.L;
@@ -213,8 +219,8 @@ __global__ void __launch_bounds__(WAVE) search_kernel(SearchArgs a)
     const double INF = __builtin_inf();
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
-    stage_row<float, C>(aF, a.Q + q * L, geo, lane);
-    stage_row<double, C>(aD, a.Q + q * L, geo, lane);
+    stage_rows<float, C>(aF, a.Q, [&](int) { return q; }, 1, geo, tid, nthr);
+    stage_rows<double, C>(aD, a.Q, [&](int) { return q; }, 1, geo, tid, nthr);
     __syncthreads();
 
     const double ub = a.init_ub ? a.ed2[qo + a.sk[qo]] : INF;
@@ -222,6 +228,9 @@ __global__ void __launch_bounds__(WAVE) search_kernel(SearchArgs a)
     int64_t bk = -1;
     int64_t c_pk = 0, c_peb = 0, c_pe = 0, c_st = 0, c_ab = 0, c_rc = 0, c_cells = 0;
     int qh = 0, qt = 0;
+    int64_t cached = -1;                 // chunk start whose bounds the lanes hold
+    uint32_t ck = 0;
+    double cbk = 0.0, cbb = 0.0, cbe = 0.0;
     const int s_start = 2 * geo.base0 + geo.Wp;
 
     int64_t pos = 0;
@@ -231,22 +240,25 @@ __global__ void __launch_bounds__(WAVE) search_kernel(SearchArgs a)
         double rb = INF;
         int64_t rk = -1;
 
-        // Run the DTW engine on up to P queued survivors, then recompute in
-        // FP64 the completed results that can decide the round.
-        auto run_pass = [&](int nt) {
-            for (int g = 0; g < nt; ++g) {
-                const uint32_t k = ring[(qh + g) % QCAP];
-                stage_row<float, C>(bF + (size_t)g * LEN, Bs + (int64_t)k * L, geo, lane);
-            }
+        // Run up to SLOTS queued survivors through the FP32 engine (their
+        // rows staged once; groups refill as candidates end), then recompute
+        // in FP64 the completed results that can decide the round.
+        auto run_batch = [&](int nt) {
+            const int h0 = qh;
+            stage_rows<float, C>(bF, Bs, [&](int i) { return ring[(h0 + i) % QCAP]; }, nt, geo, tid, nthr);
+            if (tid == 0) *next_task = 0;
             __syncthreads();
-            engine_pass<float, C, EXACT>(geo, aF, 0, bF, LEN, nt, thrF, PassOut<float>{resF, trunF});
+            engine_run<float, C, EXACT>(
+                geo, nt, next_task, [&](int) { return (const float *)aF; },
+                [&](int i) { return (const float *)(bF + (size_t)i * LEN); }, [&](int) { return thrF; },
+                TaskOut<float>{resF, trunF});
             __syncthreads();
             float d32 = __builtin_inff();
             uint32_t kg = 0;
             bool done = false;
             if (lane < nt) {
                 d32 = resF[lane];
-                kg = ring[(qh + lane) % QCAP];
+                kg = ring[(h0 + lane) % QCAP];
                 const int tr = trunF[lane];
                 const bool ab = __builtin_isinf(d32);
                 c_ab += ab;
@@ -256,77 +268,89 @@ __global__ void __launch_bounds__(WAVE) search_kernel(SearchArgs a)
                 done = !ab && (double)d32 <= thr;
             }
             qh += nt;
-            // smallest completed FP32 result of this pass
+            // smallest completed FP32 result of this batch
             float mn = done ? d32 : __builtin_inff();
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) mn = __builtin_fminf(mn, __shfl_xor(mn, off));
             const bool qual = done && (double)d32 <= (double)mn * (1.0 + 2.0 * a.eps);
             const unsigned long long qm = __ballot(qual);
             const int nq = __popcll(qm);
-            if (qual) {
-                const int r = __popcll(qm & lt_mask);
-                rq[r] = kg;
-                rqd[r] = d32;
-            }
-            __syncthreads();
+            __syncthreads();                 // every wave has read the batch results
+            if (w0 && qual) rq[__popcll(qm & lt_mask)] = kg;
             for (int b0 = 0; b0 < nq; b0 += PD) {
                 const int nd = (nq - b0) < PD ? (nq - b0) : PD;
-                for (int g = 0; g < nd; ++g)
-                    stage_row<double, C>(bD + (size_t)g * LEN, Bs + (int64_t)rq[b0 + g] * L, geo, lane);
                 __syncthreads();
-                engine_pass<double, C, EXACT>(geoD, aD, 0, bD, LEN, nd, thr, PassOut<double>{resD, trunD});
+                stage_rows<double, C>(bD, Bs, [&](int i) { return rq[b0 + i]; }, nd, geo, tid, nthr);
+                if (tid == 0) *next_task = 0;
                 __syncthreads();
-                for (int g = 0; g < nd; ++g) {
-                    const double d = resD[g];
-                    const int64_t k = rq[b0 + g];
+                engine_run<double, C, EXACT>(
+                    geo, nd, next_task, [&](int) { return (const double *)aD; },
+                    [&](int i) { return (const double *)(bD + (size_t)i * LEN); }, [&](int) { return thr; },
+                    TaskOut<double>{resD, trunD});
+                __syncthreads();
+                for (int i = 0; i < nd; ++i) {
+                    const double d = resD[i];
+                    const int64_t k = rq[b0 + i];
                     if (!__builtin_isinf(d) && d <= thr && lexless(d, k, rb, rk)) { rb = d; rk = k; }
                 }
                 c_rc += (lane == 0) ? nd : 0;
-                __syncthreads();
             }
+            __syncthreads();
         };
 
+        // Scan the visiting order in aligned chunks of 64 positions (bounds
+        // cached in registers across rounds) for the first round that has a
+        // survivor; rounds before it are wholly pruned.
         int64_t scan = pos, re = -1;
         while (scan < N) {
-            const int64_t p = scan + lane;
-            const int st = p < N ? stage_of(a, qo + p, thr) : 4;
+            const int64_t c0 = scan & ~(int64_t)(WAVE - 1);
+            const int64_t p = c0 + lane;
+            if (c0 != cached) {
+                cached = c0;
+                if (p < N) {
+                    ck = a.sk[qo + p];
+                    cbk = a.slbk[qo + p];
+                    cbb = a.slbeb[qo + p];
+                    cbe = a.slbe[qo + p];
+                }
+            }
+            const int st = (p >= scan && p < N) ? stage_of(a.cascade, cbk, cbb, cbe, thr) : 4;
             const unsigned long long sm = __ballot(st == 0);
             int64_t lim;
             if (re < 0) {
                 if (sm == 0ull) {
-                    lim = scan + WAVE;
+                    lim = c0 + WAVE;
                 } else {
-                    const int64_t f = scan + __ffsll((long long)sm) - 1;
+                    const int64_t f = c0 + __ffsll((long long)sm) - 1;
                     const int64_t rs = (f / a.R) * a.R;
                     re = (rs + a.R) < N ? (rs + a.R) : N;
-                    lim = re < scan + WAVE ? re : scan + WAVE;
+                    lim = re < c0 + WAVE ? re : c0 + WAVE;
                 }
             } else {
-                lim = re < scan + WAVE ? re : scan + WAVE;
+                lim = re < c0 + WAVE ? re : c0 + WAVE;
             }
-            const bool use = p < lim;
+            const bool use = st != 4 && p < lim;
             if (use) {
                 c_pk += st == 1;
                 c_peb += st == 2;
                 c_pe += st == 3;
             }
             const unsigned long long em = __ballot(use && st == 0);
-            if (use && st == 0) {
-                ring[(qt + __popcll(em & lt_mask)) % QCAP] = a.sk[qo + p];
-                ++c_st;
-            }
+            if (w0 && use && st == 0) ring[(qt + __popcll(em & lt_mask)) % QCAP] = ck;
+            c_st += use && st == 0;
             qt += __popcll(em);
             __syncthreads();
-            while (qt - qh >= P) run_pass(P);
-            scan += WAVE;
+            while (qt - qh >= SLOTS) run_batch(SLOTS);
+            scan = c0 + WAVE;
             if (re >= 0 && scan >= re) break;
         }
         if (re < 0) break;     // every remaining candidate was pruned
-        while (qt > qh) run_pass((qt - qh) < P ? (qt - qh) : P);
+        while (qt > qh) run_batch((qt - qh) < SLOTS ? (qt - qh) : SLOTS);
         if (rk >= 0 && lexless(rb, rk, bsf, bk)) { bsf = rb; bk = rk; }
         pos = re;
     }
 
+    if (!w0) return;
     c_pk = wave_sum(c_pk);
     c_peb = wave_sum(c_peb);
     c_pe = wave_sum(c_pe);
@@ -351,10 +375,10 @@ __global__ void __launch_bounds__(WAVE) search_kernel(SearchArgs a)
     }
 }
 
-static size_t search_lds(const EngineGeom &g, int P, int PD)
+static size_t search_lds(const EngineGeom &g, int SLOTS, int PD)
 {
-    return (size_t)g.LEN * 8 * (1 + PD) + (size_t)PD * 8 + (size_t)g.LEN * 4 * (1 + P) + (size_t)P * 4 +
-           (size_t)(P + PD) * 4 + QCAP * 4 + 64 * 8 + 64;
+    return (size_t)g.LEN * 8 * (1 + PD) + (size_t)PD * 8 + (size_t)g.LEN * 4 * (1 + SLOTS) +
+           (size_t)SLOTS * 8 + (size_t)PD * 4 + QCAP * 4 + 64 * 4 + 64 + 16;
 }
 
 int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan)
@@ -368,23 +392,33 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     if (C < 0) return fail(o->cpl > 0 ? NNDTW_EINVAL : NNDTW_EUNSUP,
                            "no DTW engine shape for W=%d (cpl=%d)", rs->W, o->cpl);
     EngineGeom g = make_geom(L, rs->W, C);
-    int P = g.P;
-    int PD = P < 4 ? P : 4;
-    while (P > 1 && search_lds(g, P, PD < P ? PD : P) > 64 * 1024) --P;
-    if (PD > P) PD = P;
-    const size_t lds = search_lds(g, P, PD);
+    const int P = g.P;
+    const int NW = o->waves > 0 ? o->waves : SEARCH_MAX_WAVES;
+    // Default round: two candidates per group, so that groups whose
+    // candidate is abandoned early take another one within the round.
+    const int64_t R = o->R > 0 ? o->R : 2 * P * NW;
+    // Rows staged per FP32 batch: the round (up to 64), at least one per
+    // group, within about 80 KB of LDS so that two queries share a CU.
+    int PD = P < 2 ? P : 2;
+    int SLOTS = (int)(R < 64 ? R : 64);
+    if (SLOTS < P) SLOTS = P;
+    while (SLOTS > P && search_lds(g, SLOTS, PD) > 80 * 1024) --SLOTS;
+    while (SLOTS > 1 && search_lds(g, SLOTS, PD) > 160 * 1024) --SLOTS;
+    const size_t lds = search_lds(g, SLOTS, PD);
     if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the search", L);
     plan->Wp = Wp;
     plan->C = C;
     plan->G = g.G;
     plan->P = P;
+    plan->PD = PD;
+    plan->SLOTS = SLOTS;
+    plan->NW = NW;
     plan->exact = g.exact;
     plan->T = g.T;
     plan->LEN = g.LEN;
-    plan->R = o->R > 0 ? o->R : P;
+    plan->R = R;
     plan->eps = o->eps > 0 ? o->eps : 2.0 * (double)(2 * L + 2) * 0x1p-24;
     plan->lds_bytes = lds;
-    (void)PD;
     return NNDTW_OK;
 }
 
@@ -428,8 +462,8 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
 
     SearchArgs a;
     a.geo = make_geom(L, rs->W, plan.C);
-    a.geo.P = plan.P;
-    a.PD = plan.P < 4 ? plan.P : 4;
+    a.PD = plan.PD;
+    a.SLOTS = plan.SLOTS;
     a.B = rs->B;
     a.n = n;
     a.Q = Qy;
@@ -446,14 +480,14 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     a.nn_idx = nn_idx;
     a.nn_dist = nn_dist;
     a.counts = counts;
-    const size_t lds = search_lds(a.geo, a.geo.P, a.PD);
+    const size_t lds = plan.lds_bytes;
     switch (plan.C) {
 #define X(c)                                                                                       \
     case c:                                                                                        \
         if (plan.exact)                                                                            \
-            hipLaunchKernelGGL((search_kernel<c, true>), dim3((unsigned)nQ), dim3(WAVE), lds, st, a); \
+            hipLaunchKernelGGL((search_kernel<c, true>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a); \
         else                                                                                       \
-            hipLaunchKernelGGL((search_kernel<c, false>), dim3((unsigned)nQ), dim3(WAVE), lds, st, a); \
+            hipLaunchKernelGGL((search_kernel<c, false>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a); \
         break;
         NNDTW_FOR_EACH_CPL(X)
 #undef X

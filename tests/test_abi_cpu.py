@@ -45,7 +45,7 @@ def test_struct_layouts():
     assert nd._Refset.B.offset == 32
     assert ctypes.sizeof(nd._SearchOpts) == 64
     assert nd._SearchOpts.eps.offset == 16 and nd._SearchOpts.events.offset == 32
-    assert nd._SearchOpts.reserved.offset == 40
+    assert nd._SearchOpts.waves.offset == 40 and nd._SearchOpts.reserved.offset == 48
 
 
 def _err(status, fragment):
