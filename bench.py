@@ -58,6 +58,31 @@ class Hip:
         return float(f.value)
 
 
+def source_fingerprint():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1808_09617_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None if the HIP sources changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"memory_counters_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    fp, val = None, None
+    for line in open(path):
+        if line.startswith("# source fingerprint:"):
+            fp = line.split(":", 1)[1].strip()
+        if line.startswith("# bytes_per_launch ") and line.split()[2] == kernel:
+            val = int(line.split()[3])
+    return val if fp == source_fingerprint() else None
+
+
 def cpu_baseline(wl, W, V, target_s):
     import numpy as np
     import oracle
@@ -87,6 +112,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the per-query arm and tightness")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after timing, one plain device copy of this many MiB (memory-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py measures one GPU only (the search shards with no exchange; see DESIGN.md); "
@@ -152,12 +179,14 @@ def main():
         t = st_avg["search"] / 1e3
         ach = cells_ops / t
         roof = {"kernel": "search_kernel", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "Tops/s", "frac": ach / VALU_PEAK_OPS, "traffic": None}
+                "unit": "Tops/s", "frac": ach / VALU_PEAK_OPS,
+                "traffic": profiled_traffic("search_kernel", "nndtw-sin256")}
     else:
         t = st_avg["bounds"] / 1e3
         ach = bounds_ops / t
         roof = {"kernel": "cascade_bounds_kernel", "bound": "alu", "achieved": ach / 1e12,
-                "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s", "frac": ach / VALU_PEAK_OPS, "traffic": None}
+                "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s", "frac": ach / VALU_PEAK_OPS,
+                "traffic": profiled_traffic("cascade_bounds_kernel", "nndtw-sin256")}
     bytes_bounds = 12.0 * N * L * math.ceil(Q / 8) + 32.0 * Q * N
     res = {
         "metric": METRIC, "value": Q / (ms_step / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": K,
@@ -202,6 +231,14 @@ def main():
             tight[f"enhanced{v}"] = float((nd.lb_enhanced(A, B, U, Lo, W, v, zip_=True)[keep] / d[keep]).mean())
         res["tightness"] = tight
         log("extras done")
+
+    if args.calib_copy_mb:
+        src = torch.ones(args.calib_copy_mb * 2 ** 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = src.numel() * 4
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(wl, W, V, args.cpu_seconds)
