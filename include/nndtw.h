@@ -171,10 +171,16 @@ typedef struct nndtw_refset {
     float   *Bt;         /* float[L][pitch]  point-major copies              */
     float   *Ut;
     float   *Lt;
+    float   *Bp;         /* float[n][ppitch] the series inside a margin of
+                          * 1e30 on both sides (rows the DTW engine streams) */
+    int64_t  ppitch;     /* row pitch of Bp (elements)                       */
+    int32_t  padl;       /* margin before the first value of a Bp row        */
+    int32_t  reserved1;
 } nndtw_refset;
 
-/* Device bytes needed for a reference set of n series of length L. */
-int nndtw_refset_bytes(int64_t n, int32_t L, size_t *bytes);
+/* Device bytes needed for a reference set of n series of length L built
+ * for window W. */
+int nndtw_refset_bytes(int64_t n, int32_t L, int32_t W, size_t *bytes);
 /* Copy B (device float[n][L]) into mem and build its envelopes and
  * point-major copies for window W.  n >= 1.  EINVAL if bytes is too small. */
 int nndtw_refset_build(const float *B, int64_t n, int32_t L, int32_t W, void *mem,

@@ -38,7 +38,9 @@ class _Refset(ctypes.Structure):
     _fields_ = [("magic", ctypes.c_uint32), ("L", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("W", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("pitch", ctypes.c_int64),
                 ("B", ctypes.c_void_p), ("U", ctypes.c_void_p), ("Lo", ctypes.c_void_p),
-                ("Bt", ctypes.c_void_p), ("Ut", ctypes.c_void_p), ("Lt", ctypes.c_void_p)]
+                ("Bt", ctypes.c_void_p), ("Ut", ctypes.c_void_p), ("Lt", ctypes.c_void_p),
+                ("Bp", ctypes.c_void_p), ("ppitch", ctypes.c_int64), ("padl", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32)]
 
 
 class _SearchOpts(ctypes.Structure):
@@ -59,7 +61,7 @@ SIGNATURES = {
     "nndtw_lb_enhanced": (ctypes.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "nndtw_dtw_w": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _I32, _P, _P]),
     "nndtw_dtw_w_f64": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _I32, _P, _P]),
-    "nndtw_refset_bytes": (ctypes.c_int, [_I64, _I32, ctypes.POINTER(_SZ)]),
+    "nndtw_refset_bytes": (ctypes.c_int, [_I64, _I32, _I32, ctypes.POINTER(_SZ)]),
     "nndtw_refset_build": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _SZ, ctypes.POINTER(_Refset), _P]),
     "nndtw_search_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(_Refset), _I64,
                                                     ctypes.POINTER(_SearchOpts), ctypes.POINTER(_SZ)]),
@@ -180,7 +182,7 @@ class RefSet:
         B = _series(B, "B")
         n, L = B.shape
         nbytes = ctypes.c_size_t(0)
-        _check(lib().nndtw_refset_bytes(n, L, ctypes.byref(nbytes)))
+        _check(lib().nndtw_refset_bytes(n, L, int(W), ctypes.byref(nbytes)))
         self.mem = torch.empty(int(nbytes.value), dtype=torch.uint8, device=B.device)
         self.desc = _Refset()
         _check(lib().nndtw_refset_build(_ptr(B), n, L, int(W), _ptr(self.mem), nbytes.value,

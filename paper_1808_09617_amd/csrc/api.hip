@@ -173,27 +173,37 @@ int nndtw_dtw_w_f64(const float *A, int64_t nA, const float *B, int64_t nB, int3
 }
 
 // ----------------------------------------------------------- reference sets
-static size_t refset_layout(int64_t n, int L, int64_t *pitch, size_t off[6])
+struct RefsetLayout {
+    int64_t pitch, ppitch;
+    int padl;
+    size_t off[7], total;
+};
+
+static RefsetLayout refset_layout(int64_t n, int L, int W)
 {
-    const int64_t p = (n + 63) / 64 * 64;
+    RefsetLayout r;
+    const int Wp = W < L - 1 ? W : L - 1;
+    r.pitch = (n + 63) / 64 * 64;
+    r.padl = padded_row_margin_left(Wp);
+    r.ppitch = ((int64_t)r.padl + L + padded_row_margin_right(Wp) + 63) / 64 * 64;
     const size_t rowb = (size_t)n * L * sizeof(float);
-    const size_t colb = (size_t)L * p * sizeof(float);
+    const size_t colb = (size_t)L * r.pitch * sizeof(float);
     size_t o = 0;
-    for (int i = 0; i < 3; ++i) { off[i] = o; o = al256(o + rowb); }
-    for (int i = 3; i < 6; ++i) { off[i] = o; o = al256(o + colb); }
-    *pitch = p;
-    return o;
+    for (int i = 0; i < 3; ++i) { r.off[i] = o; o = al256(o + rowb); }
+    for (int i = 3; i < 6; ++i) { r.off[i] = o; o = al256(o + colb); }
+    r.off[6] = o;
+    o = al256(o + (size_t)n * r.ppitch * sizeof(float));
+    r.total = o;
+    return r;
 }
 
-int nndtw_refset_bytes(int64_t n, int32_t L, size_t *bytes)
+int nndtw_refset_bytes(int64_t n, int32_t L, int32_t W, size_t *bytes)
 {
     g_err[0] = 0;
-    TRY(check_len_w(L, 0));
+    TRY(check_len_w(L, W));
     REQUIRE(n >= 1, "n=%lld: a reference set needs at least one series", (long long)n);
     REQUIRE(bytes != nullptr, "bytes is NULL");
-    int64_t pitch;
-    size_t off[6];
-    *bytes = refset_layout(n, L, &pitch, off);
+    *bytes = refset_layout(n, L, W).total;
     return NNDTW_OK;
 }
 
@@ -206,9 +216,10 @@ int nndtw_refset_build(const float *B, int64_t n, int32_t L, int32_t W, void *me
     TRY(check_ptr(B, 4, "B", true));
     TRY(check_ptr(mem, 256, "mem", true));
     REQUIRE(out != nullptr, "out is NULL");
-    int64_t pitch;
-    size_t off[6];
-    const size_t need = refset_layout(n, L, &pitch, off);
+    const RefsetLayout lay = refset_layout(n, L, W);
+    const size_t need = lay.total;
+    const int64_t pitch = lay.pitch;
+    const size_t *off = lay.off;
     REQUIRE(bytes >= need, "refset memory too small: %zu bytes given, %zu needed", bytes, need);
     hipStream_t st = (hipStream_t)stream;
     unsigned char *m = (unsigned char *)mem;
@@ -224,10 +235,14 @@ int nndtw_refset_build(const float *B, int64_t n, int32_t L, int32_t W, void *me
     r.Bt = (float *)(m + off[3]);
     r.Ut = (float *)(m + off[4]);
     r.Lt = (float *)(m + off[5]);
+    r.Bp = (float *)(m + off[6]);
+    r.ppitch = lay.ppitch;
+    r.padl = lay.padl;
     hipError_t e = hipMemcpyAsync(r.B, B, (size_t)n * L * sizeof(float), hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "refset copy");
     TRY(launch_envelopes(r.B, n, L, W, r.U, r.Lo, st));
     TRY(launch_transpose3(r.B, r.U, r.Lo, n, L, pitch, r.Bt, r.Ut, r.Lt, st));
+    TRY(launch_pad_rows(r.B, n, L, r.padl, r.ppitch, r.Bp, st));
     r.magic = NNDTW_REFSET_MAGIC;
     *out = r;
     return NNDTW_OK;

@@ -29,10 +29,17 @@ constexpr int WAVE = 64;
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------- launchers
+// Margins of the padded rows of a reference set (elements): wide enough for
+// the DTW engine at every supported shape (C <= 16 pairs per lane, prefetch
+// distance <= 8).
+inline int padded_row_margin_left(int Wp) { return (Wp + 48 + 3) / 4 * 4; }
+inline int padded_row_margin_right(int Wp) { return Wp / 2 + 40; }
+
 // envelopes.hip
 int launch_envelopes(const float *B, int64_t n, int L, int W, float *U, float *Lo, hipStream_t s);
 int launch_transpose3(const float *B, const float *U, const float *Lo, int64_t n, int L,
                       int64_t pitch, float *Bt, float *Ut, float *Lt, hipStream_t s);
+int launch_pad_rows(const float *B, int64_t n, int L, int padl, int64_t ppitch, float *Bp, hipStream_t s);
 // bounds.hip
 int launch_pair_bounds(int what, const float *A, int64_t nA, const float *B, const float *U,
                        const float *Lo, int64_t nB, int L, int W, int V, const double *cutoff,
@@ -55,20 +62,26 @@ int launch_search(const nndtw_refset *rs, const float *Q, int64_t nQ, const nndt
                   const SearchPlan &plan, int64_t *nn_idx, double *nn_dist, int64_t *counts,
                   void *ws, hipStream_t s);
 
-// LDS prefetch distance (super-steps) of the DTW engine for C diagonal pairs
-// per lane: enough super-steps to cover the LDS read latency.
-__host__ __device__ constexpr int prefetch_of(int C) { return C == 1 ? 4 : (C <= 6 ? 2 : 1); }
+// Prefetch distance (super-steps) of the DTW engine for C diagonal pairs per
+// lane, enough to cover the read latency: when a row is read from LDS ...
+__host__ __device__ constexpr int prefetch_lds(int C) { return C == 1 ? 4 : (C <= 6 ? 2 : 1); }
+// ... and when it is streamed from global memory (L2 latency).
+__host__ __device__ constexpr int prefetch_global(int C)
+{
+    return C == 1 ? 8 : (C <= 3 ? 6 : (C <= 4 ? 4 : (C <= 6 ? 3 : (C <= 12 ? 2 : 1))));
+}
 
 // Engine geometry shared by the DTW kernels (see dtw_engine.hpp).
 struct EngineGeom {
     int L, Wp, C, G, P, exact;
-    int T;      // super-steps (multiple of C + prefetch_of(C))
+    int D;      // prefetch distance (super-steps)
+    int T;      // super-steps (multiple of C + D)
     int base0;  // series index of the first super-step's base
     int LEN;    // elements per staged series in LDS (with padding)
 };
 // Choose the diagonal-pairs-per-lane C for a window (cmax bounds latency).
 int choose_cpl(int Wp, int cmax, int prefer, int chard = 16);
-EngineGeom make_geom(int L, int W, int C);
+EngineGeom make_geom(int L, int W, int C, int D);
 bool cpl_supported(int C);
 
 }  // namespace nndtw

@@ -51,7 +51,7 @@ int choose_cpl(int Wp, int cmax, int prefer, int chard)
     return best;
 }
 
-EngineGeom make_geom(int L, int W, int C)
+EngineGeom make_geom(int L, int W, int C, int D)
 {
     EngineGeom g;
     g.L = L;
@@ -60,12 +60,13 @@ EngineGeom make_geom(int L, int W, int C)
     g.G = (int)ceil_div(g.Wp + 1, C);
     g.exact = g.G * C == g.Wp + 1;
     g.P = 63 / g.G;
-    const int M = C + prefetch_of(C);
+    g.D = D;
+    const int M = C + D;
     const int T0 = L + (g.Wp + 2) / 2;
     const int epad = (M - T0 % M) % M;
     g.T = T0 + epad;
     g.base0 = -g.Wp - 1 - epad;
-    g.LEN = g.T + g.Wp + 2 * C + prefetch_of(C) + 2;
+    g.LEN = g.T + g.Wp + 2 * C + D + 2;
     return g;
 }
 
@@ -92,7 +93,7 @@ dtw_pairs_kernel(EngineGeom geo, int NB, const float *__restrict__ A, int64_t nA
                          lane);
         if (lane == 0) *next_task = 0;
         __syncthreads();
-        engine_run<T, C, EXACT>(
+        engine_run<T, C, prefetch_lds(C), EXACT>(
             geo, nt, next_task, [&](int i) { return (const T *)(aR + (size_t)i * LEN); },
             [&](int i) { return (const T *)(bR + (size_t)i * LEN); },
             [&](int i) -> T {
@@ -122,7 +123,7 @@ static int launch_pairs_t(const float *A, int64_t nA, const float *B, int64_t nB
     const int Wp = W < L - 1 ? W : L - 1;
     const int C = choose_cpl(Wp, 16, 0);
     if (C < 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
-    EngineGeom g = make_geom(L, W, C);
+    EngineGeom g = make_geom(L, W, C, prefetch_lds(C));
     // Tasks staged per batch: two per group so that groups refill, within
     // 64 KB of LDS (at least one).
     int NB = 2 * g.P < 64 ? 2 * g.P : 64;

@@ -102,12 +102,8 @@ template <> __device__ __forceinline__ double inf_of<double>() { return __builti
 template <int C> struct Stage { static constexpr int PADL = C; };
 
 // Window registers of a lane: C+1 values are in use at a super-step and the
-// LDS reads for super-step t+D are issued at the end of super-step t, so the
+// reads for super-step t+D are issued at the end of super-step t, so the
 // windows hold M = C + D values and rotate with period M.
-template <int C> struct Win {
-    static constexpr int D = prefetch_of(C);
-    static constexpr int M = C + D;
-};
 
 // Stage series `src` (float[L], global) into LDS row `dst` of geo.LEN
 // elements with PAD outside [0, L).  Whole-wave cooperative.
@@ -172,11 +168,11 @@ template <typename T> struct TaskOut {
 // boundaries are multiples of M in every group, which keeps the register
 // rotation of the windows the same in all groups.  Whole-wave call with
 // uniform arguments; ntasks >= 1.
-template <typename T, int C, bool EXACT, typename ARow, typename BRow, typename Thr>
+template <typename T, int C, int D, bool EXACT, typename ARow, typename BRow, typename Thr>
 __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, int *next_task, ARow arow, BRow brow,
                                            Thr thr_of, TaskOut<T> out)
 {
-    constexpr int D = Win<C>::D, M = Win<C>::M;
+    constexpr int M = C + D;
     const int lane = threadIdx.x & (WAVE - 1);
     const int G = geo.G, Wp = geo.Wp, T_ = geo.T;
     const int gi = lane >= 1 ? (lane - 1) / G : 0;

@@ -110,4 +110,25 @@ int launch_transpose3(const float *B, const float *U, const float *Lo, int64_t n
     return NNDTW_OK;
 }
 
+// Padded rows: Bp[k][padl + j] = B[k][j], 1e30 in the margins.
+__global__ void __launch_bounds__(256)
+pad_rows_kernel(const float *__restrict__ B, int64_t n, int L, int padl, int64_t ppitch, float *__restrict__ Bp)
+{
+    const int64_t total = n * ppitch;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t k = e / ppitch;
+        const int64_t j = e - k * ppitch - padl;
+        Bp[e] = (j >= 0 && j < L) ? B[k * L + j] : Pad<float>::big();
+    }
+}
+
+int launch_pad_rows(const float *B, int64_t n, int L, int padl, int64_t ppitch, float *Bp, hipStream_t st)
+{
+    int64_t blocks = ceil_div(n * ppitch, 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(pad_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, B, n, L, padl, ppitch, Bp);
+    NNDTW_LAUNCH_CHECK("pad rows kernel launch");
+    return NNDTW_OK;
+}
+
 }  // namespace nndtw

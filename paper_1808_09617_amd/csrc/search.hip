@@ -144,10 +144,14 @@ order_kernel(int64_t n, int npow, const double *__restrict__ ed2, const double *
 
 // ------------------------------------------------------------ search
 struct SearchArgs {
-    EngineGeom geo;
+    EngineGeom geo;    // FP32 engine (rows streamed from global memory)
+    EngineGeom geoD;   // FP64 recheck engine (rows staged in LDS)
     int PD;        // staged rows of the FP64 recheck
-    int SLOTS;     // staged candidate rows per FP32 batch (<= 64)
+    int SLOTS;     // candidates per FP32 batch (<= 64)
     const float *B;
+    const float *Bp;   // padded rows of the reference set
+    int64_t ppitch;
+    int padl;
     int64_t n;
     const float *Q;
     const uint32_t *sk;
@@ -194,14 +198,14 @@ template <int C, bool EXACT>
 __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const EngineGeom &geo = a.geo;
-    const int LEN = geo.LEN, PD = a.PD, SLOTS = a.SLOTS;
+    const EngineGeom &geo = a.geo, &geoD = a.geoD;
+    const int LEN = geo.LEN, LEND = geoD.LEN, PD = a.PD, SLOTS = a.SLOTS;
+    constexpr int DG = prefetch_global(C), DL = prefetch_lds(C);
     double *aD = reinterpret_cast<double *>(smem);
-    double *bD = aD + LEN;
-    double *resD = bD + (size_t)PD * LEN;
+    double *bD = aD + LEND;
+    double *resD = bD + (size_t)PD * LEND;
     float *aF = reinterpret_cast<float *>(resD + PD);
-    float *bF = aF + LEN;
-    float *resF = bF + (size_t)SLOTS * LEN;
+    float *resF = aF + LEN;
     int *trunF = reinterpret_cast<int *>(resF + SLOTS);
     int *trunD = trunF + SLOTS;
     uint32_t *ring = reinterpret_cast<uint32_t *>(trunD + PD);
@@ -216,11 +220,14 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
     const int L = geo.L;
     const float *Bs = a.B;
     const int64_t qo = q * N;
+    // A candidate's FP32 row is read straight from the padded copy: element e
+    // of the row the engine sees is series index base0 - PADL + e.
+    const float *Bp = a.Bp + (a.padl + geo.base0 - Stage<C>::PADL);
     const double INF = __builtin_inf();
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
     stage_rows<float, C>(aF, a.Q, [&](int) { return q; }, 1, geo, tid, nthr);
-    stage_rows<double, C>(aD, a.Q, [&](int) { return q; }, 1, geo, tid, nthr);
+    stage_rows<double, C>(aD, a.Q, [&](int) { return q; }, 1, geoD, tid, nthr);
     __syncthreads();
 
     const double ub = a.init_ub ? a.ed2[qo + a.sk[qo]] : INF;
@@ -240,17 +247,16 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
         double rb = INF;
         int64_t rk = -1;
 
-        // Run up to SLOTS queued survivors through the FP32 engine (their
-        // rows staged once; groups refill as candidates end), then recompute
-        // in FP64 the completed results that can decide the round.
+        // Run up to SLOTS queued survivors through the FP32 engine (groups
+        // refill as candidates end), then recompute in FP64 the completed
+        // results that can decide the round.
         auto run_batch = [&](int nt) {
             const int h0 = qh;
-            stage_rows<float, C>(bF, Bs, [&](int i) { return ring[(h0 + i) % QCAP]; }, nt, geo, tid, nthr);
             if (tid == 0) *next_task = 0;
             __syncthreads();
-            engine_run<float, C, EXACT>(
+            engine_run<float, C, DG, EXACT>(
                 geo, nt, next_task, [&](int) { return (const float *)aF; },
-                [&](int i) { return (const float *)(bF + (size_t)i * LEN); }, [&](int) { return thrF; },
+                [&](int i) { return Bp + (int64_t)ring[(h0 + i) % QCAP] * a.ppitch; }, [&](int) { return thrF; },
                 TaskOut<float>{resF, trunF});
             __syncthreads();
             float d32 = __builtin_inff();
@@ -280,12 +286,12 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
             for (int b0 = 0; b0 < nq; b0 += PD) {
                 const int nd = (nq - b0) < PD ? (nq - b0) : PD;
                 __syncthreads();
-                stage_rows<double, C>(bD, Bs, [&](int i) { return rq[b0 + i]; }, nd, geo, tid, nthr);
+                stage_rows<double, C>(bD, Bs, [&](int i) { return rq[b0 + i]; }, nd, geoD, tid, nthr);
                 if (tid == 0) *next_task = 0;
                 __syncthreads();
-                engine_run<double, C, EXACT>(
-                    geo, nd, next_task, [&](int) { return (const double *)aD; },
-                    [&](int i) { return (const double *)(bD + (size_t)i * LEN); }, [&](int) { return thr; },
+                engine_run<double, C, DL, EXACT>(
+                    geoD, nd, next_task, [&](int) { return (const double *)aD; },
+                    [&](int i) { return (const double *)(bD + (size_t)i * LEND); }, [&](int) { return thr; },
                     TaskOut<double>{resD, trunD});
                 __syncthreads();
                 for (int i = 0; i < nd; ++i) {
@@ -375,10 +381,10 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
     }
 }
 
-static size_t search_lds(const EngineGeom &g, int SLOTS, int PD)
+static size_t search_lds(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD)
 {
-    return (size_t)g.LEN * 8 * (1 + PD) + (size_t)PD * 8 + (size_t)g.LEN * 4 * (1 + SLOTS) +
-           (size_t)SLOTS * 8 + (size_t)PD * 4 + QCAP * 4 + 64 * 4 + 64 + 16;
+    return (size_t)gd.LEN * 8 * (1 + PD) + (size_t)PD * 8 + (size_t)g.LEN * 4 + (size_t)SLOTS * 8 +
+           (size_t)PD * 4 + QCAP * 4 + 64 * 4 + 64 + 16;
 }
 
 int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan)
@@ -391,21 +397,23 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     const int C = choose_cpl(Wp, 4, o->cpl, 12);
     if (C < 0) return fail(o->cpl > 0 ? NNDTW_EINVAL : NNDTW_EUNSUP,
                            "no DTW engine shape for W=%d (cpl=%d)", rs->W, o->cpl);
-    EngineGeom g = make_geom(L, rs->W, C);
+    EngineGeom g = make_geom(L, rs->W, C, prefetch_global(C));
+    const EngineGeom gd = make_geom(L, rs->W, C, prefetch_lds(C));
     const int P = g.P;
     const int NW = o->waves > 0 ? o->waves : SEARCH_MAX_WAVES;
     // Default round: two candidates per group, so that groups whose
     // candidate is abandoned early take another one within the round.
     const int64_t R = o->R > 0 ? o->R : 2 * P * NW;
-    // Rows staged per FP32 batch: the round (up to 64), at least one per
-    // group, within about 80 KB of LDS so that two queries share a CU.
-    int PD = P < 2 ? P : 2;
-    int SLOTS = (int)(R < 64 ? R : 64);
-    if (SLOTS < P) SLOTS = P;
-    while (SLOTS > P && search_lds(g, SLOTS, PD) > 80 * 1024) --SLOTS;
-    while (SLOTS > 1 && search_lds(g, SLOTS, PD) > 160 * 1024) --SLOTS;
-    const size_t lds = search_lds(g, SLOTS, PD);
+    // Candidates per FP32 batch: the round, up to 64 (one bookkeeping lane
+    // each).  Only the query row and the FP64 recheck rows live in LDS.
+    const int PD = P < 2 ? P : 2;
+    const int SLOTS = 64;
+    const size_t lds = search_lds(g, gd, SLOTS, PD);
     if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the search", L);
+    // the engine reads padded rows [base0 - PADL, base0 - PADL + LEN) of Bp
+    const int64_t boff = rs->padl + g.base0 - C;
+    if (boff < 0 || boff + g.LEN > rs->ppitch)
+        return fail(NNDTW_EUNSUP, "reference set margins too narrow for the DTW engine shape");
     plan->Wp = Wp;
     plan->C = C;
     plan->G = g.G;
@@ -461,10 +469,14 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     if ((r = mark(3))) return r;
 
     SearchArgs a;
-    a.geo = make_geom(L, rs->W, plan.C);
+    a.geo = make_geom(L, rs->W, plan.C, prefetch_global(plan.C));
+    a.geoD = make_geom(L, rs->W, plan.C, prefetch_lds(plan.C));
     a.PD = plan.PD;
     a.SLOTS = plan.SLOTS;
     a.B = rs->B;
+    a.Bp = rs->Bp;
+    a.ppitch = rs->ppitch;
+    a.padl = rs->padl;
     a.n = n;
     a.Q = Qy;
     a.sk = sk;

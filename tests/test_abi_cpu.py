@@ -41,7 +41,7 @@ def test_version_and_status_strings():
 
 
 def test_struct_layouts():
-    assert ctypes.sizeof(nd._Refset) == 80
+    assert ctypes.sizeof(nd._Refset) == 104
     assert nd._Refset.B.offset == 32
     assert ctypes.sizeof(nd._SearchOpts) == 64
     assert nd._SearchOpts.eps.offset == 16 and nd._SearchOpts.events.offset == 32
@@ -85,10 +85,11 @@ def test_pairwise_validation():
 def test_refset_and_search_validation():
     lib = nd.lib()
     nbytes = ctypes.c_size_t(0)
-    assert lib.nndtw_refset_bytes(100, 64, ctypes.byref(nbytes)) == 0
-    assert nbytes.value >= 6 * 100 * 64 * 4
-    assert _err(lib.nndtw_refset_bytes(0, 64, ctypes.byref(nbytes)), "at least one series") == nd.EINVAL
+    assert lib.nndtw_refset_bytes(100, 64, 6, ctypes.byref(nbytes)) == 0
+    assert nbytes.value >= 7 * 100 * 64 * 4
+    assert _err(lib.nndtw_refset_bytes(0, 64, 6, ctypes.byref(nbytes)), "at least one series") == nd.EINVAL
     desc = nd._Refset()
+    assert lib.nndtw_refset_bytes(100, 64, 3, ctypes.byref(nbytes)) == 0
     assert _err(lib.nndtw_refset_build(FAKE, 100, 64, 3, FAKE, nbytes.value - 1, ctypes.byref(desc), NULL),
                 "too small") == nd.EINVAL
     assert _err(lib.nndtw_refset_build(FAKE, 100, 64, 3, ctypes.c_void_p(0x100010), nbytes.value,
