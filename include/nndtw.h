@@ -55,6 +55,8 @@ extern "C" {
 /* Largest reference-set size nndtw_search accepts (its visiting order is
  * sorted in on-chip memory). */
 #define NNDTW_SEARCH_MAX_N 8192
+/* Largest number of waves (workgroup of 64-lane waves) one query may use. */
+#define NNDTW_SEARCH_MAX_WAVES 8
 
 /* Lower-bound cascades for nndtw_search. */
 #define NNDTW_CASCADE_NONE      0  /* DTW_W of every candidate (with abandon)        */
@@ -215,7 +217,7 @@ typedef struct nndtw_search_opts {
                           * stream before the bound pass, after it, after the
                           * cells table, after the ordering and after the search
                           * kernel; NULL records nothing                              */
-    int32_t waves;    /* waves per query (1..4); 0 = default; on return: the value used */
+    int32_t waves;    /* waves per query (1..NNDTW_SEARCH_MAX_WAVES); 0 = default; out */
     int32_t reserved32;
     int64_t reserved[2];
 } nndtw_search_opts;

@@ -264,7 +264,8 @@ static int check_opts(const nndtw_search_opts *o)
     REQUIRE(o->cascade >= NNDTW_CASCADE_NONE && o->cascade <= NNDTW_CASCADE_ENH, "cascade=%d unknown", o->cascade);
     REQUIRE(o->R >= 0, "R=%lld must be >= 0", (long long)o->R);
     REQUIRE(o->cpl >= 0, "cpl=%d must be >= 0", o->cpl);
-    REQUIRE(o->waves >= 0 && o->waves <= 4, "waves=%d must be in 0..4", o->waves);
+    REQUIRE(o->waves >= 0 && o->waves <= NNDTW_SEARCH_MAX_WAVES, "waves=%d must be in 0..%d", o->waves,
+            NNDTW_SEARCH_MAX_WAVES);
     return NNDTW_OK;
 }
 

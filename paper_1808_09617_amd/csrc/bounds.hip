@@ -144,21 +144,47 @@ cascade_bounds_kernel(const float *__restrict__ Bt, const float *__restrict__ Ut
             qa[i][t] = (i < cn && t < nq) ? (double)Q[(q0 + t) * L + c0 + i] : 0.0;
         }
         __syncthreads();
-        for (int ii = 0; ii < cn; ++ii) {
-            const int i = c0 + ii;
-            const double b = (double)Bt[(int64_t)i * pitch + kk];
-            const double u = (double)Ut[(int64_t)i * pitch + kk];
-            const double lo = (double)Lt[(int64_t)i * pitch + kk];
-            const bool mid = i >= nb && i < L - nb;
+        // Middle points [nb, L - nb) also add their Keogh term to LB_Enhanced:
+        // en = fma(kt, m, en) with m = 1 there rounds exactly like en + kt,
+        // and with m = 0 leaves en unchanged, so the loop needs no branch.
+        auto point = [&](int x, double b, double u, double lo) {
+            const int i = c0 + x;
+            const double m = (i >= nb && i < L - nb) ? 1.0 : 0.0;
 #pragma unroll
             for (int t = 0; t < TQ; ++t) {
-                const double a = qa[ii][t];
+                const double a = qa[x][t];
                 const double d = a - b;
                 e[t] += d * d;
                 const double kt = keogh_term(a, u, lo);
                 kg[t] += kt;
-                if (mid) en[t] += kt;
+                en[t] = __builtin_fma(kt, m, en[t]);
             }
+        };
+        // The reference values of point x + PF are loaded while point x is
+        // processed (a ring of PF registers per array); loads past the chunk
+        // re-read its last point, so every address stays in bounds.
+        constexpr int PF = 8;
+        float rb[PF], ru[PF], rl[PF];
+        auto fetch = [&](int x, int r) {
+            const int64_t o = (int64_t)(c0 + (x < cn ? x : cn - 1)) * pitch + kk;
+            rb[r] = Bt[o];
+            ru[r] = Ut[o];
+            rl[r] = Lt[o];
+        };
+        const int cfull = cn - cn % PF;
+#pragma unroll
+        for (int r = 0; r < PF; ++r) fetch(r, r);
+        for (int x0 = 0; x0 < cfull; x0 += PF) {
+#pragma unroll
+            for (int r = 0; r < PF; ++r) {
+                const double b = (double)rb[r], u = (double)ru[r], lo = (double)rl[r];
+                fetch(x0 + r + PF, r);
+                point(x0 + r, b, u, lo);
+            }
+        }
+        for (int x = cfull; x < cn; ++x) {
+            const int64_t o = (int64_t)(c0 + x) * pitch + kk;
+            point(x, (double)Bt[o], (double)Ut[o], (double)Lt[o]);
         }
     }
     if (!live) return;
@@ -178,7 +204,7 @@ int launch_cascade_bounds(const nndtw_refset *rs, const float *Q, int64_t nQ, in
                           double *lbk, double *lbeb, double *lbe, hipStream_t st)
 {
     if (nQ == 0 || rs->n == 0) return NNDTW_OK;
-    constexpr int TQ = 8;
+    constexpr int TQ = 4;
     const int L = rs->L;
     const int nb = V < L / 2 ? V : L / 2;
     dim3 grid((unsigned)ceil_div(rs->n, CB_THREADS), (unsigned)ceil_div(nQ, TQ));

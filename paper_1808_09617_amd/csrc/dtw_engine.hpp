@@ -155,6 +155,12 @@ __device__ __forceinline__ void stage_rows(T *dst, const float *__restrict__ src
 template <typename T> struct TaskOut {
     T *res;     // DTW_W, or +inf if abandoned
     int *trun;  // super-steps executed
+    // Optional shared abandon threshold (FP32 engine only): the bits of a
+    // non-negative float in LDS.  A task that completes with result r lowers
+    // it to round_up(r * slack), and every task abandons against
+    // min(its own threshold, that value).
+    unsigned *run_thr = nullptr;
+    double slack = 1.0;
 };
 
 // Run `ntasks` DTW tasks on the P groups of each calling wave.  Tasks are
@@ -217,6 +223,10 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
                     if (m == m0) r = (Wp & 1) ? X1[m] : X0[m];
                 out.res[task] = dead ? INF : r;
                 out.trun[task] = dead ? tl : T_;
+                if constexpr (sizeof(T) == 4) {
+                    if (out.run_thr != nullptr && !dead)
+                        atomicMin(out.run_thr, __float_as_uint(round_up_f32((double)r * out.slack)));
+                }
             }
             task = -1;
             tl = 0;
@@ -290,7 +300,13 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
         T lm = vmin(X0[0], X1[0]);
 #pragma unroll
         for (int m = 1; m < C; ++m) lm = min3(lm, X0[m], X1[m]);
-        const unsigned long long ok = __ballot(lm <= thr);
+        T thr_now = thr;
+        if constexpr (sizeof(T) == 4) {
+            if (out.run_thr != nullptr)
+                thr_now = __builtin_fminf(thr, __uint_as_float(__hip_atomic_load(
+                                                   out.run_thr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)));
+        }
+        const unsigned long long ok = __ballot(lm <= thr_now);
         if (task >= 0 && ((ok >> lane0) & gmask) == 0ull) dead = true;
     }
 }

@@ -37,7 +37,8 @@ namespace nndtw {
 #define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(9) X(12)
 
 constexpr int QCAP = 128;        // survivor ring (>= 64 + max staged rows)
-constexpr int SEARCH_MAX_WAVES = 4;
+constexpr int SEARCH_MAX_WAVES = NNDTW_SEARCH_MAX_WAVES;
+constexpr int SEARCH_DEFAULT_WAVES = 4;
 constexpr int ORDER_THREADS = 256;
 
 // ------------------------------------------------------------ workspace
@@ -211,6 +212,7 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
     uint32_t *ring = reinterpret_cast<uint32_t *>(trunD + PD);
     uint32_t *rq = ring + QCAP;      // qualifying candidates of a batch
     int *next_task = reinterpret_cast<int *>(rq + 64);
+    unsigned *run_thr = reinterpret_cast<unsigned *>(next_task + 1);
 
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (WAVE - 1);
@@ -228,6 +230,10 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
 
     stage_rows<float, C>(aF, a.Q, [&](int) { return q; }, 1, geo, tid, nthr);
     stage_rows<double, C>(aD, a.Q, [&](int) { return q; }, 1, geoD, tid, nthr);
+    // Smallest completed FP32 result so far, widened by the FP32 error slack
+    // (see the recheck rule below): a DTW whose frontier exceeds it cannot tie
+    // or beat that result, so it is abandoned.  Pruning still uses thr.
+    if (tid == 0) *run_thr = __float_as_uint(__builtin_inff());
     __syncthreads();
 
     const double ub = a.init_ub ? a.ed2[qo + a.sk[qo]] : INF;
@@ -257,7 +263,7 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
             engine_run<float, C, DG, EXACT>(
                 geo, nt, next_task, [&](int) { return (const float *)aF; },
                 [&](int i) { return Bp + (int64_t)ring[(h0 + i) % QCAP] * a.ppitch; }, [&](int) { return thrF; },
-                TaskOut<float>{resF, trunF});
+                TaskOut<float>{resF, trunF, run_thr, 1.0 + 2.0 * a.eps});
             __syncthreads();
             float d32 = __builtin_inff();
             uint32_t kg = 0;
@@ -400,7 +406,7 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     EngineGeom g = make_geom(L, rs->W, C, prefetch_global(C));
     const EngineGeom gd = make_geom(L, rs->W, C, prefetch_lds(C));
     const int P = g.P;
-    const int NW = o->waves > 0 ? o->waves : SEARCH_MAX_WAVES;
+    const int NW = o->waves > 0 ? o->waves : SEARCH_DEFAULT_WAVES;
     // Default round: two candidates per group, so that groups whose
     // candidate is abandoned early take another one within the round.
     const int64_t R = o->R > 0 ? o->R : 2 * P * NW;

@@ -31,6 +31,17 @@ def test_library_exports_every_declared_function():
     assert set(names) == set(nd.SIGNATURES), "binding signatures out of sync with the header"
 
 
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(NNDTW_\w+)\s+(\S+)", text))
+    assert int(defs["NNDTW_MAX_L"]) == nd.MAX_L
+    assert int(defs["NNDTW_SEARCH_MAX_N"]) == nd.SEARCH_MAX_N
+    assert int(defs["NNDTW_SEARCH_MAX_WAVES"]) == nd.SEARCH_MAX_WAVES
+    for name, v in nd.CASCADES.items():
+        assert int(defs["NNDTW_CASCADE_" + name.upper()]) == v
+    assert int(defs["NNDTW_NCOUNTS"]) == len(nd.COUNT_NAMES)
+
+
 def test_version_and_status_strings():
     lib = nd.lib()
     assert lib.nndtw_version() == 1

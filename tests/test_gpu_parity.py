@@ -179,15 +179,16 @@ def test_dtw_tightness_pairs_zip():
 
 
 # ------------------------------------------------------------------ search
-def run_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0):
+def run_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, waves=0):
     rs = nd.RefSet(dev(refs), W)
-    idx, dist, counts, R_used = nd.search(rs, dev(queries), V=V, cascade=cascade, R=R, init_ub=init_ub, cpl=cpl)
+    idx, dist, counts, R_used = nd.search(rs, dev(queries), V=V, cascade=cascade, R=R, init_ub=init_ub, cpl=cpl,
+                                          waves=waves)
     return host(idx), host(dist), host(counts), R_used
 
 
-def check_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, brute=True):
-    say("search", refs.shape, queries.shape, W, V, cascade, R, init_ub, cpl)
-    gi, gd, gc, R_used = run_search(refs, queries, W, V, cascade, R, init_ub, cpl)
+def check_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, brute=True, waves=0):
+    say("search", refs.shape, queries.shape, W, V, cascade, R, init_ub, cpl, waves)
+    gi, gd, gc, R_used = run_search(refs, queries, W, V, cascade, R, init_ub, cpl, waves)
     oi, od, oc = oracle.search(refs, queries, W, V, cascade, R_used, init_ub)
     assert np.array_equal(gi, oi), ("nn_idx", np.nonzero(gi != oi))
     assert np.array_equal(gd, od), ("nn_dist", np.max(np.abs(gd - od)))
@@ -253,6 +254,17 @@ def test_search_sin256_subset():
     for V in (1, 2, 5):
         check_search(wl.refs, wl.queries, 26, V, "keogh_enh", 0, True, 0, brute=False)
     check_search(wl.refs, wl.queries[:20], 26, 5, "keogh", 0, True, 0, brute=False)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 3, 5, 8])
+def test_search_waves_per_query(waves):
+    """Every workgroup size gives the oracle's result and counts (the waves of
+    a query share its DTW tasks)."""
+    wl = synth.workload("nndtw-sin256", n_refs=1000, n_queries=40)
+    for R in (0, 1, 37, 300):
+        check_search(wl.refs, wl.queries, 26, 5, "keogh_enh", R, True, 0, brute=False, waves=waves)
+    refs = series(90, 64, seed=31)
+    check_search(refs, series(5, 64, seed=32), 12, 2, "keogh_enh", 0, True, 1, waves=waves)
 
 
 @pytest.mark.parametrize("W", [5, 51, 128,
