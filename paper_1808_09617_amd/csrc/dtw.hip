@@ -51,7 +51,7 @@ int choose_cpl(int Wp, int cmax, int prefer, int chard)
     return best;
 }
 
-EngineGeom make_geom(int L, int W, int C, int D)
+EngineGeom make_geom(int L, int W, int C, int D, int M)
 {
     EngineGeom g;
     g.L = L;
@@ -61,7 +61,7 @@ EngineGeom make_geom(int L, int W, int C, int D)
     g.exact = g.G * C == g.Wp + 1;
     g.P = 63 / g.G;
     g.D = D;
-    const int M = C + D;
+    g.M = M;
     const int T0 = L + (g.Wp + 2) / 2;
     const int epad = (M - T0 % M) % M;
     g.T = T0 + epad;
@@ -93,7 +93,7 @@ dtw_pairs_kernel(EngineGeom geo, int NB, const float *__restrict__ A, int64_t nA
                          lane);
         if (lane == 0) *next_task = 0;
         __syncthreads();
-        engine_run<T, C, prefetch_lds(C), EXACT>(
+        engine_run<T, C, prefetch_lds(C), window_lds(C), EXACT>(
             geo, nt, next_task, [&](int i) { return (const T *)(aR + (size_t)i * LEN); },
             [&](int i) { return (const T *)(bR + (size_t)i * LEN); },
             [&](int i) -> T {
@@ -123,7 +123,7 @@ static int launch_pairs_t(const float *A, int64_t nA, const float *B, int64_t nB
     const int Wp = W < L - 1 ? W : L - 1;
     const int C = choose_cpl(Wp, 16, 0);
     if (C < 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
-    EngineGeom g = make_geom(L, W, C, prefetch_lds(C));
+    EngineGeom g = make_geom(L, W, C, prefetch_lds(C), window_lds(C));
     // Tasks staged per batch: two per group so that groups refill, within
     // 64 KB of LDS (at least one).
     int NB = 2 * g.P < 64 ? 2 * g.P : 64;

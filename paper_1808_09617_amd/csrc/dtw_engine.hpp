@@ -174,11 +174,11 @@ template <typename T> struct TaskOut {
 // boundaries are multiples of M in every group, which keeps the register
 // rotation of the windows the same in all groups.  Whole-wave call with
 // uniform arguments; ntasks >= 1.
-template <typename T, int C, int D, bool EXACT, typename ARow, typename BRow, typename Thr>
+template <typename T, int C, int D, int M, bool EXACT, typename ARow, typename BRow, typename Thr>
 __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, int *next_task, ARow arow, BRow brow,
                                            Thr thr_of, TaskOut<T> out)
 {
-    constexpr int M = C + D;
+    static_assert(M >= C + D, "window smaller than the live values");
     const int lane = threadIdx.x & (WAVE - 1);
     const int G = geo.G, Wp = geo.Wp, T_ = geo.T;
     const int gi = lane >= 1 ? (lane - 1) / G : 0;

@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
     extern __shared__ __align__(16) unsigned char smem[];
     const EngineGeom &geo = a.geo, &geoD = a.geoD;
     const int LEN = geo.LEN, LEND = geoD.LEN, PD = a.PD, SLOTS = a.SLOTS;
-    constexpr int DG = prefetch_global(C), DL = prefetch_lds(C);
+    constexpr int DG = prefetch_global(C), DL = prefetch_lds(C), MG = window_global(C), ML = window_lds(C);
     double *aD = reinterpret_cast<double *>(smem);
     double *bD = aD + LEND;
     double *resD = bD + (size_t)PD * LEND;
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
             const int h0 = qh;
             if (tid == 0) *next_task = 0;
             __syncthreads();
-            engine_run<float, C, DG, EXACT>(
+            engine_run<float, C, DG, MG, EXACT>(
                 geo, nt, next_task, [&](int) { return (const float *)aF; },
                 [&](int i) { return Bp + (int64_t)ring[(h0 + i) % QCAP] * a.ppitch; }, [&](int) { return thrF; },
                 TaskOut<float>{resF, trunF, run_thr, 1.0 + 2.0 * a.eps});
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
                 stage_rows<double, C>(bD, Bs, [&](int i) { return rq[b0 + i]; }, nd, geoD, tid, nthr);
                 if (tid == 0) *next_task = 0;
                 __syncthreads();
-                engine_run<double, C, DL, EXACT>(
+                engine_run<double, C, DL, ML, EXACT>(
                     geoD, nd, next_task, [&](int) { return (const double *)aD; },
                     [&](int i) { return (const double *)(bD + (size_t)i * LEND); }, [&](int) { return thr; },
                     TaskOut<double>{resD, trunD});
@@ -403,8 +403,8 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     const int C = choose_cpl(Wp, 4, o->cpl, 12);
     if (C < 0) return fail(o->cpl > 0 ? NNDTW_EINVAL : NNDTW_EUNSUP,
                            "no DTW engine shape for W=%d (cpl=%d)", rs->W, o->cpl);
-    EngineGeom g = make_geom(L, rs->W, C, prefetch_global(C));
-    const EngineGeom gd = make_geom(L, rs->W, C, prefetch_lds(C));
+    EngineGeom g = make_geom(L, rs->W, C, prefetch_global(C), window_global(C));
+    const EngineGeom gd = make_geom(L, rs->W, C, prefetch_lds(C), window_lds(C));
     const int P = g.P;
     const int NW = o->waves > 0 ? o->waves : SEARCH_DEFAULT_WAVES;
     // Default round: two candidates per group, so that groups whose
@@ -475,8 +475,8 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     if ((r = mark(3))) return r;
 
     SearchArgs a;
-    a.geo = make_geom(L, rs->W, plan.C, prefetch_global(plan.C));
-    a.geoD = make_geom(L, rs->W, plan.C, prefetch_lds(plan.C));
+    a.geo = make_geom(L, rs->W, plan.C, prefetch_global(plan.C), window_global(plan.C));
+    a.geoD = make_geom(L, rs->W, plan.C, prefetch_lds(plan.C), window_lds(plan.C));
     a.PD = plan.PD;
     a.SLOTS = plan.SLOTS;
     a.B = rs->B;
