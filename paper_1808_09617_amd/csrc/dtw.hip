@@ -62,10 +62,16 @@ EngineGeom make_geom(int L, int W, int C, int D, int M)
     g.P = 63 / g.G;
     g.D = D;
     g.M = M;
+    // The sweep starts at the first anti-diagonal pair outside the matrix
+    // and runs T0 super-steps to (L-1, L-1), plus up to M-1 super-steps that
+    // round T up to whole blocks.  Those run past the end: both series are
+    // padded there with the same value, so every later cell of diagonal 0
+    // keeps DTW_W exactly (a pad pair costs 0, a pad against a value costs
+    // +inf); a DTW that is abandoned never reaches them.
     const int T0 = L + (g.Wp + 2) / 2;
     const int epad = (M - T0 % M) % M;
     g.T = T0 + epad;
-    g.base0 = -g.Wp - 1 - epad;
+    g.base0 = -g.Wp - 1;
     g.LEN = g.T + g.Wp + 2 * C + D + 2;
     return g;
 }

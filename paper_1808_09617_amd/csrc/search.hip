@@ -100,47 +100,126 @@ __global__ void __launch_bounds__(1024) cells_prefix_kernel(int L, int Wp, uint3
 }
 
 // ------------------------------------------------------------ order
-// Bitonic sort of (ed2, index) ascending, one workgroup per query.
+// Bitonic sort of (ed2, index) ascending, one workgroup per query.  Thread t
+// holds the E consecutive positions t*E .. t*E+E-1 (npow = 256 * E), so a
+// compare-exchange at stride s pairs two of its own registers when s < E,
+// lanes t and t ^ (s / E) of one wave (a shuffle) when s < 64 E, and only
+// larger strides go through LDS with a barrier.  Keys are unique (indices
+// differ) except for the padding (+inf, 0xFFFFFFFF) entries.
+__device__ __forceinline__ bool key_gt(double ka, uint32_t ia, double kb, uint32_t ib)
+{
+    return ka > kb || (ka == kb && ia > ib);
+}
+
+// (k, x) becomes the min (want_min) or max of itself and (ko, xo).
+__device__ __forceinline__ void keep(double &k, uint32_t &x, double ko, uint32_t xo, bool want_min)
+{
+    const bool take = want_min ? key_gt(k, x, ko, xo) : key_gt(ko, xo, k, x);
+    k = take ? ko : k;
+    x = take ? xo : x;
+}
+
+template <int E>
 __global__ void __launch_bounds__(ORDER_THREADS)
-order_kernel(int64_t n, int npow, const double *__restrict__ ed2, const double *__restrict__ lbk,
+order_kernel(int64_t n, const double *__restrict__ ed2, const double *__restrict__ lbk,
              const double *__restrict__ lbeb, const double *__restrict__ lbe, uint32_t *__restrict__ sk,
              double *__restrict__ slbk, double *__restrict__ slbeb, double *__restrict__ slbe)
 {
+    constexpr int npow = ORDER_THREADS * E;
     extern __shared__ __align__(16) unsigned char smem[];
     double *key = reinterpret_cast<double *>(smem);
     uint32_t *idx = reinterpret_cast<uint32_t *>(key + npow);
     const int64_t q = blockIdx.x;
-    const double *e = ed2 + q * n;
-    for (int i = threadIdx.x; i < npow; i += ORDER_THREADS) {
-        key[i] = i < n ? e[i] : __builtin_inf();
-        idx[i] = i < n ? (uint32_t)i : 0xFFFFFFFFu;
+    const int t = threadIdx.x;
+    const double *e2 = ed2 + q * n;
+    double k[E];
+    uint32_t x[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int e = t * E + r;
+        k[r] = e < n ? e2[e] : __builtin_inf();
+        x[r] = e < n ? (uint32_t)e : 0xFFFFFFFFu;
     }
-    __syncthreads();
     for (int size = 2; size <= npow; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < npow / 2; t += ORDER_THREADS) {
-                const int lo = 2 * t - (t & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const double ka = key[lo], kb = key[hi];
-                const uint32_t ia = idx[lo], ib = idx[hi];
-                const bool a_gt_b = ka > kb || (ka == kb && ia > ib);
-                if (a_gt_b == up) {
-                    key[lo] = kb; key[hi] = ka;
-                    idx[lo] = ib; idx[hi] = ia;
-                }
+        int stride = size >> 1;
+        for (; stride >= WAVE * E; stride >>= 1) {        // across waves
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                key[t * E + r] = k[r];
+                idx[t * E + r] = x[r];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int e = t * E + r, p = e ^ stride;
+                keep(k[r], x[r], key[p], idx[p], ((e & stride) == 0) == ((e & size) == 0));
             }
             __syncthreads();
         }
+        for (; stride >= E; stride >>= 1) {               // across lanes
+            const int m = stride / E;
+            const bool lo = (t & m) == 0;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const double ko = __shfl_xor(k[r], m);
+                const uint32_t xo = (uint32_t)__shfl_xor((int)x[r], m);
+                keep(k[r], x[r], ko, xo, lo == (((t * E + r) & size) == 0));
+            }
+        }
+#pragma unroll
+        for (int s2 = E / 2; s2 >= 1; s2 >>= 1) {         // inside the thread
+            if (s2 > stride) continue;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                if (r & s2) continue;
+                const bool up = ((t * E + r) & size) == 0;
+                const double ka = k[r], kb = k[r | s2];
+                const uint32_t ia = x[r], ib = x[r | s2];
+                const bool sw = key_gt(ka, ia, kb, ib) == up;
+                k[r] = sw ? kb : ka;
+                x[r] = sw ? ib : ia;
+                k[r | s2] = sw ? ka : kb;
+                x[r | s2] = sw ? ia : ib;
+            }
+        }
     }
-    for (int i = threadIdx.x; i < n; i += ORDER_THREADS) {
-        const uint32_t k = idx[i];
+#pragma unroll
+    for (int r = 0; r < E; ++r) idx[t * E + r] = x[r];
+    __syncthreads();
+    for (int i = t; i < n; i += ORDER_THREADS) {
+        const uint32_t kk = idx[i];
         const int64_t o = q * n + i;
-        sk[o] = k;
-        slbk[o] = lbk[q * n + k];
-        slbeb[o] = lbeb[q * n + k];
-        slbe[o] = lbe[q * n + k];
+        sk[o] = kk;
+        slbk[o] = lbk[q * n + kk];
+        slbeb[o] = lbeb[q * n + kk];
+        slbe[o] = lbe[q * n + kk];
     }
+}
+
+static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *lbk, const double *lbeb,
+                        const double *lbe, uint32_t *sk, double *slbk, double *slbeb, double *slbe, hipStream_t st)
+{
+    int E = 1;
+    while ((int64_t)ORDER_THREADS * E < n) E <<= 1;
+    const size_t lds = (size_t)ORDER_THREADS * E * 12;
+#define NNDTW_ORDER_CASE(EE)                                                                              \
+    case EE:                                                                                             \
+        hipLaunchKernelGGL(order_kernel<EE>, dim3((unsigned)nQ), dim3(ORDER_THREADS), lds, st, n, ed2, lbk, \
+                           lbeb, lbe, sk, slbk, slbeb, slbe);                                            \
+        break;
+    switch (E) {
+        NNDTW_ORDER_CASE(1)
+        NNDTW_ORDER_CASE(2)
+        NNDTW_ORDER_CASE(4)
+        NNDTW_ORDER_CASE(8)
+        NNDTW_ORDER_CASE(16)
+        NNDTW_ORDER_CASE(32)
+    default:
+        return fail(NNDTW_EUNSUP, "order: %lld references exceed the supported maximum", (long long)n);
+    }
+#undef NNDTW_ORDER_CASE
+    NNDTW_LAUNCH_CHECK("order kernel launch");
+    return NNDTW_OK;
 }
 
 // ------------------------------------------------------------ search
@@ -466,12 +545,7 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     hipLaunchKernelGGL(cells_prefix_kernel, dim3(1), dim3(1024), 0, st, L, plan.Wp, prefix);
     NNDTW_LAUNCH_CHECK("cells prefix kernel launch");
     if ((r = mark(2))) return r;
-    int npow = 1;
-    while (npow < n) npow <<= 1;
-    const size_t olds = (size_t)npow * 12;
-    hipLaunchKernelGGL(order_kernel, dim3((unsigned)nQ), dim3(ORDER_THREADS), olds, st, n, npow, ed2, lbk,
-                       lbeb, lbe, sk, slbk, slbeb, slbe);
-    NNDTW_LAUNCH_CHECK("order kernel launch");
+    if ((r = launch_order(n, nQ, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, st))) return r;
     if ((r = mark(3))) return r;
 
     SearchArgs a;

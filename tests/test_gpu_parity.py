@@ -256,6 +256,15 @@ def test_search_sin256_subset():
     check_search(wl.refs, wl.queries[:20], 26, 5, "keogh", 0, True, 0, brute=False)
 
 
+@pytest.mark.parametrize("n", [1, 63, 256, 257, 300, 1024, 1025, 2049, 4096, 4100, 8192])
+def test_search_reference_counts(n):
+    """Reference-set sizes around every power of two the visiting-order sort
+    handles (1 to 32 positions per thread), against the oracle."""
+    refs = series(n, 24, seed=900 + n % 97, kind="sin5")
+    queries = series(5, 24, seed=901, kind="sin5")
+    check_search(refs, queries, 3, 2, "keogh_enh", 0, True, 0, brute=n <= 2049)
+
+
 @pytest.mark.parametrize("waves", [1, 2, 3, 5, 8])
 def test_search_waves_per_query(waves):
     """Every workgroup size gives the oracle's result and counts (the waves of
