@@ -100,6 +100,46 @@ def cpu_baseline(wl, W, V, target_s):
                       f"sequential search (R=1), LB_Keogh->LB_Enhanced^{V}, FP64, {dt:.1f} s wall"}
 
 
+def hbm_streaming(nd, synth, torch, dev):
+    """Bandwidth of the streaming kernels on a reference set far larger than
+    the 256 MB MALL (200,000 x 512, mix, W=51, V=5): the envelope pass and the
+    fused bound pass at 1 and 64 queries.  Algorithmic bytes: envelopes read B
+    and write U, Lo (12 B per element); the bound pass streams the point-major
+    B, U, Lo once per tile of 4 queries (12 B per reference point per tile),
+    reads the queries and writes four float64 values per (query, reference)."""
+    hb = synth.workload("nndtw-hbm512")
+    W, V = hb.windows[0], 5
+    n, L = hb.refs.shape
+    B = torch.from_numpy(hb.refs).to(dev)
+    Qall = torch.from_numpy(hb.queries).to(dev)
+    rs = nd.RefSet(B, W)
+
+    def timed(fn, reps=5):
+        fn()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        return sorted(times)[len(times) // 2]
+
+    out = {"workload": "nndtw-hbm512", "N": n, "L": L, "W": W, "V": V, "resident_refset_bytes": int(rs.mem.numel())}
+    t = timed(lambda: nd.envelopes(B, W))
+    out["envelopes"] = {"ms": t * 1e3, "gbps": 12.0 * n * L / t / 1e9}
+    for nq in (1, 64):
+        Qs = Qall[:nq].contiguous()
+        t = timed(lambda: nd.cascade_bounds(rs, Qs, V))
+        tiles = -(-nq // 4)
+        byts = 12.0 * n * L * tiles + 4.0 * nq * L + 32.0 * nq * n
+        out[f"bounds_q{nq}"] = {"ms": t * 1e3, "gbps": byts / t / 1e9, "fp64_gops": 10.0 * nq * n * L / t / 1e9}
+    del rs, B
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +270,7 @@ def main():
         for v in (1, 2, 5):
             tight[f"enhanced{v}"] = float((nd.lb_enhanced(A, B, U, Lo, W, v, zip_=True)[keep] / d[keep]).mean())
         res["tightness"] = tight
+        res["hbm_streaming"] = hbm_streaming(nd, synth, torch, dev)
         log("extras done")
 
     if args.calib_copy_mb:
