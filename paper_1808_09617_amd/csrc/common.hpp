@@ -77,6 +77,11 @@ __host__ __device__ constexpr int prefetch_global(int C)
 // measured fastest: 3.76 VALU instructions per cell against 4.20 at M = 9).
 __host__ __device__ constexpr int window_lds(int C) { return C + prefetch_lds(C); }
 __host__ __device__ constexpr int window_global(int C) { return C == 3 ? 15 : C + prefetch_global(C); }
+// FP64 recheck of the search: float rows from the same places, short
+// prefetch and no spare slots (double windows cost two registers per value
+// and must not raise the kernel's register count above the FP32 engine's).
+__host__ __device__ constexpr int recheck_prefetch(int C) { return prefetch_lds(C); }
+__host__ __device__ constexpr int recheck_window(int C) { return C + recheck_prefetch(C); }
 
 // Engine geometry shared by the DTW kernels (see dtw_engine.hpp).
 struct EngineGeom {

@@ -165,8 +165,9 @@ template <typename T> struct TaskOut {
 
 // Run `ntasks` DTW tasks on the P groups of each calling wave.  Tasks are
 // dealt from the LDS counter *next_task (0 before the call, shared by every
-// wave of the workgroup that takes part).  Task i compares the
-// staged rows arow(i) and brow(i) (LDS, geo.LEN elements each) and is
+// wave of the workgroup that takes part).  Task i compares the rows arow(i)
+// and brow(i) (geo.LEN elements each, in LDS or global memory; elements of
+// any type that converts exactly to T, e.g. float rows for an FP64 sweep) and is
 // abandoned once its frontier exceeds thr_of(i).  A group takes the next
 // task as soon as its current one ends (completed or abandoned), at the next
 // block boundary (every M super-steps), so abandoned candidates free their
@@ -202,8 +203,8 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
         if (!EXACT) tm[m] = ((m == C - 1 && force_last) || (in_group && glc + m == Wp)) ? INF : (T)0;
 
     T X0[C], X1[C], Aw[M], Bw[M];
-    const T *aP = arow(0) + Stage<C>::PADL + glc;
-    const T *bP = brow(0) + Stage<C>::PADL + Wp - glc;
+    auto aP = arow(0) + Stage<C>::PADL + glc;
+    auto bP = brow(0) + Stage<C>::PADL + Wp - glc;
 #pragma unroll
     for (int m = 0; m < C; ++m) { X0[m] = (T)0; X1[m] = (T)0; }
 #pragma unroll
@@ -259,14 +260,14 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
                 // b-slot m is bP[t - m] in Bw[(t - m) mod M]: preload what
                 // super-steps 0..D-1 read.
 #pragma unroll
-                for (int r = 0; r < C + D; ++r) Aw[r % M] = aP[r];
+                for (int r = 0; r < C + D; ++r) Aw[r % M] = (T)aP[r];
 #pragma unroll
-                for (int r = 1 - C; r <= D - 1; ++r) Bw[((r % M) + M) % M] = bP[r];
+                for (int r = 1 - C; r <= D - 1; ++r) Bw[((r % M) + M) % M] = (T)bP[r];
             }
         }
         if (__ballot(task >= 0) == 0ull) break;
 
-        const T *aC = aP + tl, *bC = bP + tl;
+        const auto aC = aP + tl, bC = bP + tl;
 #pragma unroll
         for (int u = 0; u < M; ++u) {
             // bottom diagonals: anti-diagonal s_b(t)
@@ -292,8 +293,8 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
                 for (int m = 0; m < C; ++m) X1[m] = vmax(X1[m], tm[m]);
             }
             // windows for super-step t+D
-            Aw[(u + D + C) % M] = aC[u + D + C];
-            Bw[(u + D) % M] = bC[u + D];
+            Aw[(u + D + C) % M] = (T)aC[u + D + C];
+            Bw[(u + D) % M] = (T)bC[u + D];
         }
         if (task >= 0) tl += M;
         // early abandon on the frontier (two consecutive anti-diagonals)

@@ -225,8 +225,8 @@ static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *
 // ------------------------------------------------------------ search
 struct SearchArgs {
     EngineGeom geo;    // FP32 engine (rows streamed from global memory)
-    EngineGeom geoD;   // FP64 recheck engine (rows staged in LDS)
-    int PD;        // staged rows of the FP64 recheck
+    EngineGeom geoD;   // FP64 recheck engine (the same float rows, converted)
+    int PD;        // FP64 rechecks per engine call (<= 64)
     int SLOTS;     // candidates per FP32 batch (<= 64)
     const float *B;
     const float *Bp;   // padded rows of the reference set
@@ -279,13 +279,13 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const EngineGeom &geo = a.geo, &geoD = a.geoD;
-    const int LEN = geo.LEN, LEND = geoD.LEN, PD = a.PD, SLOTS = a.SLOTS;
-    constexpr int DG = prefetch_global(C), DL = prefetch_lds(C), MG = window_global(C), ML = window_lds(C);
-    double *aD = reinterpret_cast<double *>(smem);
-    double *bD = aD + LEND;
-    double *resD = bD + (size_t)PD * LEND;
-    float *aF = reinterpret_cast<float *>(resD + PD);
-    float *resF = aF + LEN;
+    const int PD = a.PD, SLOTS = a.SLOTS;
+    // the query row serves both engines: stage the longer of their rows
+    const int LENA = geo.LEN > geoD.LEN ? geo.LEN : geoD.LEN;
+    constexpr int DG = prefetch_global(C), MG = window_global(C), DD = recheck_prefetch(C), MD = recheck_window(C);
+    float *aF = reinterpret_cast<float *>(smem);
+    double *resD = reinterpret_cast<double *>(aF + ((LENA + 1) & ~1));
+    float *resF = reinterpret_cast<float *>(resD + PD);
     int *trunF = reinterpret_cast<int *>(resF + SLOTS);
     int *trunD = trunF + SLOTS;
     uint32_t *ring = reinterpret_cast<uint32_t *>(trunD + PD);
@@ -299,16 +299,19 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
     const int64_t q = blockIdx.x;
     const int64_t N = a.n;
     const int L = geo.L;
-    const float *Bs = a.B;
     const int64_t qo = q * N;
     // A candidate's FP32 row is read straight from the padded copy: element e
-    // of the row the engine sees is series index base0 - PADL + e.
+    // of the row the engines see is series index base0 - PADL + e (base0 is
+    // the same in both geometries).
     const float *Bp = a.Bp + (a.padl + geo.base0 - Stage<C>::PADL);
     const double INF = __builtin_inf();
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
-    stage_rows<float, C>(aF, a.Q, [&](int) { return q; }, 1, geo, tid, nthr);
-    stage_rows<double, C>(aD, a.Q, [&](int) { return q; }, 1, geoD, tid, nthr);
+    {
+        EngineGeom ga = geo;
+        ga.LEN = LENA;
+        stage_rows<float, C>(aF, a.Q, [&](int) { return q; }, 1, ga, tid, nthr);
+    }
     // Smallest completed FP32 result so far, widened by the FP32 error slack
     // (see the recheck rule below): a DTW whose frontier exceeds it cannot tie
     // or beat that result, so it is abandoned.  Pruning still uses thr.
@@ -368,15 +371,17 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
             const int nq = __popcll(qm);
             __syncthreads();                 // every wave has read the batch results
             if (w0 && qual) rq[__popcll(qm & lt_mask)] = kg;
+            // FP64 recheck: the same float rows, widened exactly at load (the
+            // pad 1e30 squares to 1e60 in FP64, still far above any path sum
+            // of finite inputs below 1e15, so every min and sum is unchanged)
             for (int b0 = 0; b0 < nq; b0 += PD) {
                 const int nd = (nq - b0) < PD ? (nq - b0) : PD;
                 __syncthreads();
-                stage_rows<double, C>(bD, Bs, [&](int i) { return rq[b0 + i]; }, nd, geoD, tid, nthr);
                 if (tid == 0) *next_task = 0;
                 __syncthreads();
-                engine_run<double, C, DL, ML, EXACT>(
-                    geoD, nd, next_task, [&](int) { return (const double *)aD; },
-                    [&](int i) { return (const double *)(bD + (size_t)i * LEND); }, [&](int) { return thr; },
+                engine_run<double, C, DD, MD, EXACT>(
+                    geoD, nd, next_task, [&](int) { return (const float *)aF; },
+                    [&](int i) { return Bp + (int64_t)rq[b0 + i] * a.ppitch; }, [&](int) { return thr; },
                     TaskOut<double>{resD, trunD});
                 __syncthreads();
                 for (int i = 0; i < nd; ++i) {
@@ -468,8 +473,8 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
 
 static size_t search_lds(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD)
 {
-    return (size_t)gd.LEN * 8 * (1 + PD) + (size_t)PD * 8 + (size_t)g.LEN * 4 + (size_t)SLOTS * 8 +
-           (size_t)PD * 4 + QCAP * 4 + 64 * 4 + 64 + 16;
+    const int LENA = g.LEN > gd.LEN ? g.LEN : gd.LEN;
+    return (size_t)((LENA + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 8 + QCAP * 4 + 64 * 4 + 16;
 }
 
 int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan)
@@ -483,21 +488,23 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     if (C < 0) return fail(o->cpl > 0 ? NNDTW_EINVAL : NNDTW_EUNSUP,
                            "no DTW engine shape for W=%d (cpl=%d)", rs->W, o->cpl);
     EngineGeom g = make_geom(L, rs->W, C, prefetch_global(C), window_global(C));
-    const EngineGeom gd = make_geom(L, rs->W, C, prefetch_lds(C), window_lds(C));
+    const EngineGeom gd = make_geom(L, rs->W, C, recheck_prefetch(C), recheck_window(C));
     const int P = g.P;
     const int NW = o->waves > 0 ? o->waves : SEARCH_DEFAULT_WAVES;
     // Default round: two candidates per group, so that groups whose
     // candidate is abandoned early take another one within the round.
     const int64_t R = o->R > 0 ? o->R : 2 * P * NW;
     // Candidates per FP32 batch: the round, up to 64 (one bookkeeping lane
-    // each).  Only the query row and the FP64 recheck rows live in LDS.
-    const int PD = P < 2 ? P : 2;
+    // each); all FP64 rechecks of a batch in one engine call.  Only the
+    // query row and bookkeeping live in LDS.
     const int SLOTS = 64;
+    const int PD = SLOTS;
     const size_t lds = search_lds(g, gd, SLOTS, PD);
     if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the search", L);
-    // the engine reads padded rows [base0 - PADL, base0 - PADL + LEN) of Bp
+    // the engines read padded rows [base0 - PADL, base0 - PADL + LEN) of Bp
     const int64_t boff = rs->padl + g.base0 - C;
-    if (boff < 0 || boff + g.LEN > rs->ppitch)
+    const int LENA = g.LEN > gd.LEN ? g.LEN : gd.LEN;
+    if (g.base0 != gd.base0 || boff < 0 || boff + LENA > rs->ppitch)
         return fail(NNDTW_EUNSUP, "reference set margins too narrow for the DTW engine shape");
     plan->Wp = Wp;
     plan->C = C;
@@ -550,7 +557,7 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
 
     SearchArgs a;
     a.geo = make_geom(L, rs->W, plan.C, prefetch_global(plan.C), window_global(plan.C));
-    a.geoD = make_geom(L, rs->W, plan.C, prefetch_lds(plan.C), window_lds(plan.C));
+    a.geoD = make_geom(L, rs->W, plan.C, recheck_prefetch(plan.C), recheck_window(plan.C));
     a.PD = plan.PD;
     a.SLOTS = plan.SLOTS;
     a.B = rs->B;
