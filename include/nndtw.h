@@ -243,6 +243,69 @@ int nndtw_cascade_bounds(const nndtw_refset *refset, const float *Q, int64_t nQ,
                          int32_t V, double *ed2, double *lbk, double *lbe_bands,
                          double *lbe, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched search over many independent reference sets of different lengths
+ * (the search of Sections 1 and 4, per set exactly as nndtw_search with the
+ * same options, R and shape): every set's bound pass runs in one kernel, its
+ * visiting-order sort in one kernel per sort width, and the (set, query)
+ * items in one persistent search kernel per engine shape that takes items
+ * from a device counter, largest expected work first.  After nndtw_batch_prepare, the
+ * launch nndtw_search_batch allocates, copies and synchronises nothing, so it
+ * can be captured in a HIP graph and replayed.
+ *
+ * Per set: results equal nndtw_search on the same set, queries and options
+ * with R and cpl as written back here (index, distance and the defined
+ * counts; the implementation-defined counts depend on which DTW of a round
+ * finishes first, in either call).  Sets may use
+ * 1 to 4 diagonal pairs per lane, i.e. min(W, L-1) + 1 <= 252; larger windows
+ * return EUNSUP. */
+typedef struct nndtw_batch_set {
+    const nndtw_refset *refset;  /* a built reference set (host descriptor)         */
+    const float *Q;              /* device float[nQ][refset->L]                      */
+    int64_t nQ;                  /* queries (>= 0)                                   */
+    int64_t *nn_idx;             /* device int64[nQ]                                 */
+    double *nn_dist;             /* device double[nQ]                                */
+    int64_t *counts;             /* device int64[nQ][NNDTW_NCOUNTS], or NULL          */
+    int64_t R;                   /* round size, 0 = default; on return: used         */
+    int32_t cpl;                 /* pairs per lane, 0 = default; on return: used     */
+    int32_t reserved;
+} nndtw_batch_set;
+
+/* Filled by nndtw_batch_prepare; passed unchanged to nndtw_search_batch. */
+typedef struct nndtw_batch_plan {
+    uint32_t magic;
+    int32_t nsets;
+    int64_t items;               /* (set, query) items                               */
+    int64_t tiles;               /* bound-pass tiles                                  */
+    int32_t waves;               /* waves per workgroup of the search kernel          */
+    int32_t grid;                /* persistent search workgroups                     */
+    int64_t lds;                 /* search kernel LDS bytes                          */
+    int64_t ws_bytes;            /* workspace bytes the plan uses                    */
+    int64_t order_off[6];        /* item-list offset and count per sort width        */
+    int64_t order_cnt[6];        /*   1, 2, 4, 8, 16, 32 positions per thread        */
+    int64_t search_off[8];       /* item-list offset and count per engine shape      */
+    int64_t search_cnt[8];       /*   (C, exact) = (1,0), (1,1), ..., (4,1)          */
+    int64_t reserved[4];
+} nndtw_batch_plan;
+
+/* Device workspace bytes for a batch (sets as passed to prepare). */
+int nndtw_batch_workspace_bytes(const nndtw_batch_set *sets, int32_t nsets,
+                                const nndtw_search_opts *opts, size_t *bytes);
+
+/* Plan a batch into ws (device, >= nndtw_batch_workspace_bytes) and *plan:
+ * validates every set, writes back each set's R and cpl, copies the set
+ * descriptors and item lists into ws and fills the per-set cells tables.
+ * Synchronous: returns after the copies on `stream` are complete.  Options
+ * (V, cascade, eps, init_ub, waves) are common to all sets; opts->R and
+ * opts->cpl are ignored (per set instead); opts->events must be NULL. */
+int nndtw_batch_prepare(nndtw_batch_set *sets, int32_t nsets, const nndtw_search_opts *opts,
+                        void *ws, size_t ws_bytes, nndtw_batch_plan *plan, void *stream);
+
+/* Run a prepared batch: 1 + (sort widths used) + (engine shapes used)
+ * kernels on `stream`.  The
+ * sets' reference sets, queries, outputs and ws must be those of prepare. */
+int nndtw_search_batch(const nndtw_batch_plan *plan, void *ws, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,20 @@ class _SearchOpts(ctypes.Structure):
                 ("reserved", ctypes.c_int64 * 2)]
 
 
+class _BatchSet(ctypes.Structure):
+    _fields_ = [("refset", ctypes.c_void_p), ("Q", ctypes.c_void_p), ("nQ", ctypes.c_int64),
+                ("nn_idx", ctypes.c_void_p), ("nn_dist", ctypes.c_void_p), ("counts", ctypes.c_void_p),
+                ("R", ctypes.c_int64), ("cpl", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _BatchPlan(ctypes.Structure):
+    _fields_ = [("magic", ctypes.c_uint32), ("nsets", ctypes.c_int32), ("items", ctypes.c_int64),
+                ("tiles", ctypes.c_int64), ("waves", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("lds", ctypes.c_int64), ("ws_bytes", ctypes.c_int64), ("order_off", ctypes.c_int64 * 6),
+                ("order_cnt", ctypes.c_int64 * 6), ("search_off", ctypes.c_int64 * 8),
+                ("search_cnt", ctypes.c_int64 * 8), ("reserved", ctypes.c_int64 * 4)]
+
+
 _P, _I32, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 SIGNATURES = {
     "nndtw_version": (ctypes.c_int, []),
@@ -69,6 +83,11 @@ SIGNATURES = {
     "nndtw_search": (ctypes.c_int, [ctypes.POINTER(_Refset), _P, _I64, ctypes.POINTER(_SearchOpts), _P, _P,
                                     _P, _P, _SZ, _P]),
     "nndtw_cascade_bounds": (ctypes.c_int, [ctypes.POINTER(_Refset), _P, _I64, _I32, _P, _P, _P, _P, _P]),
+    "nndtw_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(_BatchSet), _I32, ctypes.POINTER(_SearchOpts),
+                                                   ctypes.POINTER(_SZ)]),
+    "nndtw_batch_prepare": (ctypes.c_int, [ctypes.POINTER(_BatchSet), _I32, ctypes.POINTER(_SearchOpts), _P, _SZ,
+                                           ctypes.POINTER(_BatchPlan), _P]),
+    "nndtw_search_batch": (ctypes.c_int, [ctypes.POINTER(_BatchPlan), _P, _P]),
 }
 
 _lib = None
@@ -272,6 +291,55 @@ class Searcher:
     @property
     def waves(self):
         return int(self.opts.waves)
+
+
+class BatchSearcher:
+    """A prepared batched search over several reference sets (ragged lengths).
+
+    ``sets`` is a list of (RefSet, queries) pairs; ``R`` and ``cpl`` are None
+    (library defaults) or one value per set.  Calling the object runs the
+    whole batch on the current stream (no allocation or copy, so it can be
+    captured in a CUDA/HIP graph) and returns per set (nn_idx, nn_dist, counts).
+    Each set's result equals ``search`` on that set with the R and cpl
+    reported in ``self.R`` / ``self.cpl``."""
+
+    def __init__(self, sets, V: int = 5, cascade: str = "keogh_enh", R=None, cpl=None, eps: float = 0.0,
+                 init_ub: bool = True, waves: int = 0):
+        n = len(sets)
+        if n == 0:
+            raise ValueError("empty batch")
+        self.refsets = [rs for rs, _ in sets]
+        self.Qs = [_series(Q, "Q") for _, Q in sets]
+        dev = self.refsets[0].device
+        self.out = []
+        arr = (_BatchSet * n)()
+        for d, (rs, Q) in enumerate(zip(self.refsets, self.Qs)):
+            if Q.shape[1] != rs.L:
+                raise ValueError(f"set {d}: queries of length {Q.shape[1]} against a reference set of length {rs.L}")
+            nq = Q.shape[0]
+            o = (torch.empty(nq, dtype=torch.int64, device=dev), torch.empty(nq, dtype=torch.float64, device=dev),
+                 torch.empty((nq, 8), dtype=torch.int64, device=dev))
+            self.out.append(o)
+            b = arr[d]
+            b.refset = ctypes.addressof(rs.desc)
+            b.Q, b.nQ = _ptr(Q), nq
+            b.nn_idx, b.nn_dist, b.counts = _ptr(o[0]), _ptr(o[1]), _ptr(o[2])
+            b.R = 0 if R is None else int(R[d])
+            b.cpl = 0 if cpl is None else int(cpl[d])
+        self.sets = arr
+        self.opts = _opts(V, cascade, 0, eps, init_ub, 0, waves)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().nndtw_batch_workspace_bytes(arr, n, ctypes.byref(self.opts), ctypes.byref(nbytes)))
+        self.ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)
+        self.plan = _BatchPlan()
+        _check(lib().nndtw_batch_prepare(arr, n, ctypes.byref(self.opts), _ptr(self.ws), self.ws.numel(),
+                                         ctypes.byref(self.plan), _stream()))
+        self.R = [int(arr[d].R) for d in range(n)]
+        self.cpl = [int(arr[d].cpl) for d in range(n)]
+
+    def __call__(self):
+        _check(lib().nndtw_search_batch(ctypes.byref(self.plan), _ptr(self.ws), _stream()))
+        return self.out
 
 
 def search(refset: RefSet, Q: torch.Tensor, V: int = 5, cascade: str = "keogh_enh", R: int = 0,

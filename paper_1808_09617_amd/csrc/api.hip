@@ -1,6 +1,6 @@
 // extern "C" entry points of libnndtw: argument validation on the host, then
 // asynchronous launches on the caller's stream.  Nothing here allocates
-// device memory or synchronises.
+// device memory; only nndtw_batch_prepare waits (for its own copies).
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -321,6 +321,68 @@ int nndtw_cascade_bounds(const nndtw_refset *refset, const float *Q, int64_t nQ,
     if (lbe_bands) TRY(check_ptr(lbe_bands, 8, "lbe_bands", any));
     if (lbe) TRY(check_ptr(lbe, 8, "lbe", any));
     return launch_cascade_bounds(refset, Q, nQ, V, ed2, lbk, lbe_bands, lbe, (hipStream_t)stream);
+}
+
+// Prefix the current error text with the set it concerns.
+static int set_error(int status, int d)
+{
+    char tmp[sizeof g_err];
+    std::snprintf(tmp, sizeof tmp, "%s", g_err);
+    return fail(status, "set %d: %s", d, tmp);
+}
+
+static int check_batch(const nndtw_batch_set *sets, int32_t nsets, const nndtw_search_opts *opts, bool ptrs)
+{
+    REQUIRE(sets != nullptr, "sets is NULL");
+    REQUIRE(nsets >= 1, "nsets=%d must be >= 1", nsets);
+    TRY(check_opts(opts));
+    REQUIRE(opts->events == nullptr, "opts->events must be NULL for a batch");
+    for (int d = 0; d < nsets; ++d) {
+        const nndtw_batch_set &s = sets[d];
+        if (int r = check_refset(s.refset)) return set_error(r, d);
+        REQUIRE(s.nQ >= 0, "set %d: nQ=%lld must be >= 0", d, (long long)s.nQ);
+        REQUIRE(s.nQ <= 0xFFFFFFFFLL, "set %d: too many queries", d);
+        REQUIRE(s.R >= 0 && s.cpl >= 0, "set %d: R and cpl must be >= 0", d);
+        if (s.refset->n > NNDTW_SEARCH_MAX_N)
+            return fail(NNDTW_EUNSUP, "set %d: reference set of %lld series exceeds NNDTW_SEARCH_MAX_N=%d", d,
+                        (long long)s.refset->n, NNDTW_SEARCH_MAX_N);
+        if (!ptrs) continue;
+        const bool any = s.nQ > 0;
+        if (int r = check_ptr(s.Q, 4, "Q", any)) return set_error(r, d);
+        if (int r = check_ptr(s.nn_idx, 8, "nn_idx", any)) return set_error(r, d);
+        if (int r = check_ptr(s.nn_dist, 8, "nn_dist", any)) return set_error(r, d);
+        if (s.counts)
+            if (int r = check_ptr(s.counts, 8, "counts", any)) return set_error(r, d);
+    }
+    return NNDTW_OK;
+}
+
+int nndtw_batch_workspace_bytes(const nndtw_batch_set *sets, int32_t nsets, const nndtw_search_opts *opts,
+                                size_t *bytes)
+{
+    g_err[0] = 0;
+    TRY(check_batch(sets, nsets, opts, false));
+    REQUIRE(bytes != nullptr, "bytes is NULL");
+    *bytes = batch_ws_bytes(sets, nsets);
+    return NNDTW_OK;
+}
+
+int nndtw_batch_prepare(nndtw_batch_set *sets, int32_t nsets, const nndtw_search_opts *opts, void *ws,
+                        size_t ws_bytes, nndtw_batch_plan *plan, void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_batch(sets, nsets, opts, true));
+    REQUIRE(plan != nullptr, "plan is NULL");
+    TRY(check_ptr(ws, 256, "ws", true));
+    return batch_prepare(sets, nsets, opts, ws, ws_bytes, plan, (hipStream_t)stream);
+}
+
+int nndtw_search_batch(const nndtw_batch_plan *plan, void *ws, void *stream)
+{
+    g_err[0] = 0;
+    REQUIRE(plan != nullptr, "plan is NULL");
+    TRY(check_ptr(ws, 256, "ws", plan->items > 0));
+    return batch_launch(plan, ws, (hipStream_t)stream);
 }
 
 }  // extern "C"

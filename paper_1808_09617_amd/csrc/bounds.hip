@@ -104,17 +104,19 @@ int launch_pair_bounds(int what, const float *A, int64_t nA, const float *B, con
 constexpr int CB_THREADS = 256;
 constexpr int CB_CHUNK = 128;   // points of the query tile staged per pass
 
+// One tile: references rt*CB_THREADS .. +CB_THREADS-1 (one per thread)
+// against queries qt*TQ .. qt*TQ+TQ-1.  Whole-workgroup call.
 template <int TQ>
-__global__ void __launch_bounds__(CB_THREADS)
-cascade_bounds_kernel(const float *__restrict__ Bt, const float *__restrict__ Ut,
-                      const float *__restrict__ Lt, int64_t pitch, int64_t n,
-                      const float *__restrict__ Q, int64_t nQ, int L, int W, int nb,
-                      double *__restrict__ ed2, double *__restrict__ lbk,
-                      double *__restrict__ lbeb, double *__restrict__ lbe)
+__device__ __forceinline__ void bounds_tile(int64_t rt, int64_t qt, const float *__restrict__ Bt,
+                                            const float *__restrict__ Ut, const float *__restrict__ Lt,
+                                            int64_t pitch, int64_t n, const float *__restrict__ Q, int64_t nQ,
+                                            int L, int W, int nb, double *__restrict__ ed2,
+                                            double *__restrict__ lbk, double *__restrict__ lbeb,
+                                            double *__restrict__ lbe)
 {
     __shared__ double qa[CB_CHUNK][TQ];
-    const int64_t k = (int64_t)blockIdx.x * CB_THREADS + threadIdx.x;
-    const int64_t q0 = (int64_t)blockIdx.y * TQ;
+    const int64_t k = rt * CB_THREADS + threadIdx.x;
+    const int64_t q0 = qt * TQ;
     const bool live = k < n;
     const int64_t kk = live ? k : 0;
     const int nq = (int)((nQ - q0) < TQ ? (nQ - q0) : TQ);
@@ -198,6 +200,51 @@ cascade_bounds_kernel(const float *__restrict__ Bt, const float *__restrict__ Ut
             if (lbe) lbe[o] = en[t];
         }
     }
+}
+
+template <int TQ>
+__global__ void __launch_bounds__(CB_THREADS)
+cascade_bounds_kernel(const float *__restrict__ Bt, const float *__restrict__ Ut,
+                      const float *__restrict__ Lt, int64_t pitch, int64_t n,
+                      const float *__restrict__ Q, int64_t nQ, int L, int W, int nb,
+                      double *__restrict__ ed2, double *__restrict__ lbk,
+                      double *__restrict__ lbeb, double *__restrict__ lbe)
+{
+    bounds_tile<TQ>(blockIdx.x, blockIdx.y, Bt, Ut, Lt, pitch, n, Q, nQ, L, W, nb, ed2, lbk, lbeb, lbe);
+}
+
+// The bound pass of a batch: one workgroup per tile of any set; the set is
+// found by binary search over the tiles' start indices.  Also resets the
+// work counter of the batch's search kernel, which runs after it.
+template <int TQ>
+__global__ void __launch_bounds__(CB_THREADS)
+batch_bounds_kernel(const BatchSet *__restrict__ sets, int nsets, const int64_t *__restrict__ tile_start,
+                    BatchHdr *hdr)
+{
+    const int64_t tile = blockIdx.x;
+    if (tile == 0 && threadIdx.x < BATCH_SHAPES) hdr->counter[threadIdx.x] = 0u;
+    int lo = 0, hi = nsets - 1;                 // last set with tile_start <= tile
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    const int d = __builtin_amdgcn_readfirstlane(lo);
+    const BatchSet &b = sets[d];
+    const int64_t local = tile - tile_start[d];
+    bounds_tile<TQ>(local % b.nrt, local / b.nrt, b.Bt, b.Ut, b.Lt, b.pitch, b.a.n, b.a.Q, b.nQ, b.L, b.W,
+                    b.nb, b.ed2w, b.lbk, b.lbeb, b.lbe);
+}
+
+constexpr int BATCH_TQ = 4;
+
+int launch_batch_bounds(const BatchSet *sets, int nsets, const int64_t *tile_start, int64_t tiles, BatchHdr *hdr,
+                        hipStream_t st)
+{
+    if (tiles == 0) return NNDTW_OK;
+    hipLaunchKernelGGL(batch_bounds_kernel<BATCH_TQ>, dim3((unsigned)tiles), dim3(CB_THREADS), 0, st, sets, nsets,
+                       tile_start, hdr);
+    NNDTW_LAUNCH_CHECK("batch bound kernel launch");
+    return NNDTW_OK;
 }
 
 int launch_cascade_bounds(const nndtw_refset *rs, const float *Q, int64_t nQ, int V, double *ed2,

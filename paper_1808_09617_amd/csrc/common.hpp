@@ -46,6 +46,11 @@ int launch_pair_bounds(int what, const float *A, int64_t nA, const float *B, con
                        int pairing, double *out, hipStream_t s);
 int launch_cascade_bounds(const nndtw_refset *rs, const float *Q, int64_t nQ, int V,
                           double *ed2, double *lbk, double *lbeb, double *lbe, hipStream_t s);
+struct BatchSet;
+struct BatchHdr;
+struct EngineGeom;
+int launch_batch_bounds(const BatchSet *sets, int nsets, const int64_t *tile_start, int64_t tiles,
+                        BatchHdr *hdr, hipStream_t s);
 // dtw.hip
 int launch_dtw_pairs(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L,
                      int W, const double *cutoff, int pairing, void *out, hipStream_t s);
@@ -61,6 +66,21 @@ size_t search_ws_bytes(int64_t nQ, int64_t n, int L);
 int launch_search(const nndtw_refset *rs, const float *Q, int64_t nQ, const nndtw_search_opts *o,
                   const SearchPlan &plan, int64_t *nn_idx, double *nn_dist, int64_t *counts,
                   void *ws, hipStream_t s);
+struct WsLayout {
+    size_t ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, prefix, total;
+};
+WsLayout ws_layout(int64_t nQ, int64_t n, int L);
+int launch_cells_prefix(int L, int Wp, uint32_t *prefix, hipStream_t s);
+int order_width(int64_t n);     // positions per thread of the visiting-order sort
+int launch_batch_order(int E, const BatchSet *sets, const int64_t *items, int64_t nitems, hipStream_t s);
+int launch_batch_search(int C, bool exact, const BatchSet *sets, const int64_t *items, int64_t nitems,
+                        unsigned *counter, int waves, int grid, size_t lds, hipStream_t s);
+size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD);
+// batch.hip
+size_t batch_ws_bytes(const nndtw_batch_set *sets, int nsets);
+int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, void *ws, size_t ws_bytes,
+                  nndtw_batch_plan *plan, hipStream_t s);
+int batch_launch(const nndtw_batch_plan *plan, void *ws, hipStream_t s);
 
 // Prefetch distance (super-steps) of the DTW engine for C diagonal pairs per
 // lane, enough to cover the read latency: when a row is read from LDS ...
@@ -92,6 +112,49 @@ struct EngineGeom {
     int base0;  // series index of the first super-step's base
     int LEN;    // elements per staged series in LDS (with padding)
 };
+// Arguments of the per-query search (search.hip): one query against one
+// reference set, with the workspace of that set.
+struct SearchArgs {
+    EngineGeom geo;    // FP32 engine (rows streamed from global memory)
+    EngineGeom geoD;   // FP64 recheck engine (the same float rows, converted)
+    int PD;        // FP64 rechecks per engine call (<= 64)
+    int SLOTS;     // candidates per FP32 batch (<= 64)
+    const float *B;
+    const float *Bp;   // padded rows of the reference set
+    int64_t ppitch;
+    int padl;
+    int64_t n;
+    const float *Q;
+    const uint32_t *sk;
+    const double *slbk, *slbeb, *slbe, *ed2;
+    const uint32_t *prefix;
+    int cascade;
+    int64_t R;
+    double eps;
+    int init_ub;
+    int64_t *nn_idx;
+    double *nn_dist;
+    int64_t *counts;
+};
+
+// One reference set of a batched search: the search arguments plus what the
+// bound pass and the ordering of the batch need (batch.hip).
+struct BatchSet {
+    SearchArgs a;
+    int C, exact;               // engine shape of the set
+    const float *Bt, *Ut, *Lt;  // point-major copies of the reference set
+    int64_t pitch, nQ;
+    int L, W, nb;               // length, window, LB_Enhanced band count
+    int64_t nrt;                // reference tiles of the bound pass
+    double *ed2w, *lbk, *lbeb, *lbe;
+    uint32_t *skw;
+    double *slbkw, *slbebw, *slbew;
+};
+constexpr int BATCH_SHAPES = 8;  // engine shapes (C, EXACT), C = 1..4
+struct BatchHdr {
+    unsigned counter[BATCH_SHAPES];   // next search item per shape (reset by the bound pass)
+};
+
 // Choose the diagonal-pairs-per-lane C for a window (cmax bounds latency).
 int choose_cpl(int Wp, int cmax, int prefer, int chard = 16);
 EngineGeom make_geom(int L, int W, int C, int D, int M);

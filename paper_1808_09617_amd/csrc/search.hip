@@ -42,11 +42,8 @@ constexpr int SEARCH_DEFAULT_WAVES = 4;
 constexpr int ORDER_THREADS = 256;
 
 // ------------------------------------------------------------ workspace
-struct WsLayout {
-    size_t ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, prefix, total;
-};
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
-static WsLayout ws_layout(int64_t nQ, int64_t n, int L)
+WsLayout ws_layout(int64_t nQ, int64_t n, int L)
 {
     WsLayout w;
     const size_t m = (size_t)nQ * (size_t)n;
@@ -120,16 +117,15 @@ __device__ __forceinline__ void keep(double &k, uint32_t &x, double ko, uint32_t
 }
 
 template <int E>
-__global__ void __launch_bounds__(ORDER_THREADS)
-order_kernel(int64_t n, const double *__restrict__ ed2, const double *__restrict__ lbk,
-             const double *__restrict__ lbeb, const double *__restrict__ lbe, uint32_t *__restrict__ sk,
-             double *__restrict__ slbk, double *__restrict__ slbeb, double *__restrict__ slbe)
+__device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *__restrict__ ed2,
+                                            const double *__restrict__ lbk, const double *__restrict__ lbeb,
+                                            const double *__restrict__ lbe, uint32_t *__restrict__ sk,
+                                            double *__restrict__ slbk, double *__restrict__ slbeb,
+                                            double *__restrict__ slbe, unsigned char *smem)
 {
     constexpr int npow = ORDER_THREADS * E;
-    extern __shared__ __align__(16) unsigned char smem[];
     double *key = reinterpret_cast<double *>(smem);
     uint32_t *idx = reinterpret_cast<uint32_t *>(key + npow);
-    const int64_t q = blockIdx.x;
     const int t = threadIdx.x;
     const double *e2 = ed2 + q * n;
     double k[E];
@@ -196,11 +192,72 @@ order_kernel(int64_t n, const double *__restrict__ ed2, const double *__restrict
     }
 }
 
-static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *lbk, const double *lbeb,
-                        const double *lbe, uint32_t *sk, double *slbk, double *slbeb, double *slbe, hipStream_t st)
+template <int E>
+__global__ void __launch_bounds__(ORDER_THREADS)
+order_kernel(int64_t n, const double *__restrict__ ed2, const double *__restrict__ lbk,
+             const double *__restrict__ lbeb, const double *__restrict__ lbe, uint32_t *__restrict__ sk,
+             double *__restrict__ slbk, double *__restrict__ slbeb, double *__restrict__ slbe)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    order_query<E>(n, blockIdx.x, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, smem);
+}
+
+// The ordering of a batch: one workgroup per (set, query) item of the sets
+// whose sort width is E (items are (set << 32) | query).
+template <int E>
+__global__ void __launch_bounds__(ORDER_THREADS)
+batch_order_kernel(const BatchSet *__restrict__ sets, const int64_t *__restrict__ items)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t it = items[blockIdx.x];
+    const int d = __builtin_amdgcn_readfirstlane((int)(it >> 32));
+    const int64_t q = it & 0xFFFFFFFF;
+    const BatchSet &b = sets[d];
+    order_query<E>(b.a.n, q, b.ed2w, b.lbk, b.lbeb, b.lbe, b.skw, b.slbkw, b.slbebw, b.slbew, smem);
+}
+
+int order_width(int64_t n)
 {
     int E = 1;
     while ((int64_t)ORDER_THREADS * E < n) E <<= 1;
+    return E;
+}
+
+int launch_batch_order(int E, const BatchSet *sets, const int64_t *items, int64_t nitems, hipStream_t st)
+{
+    if (nitems == 0) return NNDTW_OK;
+    const size_t lds = (size_t)ORDER_THREADS * E * 12;
+    switch (E) {
+#define NNDTW_BORDER_CASE(EE)                                                                             \
+    case EE:                                                                                             \
+        hipLaunchKernelGGL(batch_order_kernel<EE>, dim3((unsigned)nitems), dim3(ORDER_THREADS), lds, st, \
+                           sets, items);                                                                 \
+        break;
+        NNDTW_BORDER_CASE(1)
+        NNDTW_BORDER_CASE(2)
+        NNDTW_BORDER_CASE(4)
+        NNDTW_BORDER_CASE(8)
+        NNDTW_BORDER_CASE(16)
+        NNDTW_BORDER_CASE(32)
+#undef NNDTW_BORDER_CASE
+    default:
+        return fail(NNDTW_EUNSUP, "order: sort width %d not supported", E);
+    }
+    NNDTW_LAUNCH_CHECK("batch order kernel launch");
+    return NNDTW_OK;
+}
+
+int launch_cells_prefix(int L, int Wp, uint32_t *prefix, hipStream_t st)
+{
+    hipLaunchKernelGGL(cells_prefix_kernel, dim3(1), dim3(1024), 0, st, L, Wp, prefix);
+    NNDTW_LAUNCH_CHECK("cells prefix kernel launch");
+    return NNDTW_OK;
+}
+
+static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *lbk, const double *lbeb,
+                        const double *lbe, uint32_t *sk, double *slbk, double *slbeb, double *slbe, hipStream_t st)
+{
+    const int E = order_width(n);
     const size_t lds = (size_t)ORDER_THREADS * E * 12;
 #define NNDTW_ORDER_CASE(EE)                                                                              \
     case EE:                                                                                             \
@@ -223,28 +280,7 @@ static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *
 }
 
 // ------------------------------------------------------------ search
-struct SearchArgs {
-    EngineGeom geo;    // FP32 engine (rows streamed from global memory)
-    EngineGeom geoD;   // FP64 recheck engine (the same float rows, converted)
-    int PD;        // FP64 rechecks per engine call (<= 64)
-    int SLOTS;     // candidates per FP32 batch (<= 64)
-    const float *B;
-    const float *Bp;   // padded rows of the reference set
-    int64_t ppitch;
-    int padl;
-    int64_t n;
-    const float *Q;
-    const uint32_t *sk;
-    const double *slbk, *slbeb, *slbe, *ed2;
-    const uint32_t *prefix;
-    int cascade;
-    int64_t R;
-    double eps;
-    int init_ub;
-    int64_t *nn_idx;
-    double *nn_dist;
-    int64_t *counts;
-};
+
 
 __device__ __forceinline__ bool lexless(double d, int64_t k, double bd, int64_t bk)
 {
@@ -275,9 +311,8 @@ __device__ __forceinline__ int stage_of(int cascade, double lbk, double lbb, dou
 // writes shared LDS state and counts.  Staging and DTW tasks are spread over
 // all waves (tasks dealt from an LDS counter).
 template <int C, bool EXACT>
-__global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchArgs a)
+__device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t q, unsigned char *smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     const EngineGeom &geo = a.geo, &geoD = a.geoD;
     const int PD = a.PD, SLOTS = a.SLOTS;
     // the query row serves both engines: stage the longer of their rows
@@ -296,7 +331,6 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (WAVE - 1);
     const bool w0 = tid < WAVE;
-    const int64_t q = blockIdx.x;
     const int64_t N = a.n;
     const int L = geo.L;
     const int64_t qo = q * N;
@@ -471,7 +505,65 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchA
     }
 }
 
-static size_t search_lds(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD)
+template <int C, bool EXACT>
+__global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    search_query<C, EXACT>(a, blockIdx.x, smem);
+}
+
+// The search of a batch: persistent workgroups take (set, query) items of
+// one engine shape (C, EXACT) from that shape's counter in the batch header,
+// in the order of the item list (largest expected work first).  One launch
+// per shape present: a kernel with several engine bodies would need the
+// register count of their union.  The counters are reset by the batch's
+// bound pass.
+template <int C, bool EXACT>
+__global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES)
+batch_search_kernel(const BatchSet *__restrict__ sets, const int64_t *__restrict__ items, int64_t nitems,
+                    unsigned *counter)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int64_t cur;
+    while (true) {
+        __syncthreads();                 // the previous item is finished by every wave
+        if (threadIdx.x == 0) cur = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t i = cur;
+        if (i >= nitems) break;
+        const int64_t it = items[i];
+        const int d = __builtin_amdgcn_readfirstlane((int)(it >> 32));
+        search_query<C, EXACT>(sets[d].a, it & 0xFFFFFFFF, smem);
+    }
+}
+
+int launch_batch_search(int C, bool exact, const BatchSet *sets, const int64_t *items, int64_t nitems,
+                        unsigned *counter, int waves, int grid, size_t lds, hipStream_t st)
+{
+    if (nitems == 0) return NNDTW_OK;
+    switch (C * 2 + (exact ? 1 : 0)) {
+#define NNDTW_BSEARCH_CASE(c, e)                                                                             \
+    case c * 2 + e:                                                                                       \
+        hipLaunchKernelGGL((batch_search_kernel<c, e>), dim3((unsigned)grid), dim3(WAVE * waves), lds, st, sets, \
+                           items, nitems, counter);                                                       \
+        break;
+        NNDTW_BSEARCH_CASE(1, 0)
+        NNDTW_BSEARCH_CASE(1, 1)
+        NNDTW_BSEARCH_CASE(2, 0)
+        NNDTW_BSEARCH_CASE(2, 1)
+        NNDTW_BSEARCH_CASE(3, 0)
+        NNDTW_BSEARCH_CASE(3, 1)
+        NNDTW_BSEARCH_CASE(4, 0)
+        NNDTW_BSEARCH_CASE(4, 1)
+#undef NNDTW_BSEARCH_CASE
+    default:
+        return fail(NNDTW_EUNSUP, "batch search: %d pairs per lane not supported", C);
+    }
+    NNDTW_LAUNCH_CHECK("batch search kernel launch");
+    return NNDTW_OK;
+}
+
+size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD)
 {
     const int LENA = g.LEN > gd.LEN ? g.LEN : gd.LEN;
     return (size_t)((LENA + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 8 + QCAP * 4 + 64 * 4 + 16;
@@ -499,7 +591,7 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     // query row and bookkeeping live in LDS.
     const int SLOTS = 64;
     const int PD = SLOTS;
-    const size_t lds = search_lds(g, gd, SLOTS, PD);
+    const size_t lds = search_lds_bytes(g, gd, SLOTS, PD);
     if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the search", L);
     // the engines read padded rows [base0 - PADL, base0 - PADL + LEN) of Bp
     const int64_t boff = rs->padl + g.base0 - C;
@@ -549,8 +641,7 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     r = launch_cascade_bounds(rs, Qy, nQ, o->V, ed2, lbk, lbeb, lbe, st);
     if (r) return r;
     if ((r = mark(1))) return r;
-    hipLaunchKernelGGL(cells_prefix_kernel, dim3(1), dim3(1024), 0, st, L, plan.Wp, prefix);
-    NNDTW_LAUNCH_CHECK("cells prefix kernel launch");
+    if ((r = launch_cells_prefix(L, plan.Wp, prefix, st))) return r;
     if ((r = mark(2))) return r;
     if ((r = launch_order(n, nQ, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, st))) return r;
     if ((r = mark(3))) return r;

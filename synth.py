@@ -125,6 +125,45 @@ def workload(name: str, n_refs: int | None = None, n_queries: int | None = None)
     return Workload(name, refs, queries, ws, vs, desc=f"{kind} N={N} Q={Q} L={L}")
 
 
+@dataclass
+class BatchDataset:
+    refs: np.ndarray          # float32 [N][L]
+    queries: np.ndarray       # float32 [Q][L]
+    W: int
+    V: int
+
+    @property
+    def L(self) -> int:
+        return self.refs.shape[1]
+
+
+def batch_params(n_sets: int = 64, L_range=(24, 2048), N_range=(50, 8000), q_frac: float = 0.1,
+                 w_frac: float = 0.1, config_id: int = 4):
+    """(L, N, Q, W) of each dataset of the batching workload: L log-uniform in
+    L_range (rounded), N uniform in N_range, Q = max(1, round(q_frac N)),
+    W = round-half-up(w_frac L).  Drawn from stream 4 of the configuration."""
+    rng = rng_for(config_id, 4)
+    L = np.rint(np.exp(rng.uniform(math.log(L_range[0]), math.log(L_range[1]), n_sets))).astype(int)
+    N = rng.integers(N_range[0], N_range[1] + 1, n_sets)
+    Q = np.maximum(1, np.rint(q_frac * N)).astype(int)
+    W = np.array([window_from_fraction(w_frac, int(l)) for l in L])
+    return [(int(L[d]), int(N[d]), int(Q[d]), int(W[d])) for d in range(n_sets)]
+
+
+def batch_workload(n_sets: int = 64, L_range=(24, 2048), N_range=(50, 8000), q_frac: float = 0.1,
+                   w_frac: float = 0.1, V: int = 5, config_id: int = 4) -> list:
+    """The batching workload: independent random-walk datasets of ragged
+    lengths (64 sets, L log-uniform in [24, 2048], N uniform in [50, 8000],
+    Q = 0.1 N, W = 0.1 L, V = 5 by default).  Dataset d draws its references
+    and queries from SeedSequence([180809617, config_id, 100 + d, stream])."""
+    out = []
+    for d, (L, N, Q, W) in enumerate(batch_params(n_sets, L_range, N_range, q_frac, w_frac, config_id)):
+        rr = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, config_id, 100 + d, STREAM_REFS]))
+        rq = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, config_id, 100 + d, STREAM_QUERIES]))
+        out.append(BatchDataset(rw(N, L, rr), rw(Q, L, rq), W, V))
+    return out
+
+
 def tightness_pairs(n_pairs: int = 250_000, L: int = 256, config_id: int = 2):
     """Independent sin5 pairs (A_k, B_k) for LB/DTW tightness (Figure 1 workload shape)."""
     rng = rng_for(config_id, STREAM_PAIRS)

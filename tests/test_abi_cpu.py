@@ -127,6 +127,57 @@ def test_refset_and_search_validation():
                 "Q is NULL") == nd.EINVAL
 
 
+def test_batch_struct_layouts():
+    assert ctypes.sizeof(nd._BatchSet) == 64
+    assert nd._BatchSet.R.offset == 48 and nd._BatchSet.cpl.offset == 56
+    assert ctypes.sizeof(nd._BatchPlan) == 304
+    assert nd._BatchPlan.order_off.offset == 48 and nd._BatchPlan.search_off.offset == 144
+    assert nd._BatchPlan.reserved.offset == 272
+
+
+def test_batch_validation_and_workspace_size():
+    lib = nd.lib()
+    opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
+    nbytes = ctypes.c_size_t(0)
+    descs = []
+    for L, n, W in ((24, 50, 2), (300, 700, 30), (1839, 200, 184)):
+        d = nd._Refset()
+        d.magic, d.L, d.n, d.W = nd.REFSET_MAGIC, L, n, W
+        descs.append(d)
+    sets = (nd._BatchSet * 3)()
+    for i, d in enumerate(descs):
+        sets[i].refset = ctypes.addressof(d)
+        sets[i].Q, sets[i].nQ, sets[i].nn_idx, sets[i].nn_dist = FAKE, 5 + i, FAKE, FAKE
+    assert lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(opts), ctypes.byref(nbytes)) == 0
+    # at least the three sets' search workspaces (bounds, order, gathered bounds)
+    assert nbytes.value >= sum(8 * 7 * (5 + i) * d.n for i, d in enumerate(descs))
+    assert _err(lib.nndtw_batch_workspace_bytes(sets, 0, ctypes.byref(opts), ctypes.byref(nbytes)),
+                "nsets=0") == nd.EINVAL
+    assert _err(lib.nndtw_batch_workspace_bytes(None, 3, ctypes.byref(opts), ctypes.byref(nbytes)),
+                "sets is NULL") == nd.EINVAL
+    plan = nd._BatchPlan()
+    assert _err(lib.nndtw_batch_prepare(sets, 3, ctypes.byref(opts), ctypes.c_void_p(0x100000), 1,
+                                        ctypes.byref(plan), NULL), "workspace too small") == nd.EINVAL
+    sets[1].nQ = -1
+    assert _err(lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(opts), ctypes.byref(nbytes)),
+                "set 1: nQ=-1") == nd.EINVAL
+    sets[1].nQ = 6
+    sets[2].nn_dist = NULL
+    assert _err(lib.nndtw_batch_prepare(sets, 3, ctypes.byref(opts), FAKE, 1 << 40, ctypes.byref(plan), NULL),
+                "set 2: nn_dist is NULL") == nd.EINVAL
+    bad = nd._Refset()
+    sets[0].refset = ctypes.addressof(bad)
+    assert _err(lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(opts), ctypes.byref(nbytes)),
+                "set 0: refset was not built") == nd.EINVAL
+    sets[0].refset = ctypes.addressof(descs[0])
+    ev = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
+    ev.events = FAKE
+    assert _err(lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(ev), ctypes.byref(nbytes)),
+                "events must be NULL") == nd.EINVAL
+    assert _err(lib.nndtw_search_batch(None, FAKE, NULL), "plan is NULL") == nd.EINVAL
+    assert _err(lib.nndtw_search_batch(ctypes.byref(plan), FAKE, NULL), "not made by") == nd.EINVAL
+
+
 def test_python_binding_rejects_cpu_tensors():
     import torch
     with pytest.raises(TypeError):

@@ -308,3 +308,99 @@ def test_search_full_sin256_properties():
     oi, od, oc = oracle.search(wl.refs, wl.queries[sel], 26, 5, "keogh_enh", R, True)
     assert np.array_equal(gi[sel], oi) and np.array_equal(gd[sel], od)
     assert np.array_equal(gc[sel, :5], oc[:, :5])
+
+
+# ------------------------------------------------------------------ batching
+def run_batch(datasets, V=5, R=None, cpl=None, waves=0):
+    pairs = [(nd.RefSet(dev(ds.refs), ds.W), dev(ds.queries)) for ds in datasets]
+    bsr = nd.BatchSearcher(pairs, V=V, R=R, cpl=cpl, waves=waves)
+    out = bsr()
+    return bsr, pairs, [(host(i), host(d), host(c)) for i, d, c in out]
+
+
+@pytest.mark.parametrize("waves", [0, 2, 8])
+def test_batch_matches_single_search_and_oracle(waves):
+    """Every set of a ragged batch gives exactly the single-set search (index,
+    distance, the five defined counts) at the R and shape the batch used, and
+    the oracle on a sample of its queries.  The implementation-defined counts
+    (abandoned, cells, rechecks) depend on which DTW of a round finishes first
+    and are only checked for consistency."""
+    sets = synth.batch_workload(n_sets=10, L_range=(24, 700), N_range=(50, 600), q_frac=0.05)
+    say("batch", len(sets), "sets, waves", waves)
+    bsr, pairs, res = run_batch(sets, waves=waves)
+    for d, ds in enumerate(sets):
+        say("batch set", d, ds.refs.shape, ds.queries.shape, ds.W, bsr.R[d], bsr.cpl[d])
+        gi, gd, gc = res[d]
+        si, sd, sc, _ = nd.search(pairs[d][0], pairs[d][1], V=5, R=bsr.R[d], cpl=bsr.cpl[d], waves=waves)
+        assert np.array_equal(gi, host(si)) and np.array_equal(gd, host(sd))
+        assert np.array_equal(gc[:, :5], host(sc)[:, :5])
+        assert np.all(gc[:, 5] <= gc[:, 4]) and np.all(gc[:, 6] >= 0) and np.all(gc[:, 7] >= (gc[:, 4] > 0))
+        oi, od, oc = oracle.search(ds.refs, ds.queries[:3], ds.W, 5, "keogh_enh", bsr.R[d], True)
+        assert np.array_equal(gi[:3], oi) and np.array_equal(gd[:3], od)
+        assert np.array_equal(gc[:3, :5], oc[:, :5])
+
+
+def test_batch_rounds_and_shapes_per_set():
+    """Per-set R and engine shape overrides (as an autotuner sets them)."""
+    sets = synth.batch_workload(n_sets=5, L_range=(30, 200), N_range=(60, 300), q_frac=0.05)
+    R = [1, 7, 64, 0, 300]
+    cpl = [1, 2, 0, 4, 3]
+    bsr, pairs, res = run_batch(sets, R=R, cpl=cpl)
+    for d, ds in enumerate(sets):
+        if R[d]:
+            assert bsr.R[d] == R[d]
+        if cpl[d]:
+            assert bsr.cpl[d] == cpl[d]
+        oi, od, oc = oracle.search(ds.refs, ds.queries, ds.W, 5, "keogh_enh", bsr.R[d], True)
+        gi, gd, gc = res[d]
+        assert np.array_equal(gi, oi) and np.array_equal(gd, od) and np.array_equal(gc[:, :5], oc[:, :5])
+
+
+def test_batch_graph_replay():
+    """The launch sequence captured in a graph: every replay, with eager work
+    and synchronisation between replays, reproduces the eager result."""
+    sets = synth.batch_workload(n_sets=6, L_range=(24, 300), N_range=(50, 400), q_frac=0.05)
+    bsr, pairs, ref = run_batch(sets)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bsr()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bsr()
+    for rep in range(3):
+        say("graph replay", rep)
+        for i, dd, c in bsr.out:
+            i.fill_(-7)
+            dd.fill_(-1.0)
+            c.fill_(-3)
+        x = torch.randn(4096, device=DEV)
+        (x * x).sum().item()
+        g.replay()
+        torch.cuda.synchronize()
+        for d, (i, dd, c) in enumerate(bsr.out):
+            assert np.array_equal(host(i), ref[d][0]) and np.array_equal(host(dd), ref[d][1])
+            assert np.array_equal(host(c)[:, :5], ref[d][2][:, :5])
+
+
+def test_batch_full_workload_sampled():
+    """The full batching workload (64 sets, L 25..1839, 26,583 queries) in the
+    benchmarked launch shape: all queries against size-independent properties,
+    sampled queries of sampled sets against the oracle."""
+    sets = synth.batch_workload()
+    say("batch full", len(sets), "sets")
+    bsr, pairs, res = run_batch(sets)
+    for d, ds in enumerate(sets):
+        gi, gd, gc = res[d]
+        assert np.all(gc[:, 1:5].sum(1) == ds.refs.shape[0])
+        assert np.all((gi >= 0) & (gi < ds.refs.shape[0]))
+        assert np.array_equal(gd, oracle.dtw(ds.queries, ds.refs[gi], ds.W, zip_=True))
+    cost = [ds.refs.shape[0] * ds.L * ds.W for ds in sets]
+    for d in sorted({0, 21, 42, 63, int(np.argmax(cost)), int(np.argmin(cost))}):
+        ds = sets[d]
+        say("batch full oracle set", d, ds.refs.shape, ds.W, bsr.R[d], bsr.cpl[d])
+        oi, od, oc = oracle.search(ds.refs, ds.queries[:2], ds.W, 5, "keogh_enh", bsr.R[d], True)
+        gi, gd, gc = res[d]
+        assert np.array_equal(gi[:2], oi) and np.array_equal(gd[:2], od) and np.array_equal(gc[:2, :5], oc[:, :5])
