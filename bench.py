@@ -140,6 +140,74 @@ def hbm_streaming(nd, synth, torch, dev):
     return out
 
 
+def batch_bench(nd, synth, torch, dev, reps=3, tuned=None):
+    """The batching workload (64 random-walk sets, L 25..1839, 26,583 queries,
+    W = 0.1 L, V = 5) as one captured graph of the batched search, inputs
+    resident; against the same sets searched one after another with the
+    single-set entry point.  Reference-set builds and planning are untimed
+    (the paper's training time)."""
+    sets = synth.batch_workload()
+    pairs = [(nd.RefSet(torch.from_numpy(ds.refs).to(dev), ds.W), torch.from_numpy(ds.queries).to(dev))
+             for ds in sets]
+    nq = sum(ds.queries.shape[0] for ds in sets)
+    R = cpl = None
+    report = None
+    if tuned is not None:
+        from paper_1808_09617_amd import tune
+        t0 = time.perf_counter()
+        R, cpl, report = tune.autotune(pairs, V=5)
+        tune_s = time.perf_counter() - t0
+    bsr = nd.BatchSearcher(pairs, V=5, R=R, cpl=cpl)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bsr()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bsr()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    t = sorted(times)[len(times) // 2]
+    cells = sum(int(c[:, 6].sum()) for _, _, c in bsr.out)
+    started = sum(int(c[:, 4].sum()) for _, _, c in bsr.out)
+    pairs_total = sum(ds.refs.shape[0] * ds.queries.shape[0] for ds in sets)
+    out = {"workload": "batch64-rw", "sets": len(sets), "queries": nq, "pairs": pairs_total,
+           "schedule": "autotuned" if tuned is not None else "library defaults",
+           "ms": t * 1e3, "queries_per_s": nq / t, "dtw_cells_per_s": cells / t,
+           "valu_frac_dtw": 3.0 * cells / t / VALU_PEAK_OPS, "pruning_rate": 1.0 - started / pairs_total,
+           "launches": 1 + sum(1 for c in bsr.plan.order_cnt if c) + sum(1 for c in bsr.plan.search_cnt if c),
+           "shapes": {f"C{sh // 2 + 1}{'x' if sh & 1 else ''}": int(bsr.plan.search_cnt[sh])
+                      for sh in range(8) if bsr.plan.search_cnt[sh]}}
+    # the same sets one after another through the single-set entry point
+    srs = [nd.Searcher(rs, Q.shape[0], V=5, R=bsr.R[d], cpl=bsr.cpl[d]) for d, (rs, Q) in enumerate(pairs)]
+    for (rs, Q), sr in zip(pairs, srs):
+        sr(Q)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for (rs, Q), sr in zip(pairs, srs):
+        sr(Q)
+    e1.record()
+    e1.synchronize()
+    t1 = e0.elapsed_time(e1) / 1e3
+    out["per_set_loop_ms"] = t1 * 1e3
+    out["speedup_vs_per_set_loop"] = t1 / t
+    if report is not None:
+        out["tuning_s"] = tune_s
+        out["buckets"] = {k: {"sets": v["sets"], "cpl": v["cpl"], "R": v["R"]} for k, v in report.items()}
+    del g, bsr, srs, pairs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +339,8 @@ def main():
             tight[f"enhanced{v}"] = float((nd.lb_enhanced(A, B, U, Lo, W, v, zip_=True)[keep] / d[keep]).mean())
         res["tightness"] = tight
         res["hbm_streaming"] = hbm_streaming(nd, synth, torch, dev)
+        res["batch"] = batch_bench(nd, synth, torch, dev)
+        res["batch_tuned"] = batch_bench(nd, synth, torch, dev, tuned="auto")
         log("extras done")
 
     if args.calib_copy_mb:

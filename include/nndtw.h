@@ -281,8 +281,8 @@ typedef struct nndtw_batch_plan {
     int32_t grid;                /* persistent search workgroups                     */
     int64_t lds;                 /* search kernel LDS bytes                          */
     int64_t ws_bytes;            /* workspace bytes the plan uses                    */
-    int64_t order_off[6];        /* item-list offset and count per sort width        */
-    int64_t order_cnt[6];        /*   1, 2, 4, 8, 16, 32 positions per thread        */
+    int64_t order_off[6];        /* item-list offset and count per sort size class   */
+    int64_t order_cnt[6];        /*   256, 512, ..., 8192 padded references          */
     int64_t search_off[8];       /* item-list offset and count per engine shape      */
     int64_t search_cnt[8];       /*   (C, exact) = (1,0), (1,1), ..., (4,1)          */
     int64_t reserved[4];

@@ -71,7 +71,7 @@ struct WsLayout {
 };
 WsLayout ws_layout(int64_t nQ, int64_t n, int L);
 int launch_cells_prefix(int L, int Wp, uint32_t *prefix, hipStream_t s);
-int order_width(int64_t n);     // positions per thread of the visiting-order sort
+int order_width(int64_t n);     // visiting-order sort size class: npow = 256 * width
 int launch_batch_order(int E, const BatchSet *sets, const int64_t *items, int64_t nitems, hipStream_t s);
 int launch_batch_search(int C, bool exact, const BatchSet *sets, const int64_t *items, int64_t nitems,
                         unsigned *counter, int waves, int grid, size_t lds, hipStream_t s);

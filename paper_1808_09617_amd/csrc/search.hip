@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(1024) cells_prefix_kernel(int L, int Wp, uint3
 
 // ------------------------------------------------------------ order
 // Bitonic sort of (ed2, index) ascending, one workgroup per query.  Thread t
-// holds the E consecutive positions t*E .. t*E+E-1 (npow = 256 * E), so a
+// of NT holds the E consecutive positions t*E .. t*E+E-1 (npow = NT * E), so a
 // compare-exchange at stride s pairs two of its own registers when s < E,
 // lanes t and t ^ (s / E) of one wave (a shuffle) when s < 64 E, and only
 // larger strides go through LDS with a barrier.  Keys are unique (indices
@@ -116,14 +116,14 @@ __device__ __forceinline__ void keep(double &k, uint32_t &x, double ko, uint32_t
     x = take ? xo : x;
 }
 
-template <int E>
+template <int E, int NT>
 __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *__restrict__ ed2,
                                             const double *__restrict__ lbk, const double *__restrict__ lbeb,
                                             const double *__restrict__ lbe, uint32_t *__restrict__ sk,
                                             double *__restrict__ slbk, double *__restrict__ slbeb,
                                             double *__restrict__ slbe, unsigned char *smem)
 {
-    constexpr int npow = ORDER_THREADS * E;
+    constexpr int npow = NT * E;
     double *key = reinterpret_cast<double *>(smem);
     uint32_t *idx = reinterpret_cast<uint32_t *>(key + npow);
     const int t = threadIdx.x;
@@ -182,7 +182,7 @@ __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *
 #pragma unroll
     for (int r = 0; r < E; ++r) idx[t * E + r] = x[r];
     __syncthreads();
-    for (int i = t; i < n; i += ORDER_THREADS) {
+    for (int i = t; i < n; i += NT) {
         const uint32_t kk = idx[i];
         const int64_t o = q * n + i;
         sk[o] = kk;
@@ -192,20 +192,20 @@ __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *
     }
 }
 
-template <int E>
-__global__ void __launch_bounds__(ORDER_THREADS)
+template <int E, int NT>
+__global__ void __launch_bounds__(NT)
 order_kernel(int64_t n, const double *__restrict__ ed2, const double *__restrict__ lbk,
              const double *__restrict__ lbeb, const double *__restrict__ lbe, uint32_t *__restrict__ sk,
              double *__restrict__ slbk, double *__restrict__ slbeb, double *__restrict__ slbe)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    order_query<E>(n, blockIdx.x, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, smem);
+    order_query<E, NT>(n, blockIdx.x, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, smem);
 }
 
 // The ordering of a batch: one workgroup per (set, query) item of the sets
 // whose sort width is E (items are (set << 32) | query).
-template <int E>
-__global__ void __launch_bounds__(ORDER_THREADS)
+template <int E, int NT>
+__global__ void __launch_bounds__(NT)
 batch_order_kernel(const BatchSet *__restrict__ sets, const int64_t *__restrict__ items)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -213,7 +213,7 @@ batch_order_kernel(const BatchSet *__restrict__ sets, const int64_t *__restrict_
     const int d = __builtin_amdgcn_readfirstlane((int)(it >> 32));
     const int64_t q = it & 0xFFFFFFFF;
     const BatchSet &b = sets[d];
-    order_query<E>(b.a.n, q, b.ed2w, b.lbk, b.lbeb, b.lbe, b.skw, b.slbkw, b.slbebw, b.slbew, smem);
+    order_query<E, NT>(b.a.n, q, b.ed2w, b.lbk, b.lbeb, b.lbe, b.skw, b.slbkw, b.slbebw, b.slbew, smem);
 }
 
 int order_width(int64_t n)
@@ -223,25 +223,25 @@ int order_width(int64_t n)
     return E;
 }
 
-int launch_batch_order(int E, const BatchSet *sets, const int64_t *items, int64_t nitems, hipStream_t st)
+// Sort shapes by padded size npow = 256 * W (W = order_width): at most 8
+// positions per thread, so large sorts run 512 or 1024 threads (more waves
+// share the one workgroup an LDS-heavy sort leaves on a CU).
+#define NNDTW_FOR_EACH_SORT(X) X(1, 1, 256) X(2, 2, 256) X(4, 4, 256) X(8, 8, 256) X(16, 8, 512) X(32, 8, 1024)
+
+int launch_batch_order(int Wd, const BatchSet *sets, const int64_t *items, int64_t nitems, hipStream_t st)
 {
     if (nitems == 0) return NNDTW_OK;
-    const size_t lds = (size_t)ORDER_THREADS * E * 12;
-    switch (E) {
-#define NNDTW_BORDER_CASE(EE)                                                                             \
-    case EE:                                                                                             \
-        hipLaunchKernelGGL(batch_order_kernel<EE>, dim3((unsigned)nitems), dim3(ORDER_THREADS), lds, st, \
-                           sets, items);                                                                 \
+    const size_t lds = (size_t)ORDER_THREADS * Wd * 12;
+    switch (Wd) {
+#define NNDTW_BORDER_CASE(WW, EE, NT)                                                                \
+    case WW:                                                                                         \
+        hipLaunchKernelGGL((batch_order_kernel<EE, NT>), dim3((unsigned)nitems), dim3(NT), lds, st, \
+                           sets, items);                                                             \
         break;
-        NNDTW_BORDER_CASE(1)
-        NNDTW_BORDER_CASE(2)
-        NNDTW_BORDER_CASE(4)
-        NNDTW_BORDER_CASE(8)
-        NNDTW_BORDER_CASE(16)
-        NNDTW_BORDER_CASE(32)
+        NNDTW_FOR_EACH_SORT(NNDTW_BORDER_CASE)
 #undef NNDTW_BORDER_CASE
     default:
-        return fail(NNDTW_EUNSUP, "order: sort width %d not supported", E);
+        return fail(NNDTW_EUNSUP, "order: sort width %d not supported", Wd);
     }
     NNDTW_LAUNCH_CHECK("batch order kernel launch");
     return NNDTW_OK;
@@ -257,24 +257,19 @@ int launch_cells_prefix(int L, int Wp, uint32_t *prefix, hipStream_t st)
 static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *lbk, const double *lbeb,
                         const double *lbe, uint32_t *sk, double *slbk, double *slbeb, double *slbe, hipStream_t st)
 {
-    const int E = order_width(n);
-    const size_t lds = (size_t)ORDER_THREADS * E * 12;
-#define NNDTW_ORDER_CASE(EE)                                                                              \
-    case EE:                                                                                             \
-        hipLaunchKernelGGL(order_kernel<EE>, dim3((unsigned)nQ), dim3(ORDER_THREADS), lds, st, n, ed2, lbk, \
-                           lbeb, lbe, sk, slbk, slbeb, slbe);                                            \
+    const int Wd = order_width(n);
+    const size_t lds = (size_t)ORDER_THREADS * Wd * 12;
+    switch (Wd) {
+#define NNDTW_ORDER_CASE(WW, EE, NT)                                                                     \
+    case WW:                                                                                             \
+        hipLaunchKernelGGL((order_kernel<EE, NT>), dim3((unsigned)nQ), dim3(NT), lds, st, n, ed2, lbk, lbeb, \
+                           lbe, sk, slbk, slbeb, slbe);                                                  \
         break;
-    switch (E) {
-        NNDTW_ORDER_CASE(1)
-        NNDTW_ORDER_CASE(2)
-        NNDTW_ORDER_CASE(4)
-        NNDTW_ORDER_CASE(8)
-        NNDTW_ORDER_CASE(16)
-        NNDTW_ORDER_CASE(32)
+        NNDTW_FOR_EACH_SORT(NNDTW_ORDER_CASE)
+#undef NNDTW_ORDER_CASE
     default:
         return fail(NNDTW_EUNSUP, "order: %lld references exceed the supported maximum", (long long)n);
     }
-#undef NNDTW_ORDER_CASE
     NNDTW_LAUNCH_CHECK("order kernel launch");
     return NNDTW_OK;
 }
