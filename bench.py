@@ -220,6 +220,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the per-query arm and tightness")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batching workload (defaults and autotuned), one JSON line each")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, one plain device copy of this many MiB (memory-counter calibration)")
     args = ap.parse_args()
@@ -233,6 +235,12 @@ def main():
 
     import paper_1808_09617_amd as nd
     import synth
+
+    if args.batch_only:
+        dev = torch.device("cuda:0")
+        for tuned in (None, "auto"):
+            print(json.dumps(batch_bench(nd, synth, torch, dev, tuned=tuned)), flush=True)
+        return
 
     wl = synth.workload("nndtw-sin256")
     W, V = wl.windows[0], args.V
