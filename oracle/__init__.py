@@ -72,6 +72,8 @@ def lib():
             "oracle_lb_keogh_batch": (None, [p, i64, p, p, i64, i32, i32, p]),
             "oracle_lb_enhanced_batch": (None, [p, i64, p, p, p, i64, i32, i32, i32, p, i32, i32, p]),
             "oracle_dtw_batch": (None, [p, i64, p, i64, i32, i32, p, i32, p]),
+            "oracle_dtw_path": (ctypes.c_double, [p, p, i32, i32, p, p, p]),
+            "oracle_dtw_grad_batch": (None, [p, i64, p, i64, i32, i32, i32, p, p, p]),
             "oracle_brute_nn": (None, [p, i64, p, i64, i32, i32, p, p]),
             "oracle_search": (None, [p, i64, p, i64, i32, i32, i32, i32, i64, i32, p, p, p]),
             "oracle_max_threads": (i32, []),
@@ -160,6 +162,33 @@ def dtw(A, B, W, cutoff=None, zip_=False):
     lib().oracle_dtw_batch(_ptr(A), A.shape[0], _ptr(B), B.shape[0], A.shape[1], int(W), _ptr(cut),
                            int(zip_), _ptr(out))
     return out
+
+
+def dtw_path(a, b, W):
+    """(DTW_W(a, b), argmin warping path as an int array [n][2] from (0,0) to
+    (L-1,L-1)); ties resolved in the order (i-1,j-1), (i-1,j), (i,j-1)."""
+    a, b = _f32(a), _f32(b)
+    L = a.shape[0]
+    pi = np.zeros(2 * L, np.int32)
+    pj = np.zeros(2 * L, np.int32)
+    n = ctypes.c_int(0)
+    d = lib().oracle_dtw_path(_ptr(a), _ptr(b), L, int(W), _ptr(pi), _ptr(pj), ctypes.byref(n))
+    return d, np.stack([pi[:n.value], pj[:n.value]], 1)
+
+
+def dtw_grad(A, B, W, gout=None, zip_=False):
+    """Gradient of DTW_W with respect to the query along the argmin path:
+    returns (gA [nA][L], DTW_W per pair) with gA[a] = sum over the pairs
+    (a, b) of gout[pair] * dDTW(a, b)/dA_a (gout defaults to ones)."""
+    A, B = _one(A), _one(B)
+    shape = _pairing(A, B, zip_)
+    g = np.ones(shape, np.float64) if gout is None else np.ascontiguousarray(np.broadcast_to(
+        np.asarray(gout, np.float64), shape))
+    gA = np.zeros(A.shape, np.float64)
+    dist = np.empty(shape, np.float64)
+    lib().oracle_dtw_grad_batch(_ptr(A), A.shape[0], _ptr(B), B.shape[0], A.shape[1], int(W), int(zip_),
+                                _ptr(g), _ptr(gA), _ptr(dist))
+    return gA, dist
 
 
 def left_bands_sum(a, b, W):

@@ -442,6 +442,108 @@ void oracle_search(const float *refs, int64_t N, const float *queries, int64_t Q
     free(Lo);
 }
 
+/* ------------------------------------------------------------------------ */
+/* DTW_W gradient with respect to the query along the argmin warping path.    */
+/* The paper defines DTW_W (Equation 1) but no gradient.  With the point cost */
+/* delta(a_i, b_j) = (a_i - b_j)^2, DTW_W(A, B) is the minimum over warping   */
+/* paths of the path cost; where the minimising path P* is unique, the cost   */
+/* is differentiable in A with                                               */
+/*   dDTW/da_i = sum over the cells (i, j) of P* of 2 (a_i - b_j).           */
+/* P* is recovered by walking back from (L-1, L-1): at each cell the         */
+/* predecessor is the first of (i-1, j-1), (i-1, j), (i, j-1) whose D equals */
+/* their minimum (the fixed order that also resolves exact ties).            */
+
+/* Full FP64 cost matrix D[i*L + j] (+inf outside the window); returns D(L-1,L-1). */
+static double dtw_full(const float *A, const float *B, int L, int W, double *D)
+{
+    int w = eff_window(L, W);
+    for (int i = 0; i < L; ++i) {
+        for (int j = 0; j < L; ++j) {
+            double v = OINF;
+            if (abs(i - j) <= w) {
+                double m;
+                if (i == 0 && j == 0) m = 0.0;
+                else {
+                    double dg = (i > 0 && j > 0) ? D[(i - 1) * L + j - 1] : OINF;
+                    double up = i > 0 ? D[(i - 1) * L + j] : OINF;
+                    double lf = j > 0 ? D[i * L + j - 1] : OINF;
+                    m = dmin(dmin(dg, up), lf);
+                }
+                v = delta(A[i], B[j]) + m;
+            }
+            D[i * L + j] = v;
+        }
+    }
+    return D[L * L - 1];
+}
+
+/* The argmin path, (0,0) first; returns its number of cells (<= 2L-1). */
+static int backtrack(const double *D, int L, int *pi, int *pj)
+{
+    int i = L - 1, j = L - 1, n = 0;
+    int ri[4096], rj[4096];
+    for (;;) {
+        ri[n] = i;
+        rj[n] = j;
+        ++n;
+        if (i == 0 && j == 0) break;
+        double dg = (i > 0 && j > 0) ? D[(i - 1) * L + j - 1] : OINF;
+        double up = i > 0 ? D[(i - 1) * L + j] : OINF;
+        double lf = j > 0 ? D[i * L + j - 1] : OINF;
+        double m = dmin(dmin(dg, up), lf);
+        if (dg == m) { --i; --j; }
+        else if (up == m) { --i; }
+        else { --j; }
+    }
+    for (int k = 0; k < n; ++k) {
+        pi[k] = ri[n - 1 - k];
+        pj[k] = rj[n - 1 - k];
+    }
+    return n;
+}
+
+/* DTW_W(A, B) and its argmin path (capacity 2L-1 cells each in pi, pj). */
+double oracle_dtw_path(const float *A, const float *B, int L, int W, int *pi, int *pj, int *len)
+{
+    double *D = (double *)malloc(sizeof(double) * (size_t)L * L);
+    double d = dtw_full(A, B, L, W, D);
+    *len = backtrack(D, L, pi, pj);
+    free(D);
+    return d;
+}
+
+/* gA[i] += g * dDTW_W(A, B)/dA_i along the argmin path; returns DTW_W. */
+static double dtw_grad_add(const float *A, const float *B, int L, int W, double g, double *gA)
+{
+    int *pi = (int *)malloc(sizeof(int) * (size_t)(2 * L));
+    int *pj = (int *)malloc(sizeof(int) * (size_t)(2 * L));
+    int n = 0;
+    double d = oracle_dtw_path(A, B, L, W, pi, pj, &n);
+    for (int k = 0; k < n; ++k)
+        gA[pi[k]] += g * (2.0 * ((double)A[pi[k]] - (double)B[pj[k]]));
+    free(pi);
+    free(pj);
+    return d;
+}
+
+/* Batched: gA[a][i] = sum over the pairs (a, b) of gout[pair] * dDTW/dA_a[i]
+ * (pairing 0 cross: pair a*nB + b; 1 zip: pair a, b = a); dist[pair] = DTW_W. */
+void oracle_dtw_grad_batch(const float *A, int64_t nA, const float *B, int64_t nB, int L, int W,
+                           int pairing, const double *gout, double *gA, double *dist)
+{
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t a = 0; a < nA; ++a) {
+        double *g = gA + a * L;
+        for (int i = 0; i < L; ++i) g[i] = 0.0;
+        int64_t b0 = pairing ? a : 0, b1 = pairing ? a + 1 : nB;
+        for (int64_t b = b0; b < b1; ++b) {
+            int64_t p = pairing ? a : a * nB + b;
+            double d = dtw_grad_add(A + a * L, B + b * L, L, W, gout[p], g);
+            if (dist) dist[p] = d;
+        }
+    }
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

@@ -30,6 +30,12 @@ MUTATIONS = [
     ("search: no slack", "double thr = dmin(bsf, ub) * (1.0 + slack);", "double thr = dmin(bsf, ub);"),
     ("brute nn: last index on ties", "if (bi < 0 || d < best)", "if (bi < 0 || d <= best)"),
     ("ed2 skips the last point", "for (int i = 0; i < L; ++i) s += delta(A[i], B[i]);", "for (int i = 0; i < L - 1; ++i) s += delta(A[i], B[i]);"),
+    ("grad: (i,j-1) preferred to (i-1,j) on ties", "else if (up == m) { --i; }\n        else { --j; }", "else if (lf == m) { --j; }\n        else { --i; }"),
+    ("grad: diagonal preferred last on ties", "if (dg == m) { --i; --j; }\n        else if (up == m) { --i; }", "if (up == m) { --i; }\n        else if (dg == m) { --i; --j; }"),
+    ("grad: factor 2 dropped", "g * (2.0 * ((double)A[pi[k]] - (double)B[pj[k]]))", "g * (((double)A[pi[k]] - (double)B[pj[k]]))"),
+    ("grad: accumulated at the reference index", "gA[pi[k]] += g * (2.0", "gA[pj[k]] += g * (2.0"),
+    ("grad: output weight ignored", "gA[pi[k]] += g * (2.0", "gA[pi[k]] += 1.0 * (2.0"),
+    ("grad: last path cell dropped", "    for (int k = 0; k < n; ++k)\n        gA[pi[k]]", "    for (int k = 0; k < n - 1; ++k)\n        gA[pi[k]]"),
 ]
 
 

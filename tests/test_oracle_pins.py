@@ -388,3 +388,123 @@ def test_search_equal_ed_visited_by_index(orc):
     refs = np.stack([B1, B2])                   # B1 first: both need DTW
     idx, dist, cnt = orc.search(refs, A, 1, 1, "enh", 1)
     assert idx[0] == 1 and cnt[0, 4] == 2
+
+
+# ------------------------------------------------------------------ gradient
+# DTW_W (Equation 1) is the minimum over warping paths of the path cost; the
+# oracle's gradient with respect to the query follows the minimising path
+# recovered by walking back from (L-1, L-1), ties broken in the order
+# (i-1,j-1), (i-1,j), (i,j-1).  Pinned against path enumeration, closed forms
+# and exact finite differences.
+
+def _moves_from_end(path):
+    """The walk back from (L-1,L-1) as a move sequence: 0 diagonal, 1 (i-1,j), 2 (i,j-1)."""
+    out = []
+    for (i0, j0), (i1, j1) in zip(path[::-1][1:], path[::-1][:-1]):
+        out.append(0 if (i1 - i0, j1 - j0) == (1, 1) else (1 if (i1 - i0, j1 - j0) == (1, 0) else 2))
+    return tuple(out)
+
+
+def _brute_path(a, b, W):
+    """Among all minimum-cost paths, the one whose walk back takes the first
+    predecessor of the order diagonal, (i-1,j), (i,j-1) at every step, i.e.
+    the lexicographically smallest move sequence from the end."""
+    ps = paths.enumerate_paths(len(a), W)
+    costs = [paths.path_cost(a, b, p) for p in ps]
+    best = min(costs)
+    opt = [p for p, c in zip(ps, costs) if c == best]
+    return best, min(opt, key=_moves_from_end), sorted(costs)
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 7])
+def test_grad_path_is_the_unique_argmin(orc, L):
+    rng = np.random.default_rng(700 + L)
+    for W in range(0, L):
+        for _ in range(4):
+            a = rng.standard_normal(L).astype(np.float32)
+            b = rng.standard_normal(L).astype(np.float32)
+            best, p, costs = _brute_path(a, b, W)
+            d, path = orc.dtw_path(a, b, W)
+            assert d == best
+            if len(costs) > 1:
+                assert costs[1] > costs[0]          # continuous data: unique argmin
+            assert [tuple(x) for x in path] == list(p)
+
+
+@pytest.mark.parametrize("L", [3, 4, 5, 6])
+def test_grad_path_tie_order_on_integer_series(orc, L):
+    """Integer-valued series create exact ties between optimal paths; the
+    path must be the one the fixed predecessor order selects."""
+    rng = np.random.default_rng(800 + L)
+    nties = 0
+    for W in range(0, L):
+        for _ in range(12):
+            a = rng.integers(0, 3, L).astype(np.float32)
+            b = rng.integers(0, 3, L).astype(np.float32)
+            best, p, costs = _brute_path(a, b, W)
+            nties += len(costs) > 1 and costs[1] == costs[0]
+            d, path = orc.dtw_path(a, b, W)
+            assert d == best and [tuple(x) for x in path] == list(p)
+    assert nties > 0
+
+
+def test_grad_w0_and_identical_series(orc):
+    A = synth.random_series(6, 40, seed=81)
+    B = synth.random_series(6, 40, seed=82)
+    g, d = orc.dtw_grad(A, B, 0, zip_=True)
+    assert np.array_equal(g, 2.0 * (A.astype(np.float64) - B.astype(np.float64)))
+    assert np.array_equal(d, orc.ed2(A, B, zip_=True))
+    g, d = orc.dtw_grad(A, A, 7, zip_=True)
+    assert np.all(g == 0.0) and np.all(d == 0.0)
+
+
+def test_grad_path_cost_is_dtw_and_path_is_valid(orc):
+    A = synth.random_series(4, 64, seed=83)
+    B = synth.random_series(4, 64, seed=84)
+    for W in (3, 9, 63):
+        for a, b in zip(A, B):
+            d, path = orc.dtw_path(a, b, W)
+            assert d == orc.dtw(a, b, W)[0, 0]
+            assert d == paths.path_cost(a, b, [tuple(x) for x in path])
+            assert tuple(path[0]) == (0, 0) and tuple(path[-1]) == (63, 63)
+            steps = np.diff(path, axis=0)
+            assert all(tuple(s) in ((1, 0), (0, 1), (1, 1)) for s in steps)
+            assert np.all(np.abs(path[:, 0] - path[:, 1]) <= W)
+
+
+def test_grad_exact_finite_differences(orc):
+    """Along a fixed path the cost is a quadratic in each a_i, so the central
+    difference with a step h that is exact in float32 equals the derivative;
+    checked wherever perturbing a_i by +-h leaves the path unchanged."""
+    rng = np.random.default_rng(85)
+    h = 2.0 ** -8
+    checked = 0
+    for L, W in ((16, 3), (24, 6), (32, 31)):
+        a = (np.round(rng.standard_normal(L) * 256) / 256).astype(np.float32)
+        b = (np.round(rng.standard_normal(L) * 256) / 256).astype(np.float32)
+        g, _ = orc.dtw_grad(a, b, W)
+        _, p0 = orc.dtw_path(a, b, W)
+        for i in range(L):
+            ap, am = a.copy(), a.copy()
+            ap[i] += np.float32(h)
+            am[i] -= np.float32(h)
+            dp, pp = orc.dtw_path(ap, b, W)
+            dm, pm = orc.dtw_path(am, b, W)
+            if np.array_equal(pp, p0) and np.array_equal(pm, p0):
+                assert abs((dp - dm) / (2 * h) - g[0, i]) <= 1e-9 * (1 + abs(g[0, i]))
+                checked += 1
+    assert checked >= 40
+
+
+def test_grad_is_linear_in_the_output_weights(orc):
+    A = synth.random_series(3, 48, seed=86)
+    B = synth.random_series(5, 48, seed=87)
+    w = np.random.default_rng(88).standard_normal((3, 5))
+    g, d = orc.dtw_grad(A, B, 5, gout=w)
+    assert np.array_equal(d, orc.dtw(A, B, 5))
+    for x in range(3):
+        want = np.zeros(48)
+        for y in range(5):
+            gy, _ = orc.dtw_grad(A[x], B[y], 5)
+            want += w[x, y] * gy[0]
+        assert np.allclose(g[x], want, rtol=1e-12, atol=1e-12)
