@@ -244,6 +244,36 @@ int nndtw_cascade_bounds(const nndtw_refset *refset, const float *Q, int64_t nQ,
                          double *lbe, void *stream);
 
 /* ------------------------------------------------------------------------
+ * DTW_W backward: gradient with respect to the query along the minimising
+ * warping path.  Equation (1) defines DTW_W as the minimum over warping paths
+ * of the path cost; where the minimising path P* is unique the cost is
+ * differentiable in A with dDTW/dA_i = sum over the cells (i, j) of P* of
+ * 2 (A_i - B_j).  P* is recovered from (L-1, L-1) by taking at every cell the
+ * first of (i-1,j-1), (i-1,j), (i,j-1) that attains the minimum (the order
+ * that also resolves exact ties).  Arrays as for nndtw_dtw_w; f64 = 1 runs
+ * the forward cells and the backward sums in FP64 (out, gout, gA double),
+ * f64 = 0 in FP32 (float).  Near-ties can make FP32 choose another path than
+ * FP64 with an equal cost up to FP32 rounding. */
+
+/* Bytes of the predecessor codes of np pairs (np = nA*nB cross, nA zip):
+ * one byte per (anti-diagonal pair, window diagonal pair) of each series pair. */
+int nndtw_dtw_codes_bytes(int64_t nA, int64_t nB, int32_t L, int32_t W, int32_t pairing,
+                          size_t *bytes);
+
+/* Forward: out = DTW_W per pair (no abandoning) and the predecessor codes
+ * (device, >= nndtw_dtw_codes_bytes bytes, layout private to the library). */
+int nndtw_dtw_w_codes(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L,
+                      int32_t W, int32_t pairing, int32_t f64, void *out, uint8_t *codes,
+                      size_t codes_bytes, void *stream);
+
+/* Backward: gA[a][i] = sum over the pairs (a, b) of gout[pair] * dDTW/dA_a[i]
+ * (cross: gout [nA][nB]; zip: gout [nA]), from the codes of the forward call
+ * with the same A, B, L, W, pairing and f64.  gA: device [nA][L]. */
+int nndtw_dtw_w_backward(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L,
+                         int32_t W, int32_t pairing, int32_t f64, const void *gout,
+                         const uint8_t *codes, size_t codes_bytes, void *gA, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched search over many independent reference sets of different lengths
  * (the search of Sections 1 and 4, per set exactly as nndtw_search with the
  * same options, R and shape): every set's bound pass runs in one kernel, its

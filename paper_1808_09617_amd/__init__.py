@@ -76,6 +76,9 @@ SIGNATURES = {
     "nndtw_lb_enhanced": (ctypes.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "nndtw_dtw_w": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _I32, _P, _P]),
     "nndtw_dtw_w_f64": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _I32, _P, _P]),
+    "nndtw_dtw_codes_bytes": (ctypes.c_int, [_I64, _I64, _I32, _I32, _I32, ctypes.POINTER(_SZ)]),
+    "nndtw_dtw_w_codes": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _SZ, _P]),
+    "nndtw_dtw_w_backward": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _SZ, _P, _P]),
     "nndtw_refset_bytes": (ctypes.c_int, [_I64, _I32, _I32, ctypes.POINTER(_SZ)]),
     "nndtw_refset_build": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _SZ, ctypes.POINTER(_Refset), _P]),
     "nndtw_search_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(_Refset), _I64,
@@ -193,6 +196,57 @@ def dtw_w(A, B, W: int, cutoff=None, zip_: bool = False, f64: bool = False):
     _check(fn(_ptr(A), A.shape[0], _ptr(B), B.shape[0], A.shape[1], int(W), _ptr(cut), int(zip_), _ptr(out),
               _stream()))
     return out
+
+
+def dtw_w_codes(A, B, W: int, zip_: bool = False, f64: bool = False):
+    """Forward DTW_W (no abandoning) plus the predecessor codes of every band
+    cell, for dtw_w_backward.  Returns (distances, codes uint8 tensor)."""
+    A, B = _series(A, "A"), _series(B, "B")
+    nA, nB, L = A.shape[0], B.shape[0], A.shape[1]
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().nndtw_dtw_codes_bytes(nA, nB, L, int(W), int(zip_), ctypes.byref(nbytes)))
+    codes = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=A.device)
+    out = torch.empty(_pair_shape(nA, nB, zip_), dtype=torch.float64 if f64 else torch.float32, device=A.device)
+    _check(lib().nndtw_dtw_w_codes(_ptr(A), nA, _ptr(B), nB, L, int(W), int(zip_), int(f64), _ptr(out),
+                                   _ptr(codes), codes.numel(), _stream()))
+    return out, codes
+
+
+def dtw_w_backward(A, B, W: int, gout, codes, zip_: bool = False, f64: bool = False):
+    """Gradient with respect to A: gA[a] = sum over pairs (a, b) of
+    gout[pair] * dDTW_W(a, b)/dA_a along the minimising warping path."""
+    A, B = _series(A, "A"), _series(B, "B")
+    dt = torch.float64 if f64 else torch.float32
+    g = gout.to(dt).contiguous()
+    if tuple(g.shape) != _pair_shape(A.shape[0], B.shape[0], zip_):
+        raise ValueError("gout has the wrong shape")
+    gA = torch.empty(A.shape, dtype=dt, device=A.device)
+    _check(lib().nndtw_dtw_w_backward(_ptr(A), A.shape[0], _ptr(B), B.shape[0], A.shape[1], int(W), int(zip_),
+                                      int(f64), _ptr(g), _ptr(codes), codes.numel(), _ptr(gA), _stream()))
+    return gA
+
+
+class DTWFunction(torch.autograd.Function):
+    """DTW_W(A, B) with its gradient with respect to the queries A (the
+    references B get none).  ``dtw(A, B, W)`` = DTWFunction.apply(A, B, W, zip_, f64)."""
+
+    @staticmethod
+    def forward(ctx, A, B, W, zip_=False, f64=False):
+        out, codes = dtw_w_codes(A.detach(), B.detach(), W, zip_, f64)
+        ctx.save_for_backward(A, B)
+        ctx.codes, ctx.W, ctx.zip_, ctx.f64 = codes, W, zip_, f64
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        A, B = ctx.saved_tensors
+        gA = dtw_w_backward(A.detach(), B.detach(), ctx.W, gout, ctx.codes, ctx.zip_, ctx.f64)
+        return gA.to(A.dtype), None, None, None, None
+
+
+def dtw(A, B, W: int, zip_: bool = False, f64: bool = False):
+    """Differentiable DTW_W (gradient with respect to A)."""
+    return DTWFunction.apply(A, B, W, zip_, f64)
 
 
 class RefSet:

@@ -323,6 +323,55 @@ int nndtw_cascade_bounds(const nndtw_refset *refset, const float *Q, int64_t nQ,
     return launch_cascade_bounds(refset, Q, nQ, V, ed2, lbk, lbe_bands, lbe, (hipStream_t)stream);
 }
 
+int nndtw_dtw_codes_bytes(int64_t nA, int64_t nB, int32_t L, int32_t W, int32_t pairing, size_t *bytes)
+{
+    g_err[0] = 0;
+    TRY(check_len_w(L, W));
+    TRY(check_pairing(pairing, nA, nB));
+    REQUIRE(bytes != nullptr, "bytes is NULL");
+    const int64_t np = pairing ? nA : nA * nB;
+    *bytes = np ? dtw_codes_bytes(np, L, W) : 0;
+    if (np && *bytes == 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
+    return NNDTW_OK;
+}
+
+static int grad_common(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L, int32_t W,
+                       int32_t pairing, int32_t f64, const void *p, const char *pname, const void *codes,
+                       size_t codes_bytes)
+{
+    TRY(check_len_w(L, W));
+    TRY(check_pairing(pairing, nA, nB));
+    REQUIRE(f64 == 0 || f64 == 1, "f64=%d must be 0 or 1", f64);
+    const int64_t np = pairing ? nA : nA * nB;
+    const bool any = np > 0;
+    TRY(check_ptr(A, 4, "A", any));
+    TRY(check_ptr(B, 4, "B", any));
+    TRY(check_ptr(p, f64 ? 8 : 4, pname, any));
+    TRY(check_ptr(codes, 1, "codes", any));
+    const size_t need = any ? dtw_codes_bytes(np, L, W) : 0;
+    REQUIRE(!any || need > 0, "window %d too wide for the DTW engine", W);
+    REQUIRE(codes_bytes >= need, "codes buffer too small: %zu bytes given, %zu needed", codes_bytes, need);
+    return NNDTW_OK;
+}
+
+int nndtw_dtw_w_codes(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L, int32_t W,
+                      int32_t pairing, int32_t f64, void *out, uint8_t *codes, size_t codes_bytes, void *stream)
+{
+    g_err[0] = 0;
+    TRY(grad_common(A, nA, B, nB, L, W, pairing, f64, out, "out", codes, codes_bytes));
+    return launch_dtw_codes(f64 != 0, A, nA, B, nB, L, W, pairing, out, codes, (hipStream_t)stream);
+}
+
+int nndtw_dtw_w_backward(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L, int32_t W,
+                         int32_t pairing, int32_t f64, const void *gout, const uint8_t *codes, size_t codes_bytes,
+                         void *gA, void *stream)
+{
+    g_err[0] = 0;
+    TRY(grad_common(A, nA, B, nB, L, W, pairing, f64, gout, "gout", codes, codes_bytes));
+    TRY(check_ptr(gA, f64 ? 8 : 4, "gA", nA > 0));
+    return launch_dtw_backward(f64 != 0, A, nA, B, nB, L, W, pairing, gout, codes, gA, (hipStream_t)stream);
+}
+
 // Prefix the current error text with the set it concerns.
 static int set_error(int status, int d)
 {

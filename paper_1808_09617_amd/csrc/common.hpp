@@ -54,6 +54,12 @@ int launch_batch_bounds(const BatchSet *sets, int nsets, const int64_t *tile_sta
 // dtw.hip
 int launch_dtw_pairs(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L,
                      int W, const double *cutoff, int pairing, void *out, hipStream_t s);
+// grad.hip
+size_t dtw_codes_bytes(int64_t np, int L, int W);
+int launch_dtw_codes(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L, int W, int pairing,
+                     void *out, uint8_t *codes, hipStream_t s);
+int launch_dtw_backward(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L, int W, int pairing,
+                        const void *gout, const uint8_t *codes, void *gA, hipStream_t s);
 // search.hip
 struct SearchPlan {
     int Wp, C, G, P, PD, SLOTS, NW, exact, T, LEN;

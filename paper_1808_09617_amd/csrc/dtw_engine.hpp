@@ -163,6 +163,25 @@ template <typename T> struct TaskOut {
     double slack = 1.0;
 };
 
+// Optional per-cell record of the minimising predecessor (for the argmin
+// warping path): codes(task) is the task's byte array [T][W'+1]; byte
+// (t, p) holds the code of pair p's bottom cell at super-step t in bits 0-1
+// and of its top cell in bits 2-3: 0 = (i-1, j-1), 1 = (i-1, j),
+// 2 = (i, j-1), the first of them that attains the minimum.
+struct NoCodes {
+    static constexpr bool on = false;
+    __device__ uint8_t *operator()(int) const { return nullptr; }
+};
+
+__device__ __forceinline__ unsigned argmin_code(float dg, float up, float lf)
+{
+    return dg <= __builtin_fminf(up, lf) ? 0u : (up <= lf ? 1u : 2u);
+}
+__device__ __forceinline__ unsigned argmin_code(double dg, double up, double lf)
+{
+    return dg <= __builtin_fmin(up, lf) ? 0u : (up <= lf ? 1u : 2u);
+}
+
 // Run `ntasks` DTW tasks on the P groups of each calling wave.  Tasks are
 // dealt from the LDS counter *next_task (0 before the call, shared by every
 // wave of the workgroup that takes part).  Task i compares the rows arow(i)
@@ -175,9 +194,10 @@ template <typename T> struct TaskOut {
 // boundaries are multiples of M in every group, which keeps the register
 // rotation of the windows the same in all groups.  Whole-wave call with
 // uniform arguments; ntasks >= 1.
-template <typename T, int C, int D, int M, bool EXACT, typename ARow, typename BRow, typename Thr>
+template <typename T, int C, int D, int M, bool EXACT, typename ARow, typename BRow, typename Thr,
+          typename Codes = NoCodes>
 __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, int *next_task, ARow arow, BRow brow,
-                                           Thr thr_of, TaskOut<T> out)
+                                           Thr thr_of, TaskOut<T> out, Codes codes_of = Codes())
 {
     static_assert(M >= C + D, "window smaller than the live values");
     const int lane = threadIdx.x & (WAVE - 1);
@@ -213,6 +233,8 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
 
     int task = -1, tl = 0;
     bool dead = true, exhausted = false;
+    uint8_t *cb = nullptr;                           // this lane's codes of super-step 0 (Codes::on)
+    const int cpitch = Wp + 1;
     T thr = INF;
     while (true) {
         // retire the tasks that ended
@@ -249,6 +271,7 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
                 dead = false;
                 aP = arow(task) + Stage<C>::PADL + glc;
                 bP = brow(task) + Stage<C>::PADL + Wp - glc;
+                if constexpr (Codes::on) cb = codes_of(task) + glc;
 #pragma unroll
                 for (int m = 0; m < C; ++m) {
                     const int p = glc + m;           // global pair index
@@ -272,10 +295,13 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
         for (int u = 0; u < M; ++u) {
             // bottom diagonals: anti-diagonal s_b(t)
             const T nb = from_lower(X1[C - 1]);
+            unsigned code[C];
 #pragma unroll
             for (int m = 0; m < C; ++m) {
                 const T lo = (m == 0) ? nb : X1[m - 1];
                 const T d = Aw[(u + m) % M] - Bw[(u - m + M) % M];
+                // predecessors: (i-1,j-1) = X0[m], (i-1,j) = lo, (i,j-1) = X1[m]
+                if constexpr (Codes::on) code[m] = argmin_code(X0[m], lo, X1[m]);
                 X0[m] = cell(d, min3(X0[m], lo, X1[m]));
             }
             // top diagonals: anti-diagonal s_b(t) + 1
@@ -284,7 +310,16 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
             for (int m = 0; m < C; ++m) {
                 const T hi = (m == C - 1) ? nt : X0[m + 1];
                 const T d = Aw[(u + m + 1) % M] - Bw[(u - m + M) % M];
+                // predecessors: (i-1,j-1) = X1[m], (i-1,j) = X0[m], (i,j-1) = hi
+                if constexpr (Codes::on) code[m] |= argmin_code(X1[m], X0[m], hi) << 2;
                 X1[m] = cell(d, min3(X1[m], X0[m], hi));
+            }
+            if constexpr (Codes::on) {
+                if (task >= 0) {
+#pragma unroll
+                    for (int m = 0; m < C; ++m)
+                        if (glc + m <= Wp) cb[(int64_t)(tl + u) * cpitch + m] = (uint8_t)code[m];
+                }
             }
             if (EXACT) {
                 X1[C - 1] = force_last ? INF : X1[C - 1];

@@ -404,3 +404,127 @@ def test_batch_full_workload_sampled():
         oi, od, oc = oracle.search(ds.refs, ds.queries[:2], ds.W, 5, "keogh_enh", bsr.R[d], True)
         gi, gd, gc = res[d]
         assert np.array_equal(gi[:2], oi) and np.array_equal(gd[:2], od) and np.array_equal(gc[:2, :5], oc[:, :5])
+
+
+# ------------------------------------------------------------------ DTW backward
+@pytest.mark.parametrize("L,W", [(2, 1), (17, 0), (17, 4), (64, 6), (64, 63), (256, 26), (300, 100)])
+def test_dtw_backward_f64_matches_oracle(L, W):
+    """FP64 forward with codes: distances bit-exact; the gradient with respect
+    to the queries equal to the oracle's up to the order of its sums."""
+    A = series(9, L, seed=1300 + L + W)
+    B = series(7, L, seed=1400 + L + W)
+    w = np.random.default_rng(L + W).standard_normal((9, 7))
+    say("backward f64", L, W)
+    out, codes = nd.dtw_w_codes(dev(A), dev(B), W, f64=True)
+    assert np.array_equal(host(out), oracle.dtw(A, B, W))
+    g = host(nd.dtw_w_backward(dev(A), dev(B), W, torch.from_numpy(w).to(DEV), codes, f64=True))
+    og, od = oracle.dtw_grad(A, B, W, gout=w)
+    assert np.allclose(g, og, rtol=1e-12, atol=1e-12 * np.abs(og).max())
+
+
+def test_dtw_backward_tie_order_on_integer_series():
+    """Exact ties between predecessors (integer-valued series) are broken in
+    the oracle's order: (i-1,j-1), then (i-1,j), then (i,j-1)."""
+    rng = np.random.default_rng(1500)
+    for L, W in ((6, 2), (12, 4), (40, 7)):
+        A = rng.integers(0, 3, (30, L)).astype(np.float32)
+        B = rng.integers(0, 3, (30, L)).astype(np.float32)
+        for f64 in (True, False):
+            out, codes = nd.dtw_w_codes(dev(A), dev(B), W, zip_=True, f64=f64)
+            g = host(nd.dtw_w_backward(dev(A), dev(B), W, torch.ones(30, device=DEV), codes, zip_=True, f64=f64))
+            og, od = oracle.dtw_grad(A, B, W, zip_=True)
+            assert np.array_equal(host(out).astype(np.float64), od)   # small integers: exact in FP32 too
+            assert np.array_equal(g.astype(np.float64), og)
+
+
+def test_dtw_backward_f32_against_f64():
+    """FP32 codes follow the FP64 path except where two paths cost the same
+    up to FP32 rounding; such pairs are rare and their costs are checked."""
+    L, W = 256, 26
+    A = series(400, L, seed=1600, kind="sin5")
+    B = series(400, L, seed=1601, kind="sin5")
+    ones = torch.ones(400, device=DEV)
+    o32, c32 = nd.dtw_w_codes(dev(A), dev(B), W, zip_=True)
+    g32 = host(nd.dtw_w_backward(dev(A), dev(B), W, ones, c32, zip_=True))
+    og, od = oracle.dtw_grad(A, B, W, zip_=True)
+    assert np.all(np.abs(host(o32) - od) <= 1e-5 * od)
+    scale = np.abs(og).max(1, keepdims=True) + 1e-30
+    same = np.all(np.abs(g32 - og) <= 1e-4 * scale, axis=1)
+    assert same.mean() >= 0.98, same.mean()
+    for k in np.nonzero(~same)[0]:
+        # the FP32 path is another optimum: the gradient differs, the cost does not
+        assert abs(float(host(o32)[k]) - od[k]) <= 4 * oracle.slack(L) * od[k]
+
+
+def test_dtw_autograd_function():
+    L, W = 64, 6
+    A = series(5, L, seed=1700)
+    B = series(3, L, seed=1701)
+    w = np.random.default_rng(1702).standard_normal((5, 3))
+    At = dev(A).requires_grad_(True)
+    loss = (nd.dtw(At, dev(B), W, f64=True) * torch.from_numpy(w).to(DEV)).sum()
+    loss.backward()
+    og, _ = oracle.dtw_grad(A, B, W, gout=w)
+    assert At.grad.dtype == torch.float32
+    assert np.allclose(host(At.grad), og, rtol=1e-6, atol=1e-6 * np.abs(og).max())
+
+
+def test_dtw_backward_finite_differences_on_gpu():
+    """Central differences of the GPU's FP64 DTW_W with a step exact in
+    float32 equal the GPU gradient wherever the path does not change."""
+    rng = np.random.default_rng(1800)
+    L, W = 48, 5
+    A = (np.round(rng.standard_normal((4, L)) * 256) / 256).astype(np.float32)
+    B = (np.round(rng.standard_normal((4, L)) * 256) / 256).astype(np.float32)
+    h = np.float32(2.0 ** -8)
+    _, codes = nd.dtw_w_codes(dev(A), dev(B), W, zip_=True, f64=True)
+    g = host(nd.dtw_w_backward(dev(A), dev(B), W, torch.ones(4, device=DEV, dtype=torch.float64), codes,
+                                zip_=True, f64=True))
+    agree = 0
+    for i in range(L):
+        Ap, Am = A.copy(), A.copy()
+        Ap[:, i] += h
+        Am[:, i] -= h
+        dp = host(nd.dtw_w(dev(Ap), dev(B), W, zip_=True, f64=True))
+        dm = host(nd.dtw_w(dev(Am), dev(B), W, zip_=True, f64=True))
+        fd = (dp - dm) / (2 * float(h))
+        for k in range(4):
+            _, p0 = oracle.dtw_path(A[k], B[k], W)
+            _, pp = oracle.dtw_path(Ap[k], B[k], W)
+            _, pm = oracle.dtw_path(Am[k], B[k], W)
+            if np.array_equal(p0, pp) and np.array_equal(p0, pm):
+                assert abs(fd[k] - g[k, i]) <= 1e-9 * (1 + abs(g[k, i]))
+                agree += 1
+    assert agree >= 0.8 * 4 * L
+
+
+def test_dtw_backward_full_config():
+    """256 queries x 256 references, L=256, W=26 (cross) in the benchmarked
+    launch shape.  FP32: all distances within 1e-5 of FP64; per pair of the
+    sampled queries, the gradient equals the oracle's or the FP32 path is
+    another optimum up to FP32 rounding (a near-tie; at most 2 % of pairs).
+    FP64: sampled queries' gradients equal the oracle's."""
+    L, W = 256, 26
+    A = series(256, L, seed=1900, kind="sin5")
+    B = series(256, L, seed=1901, kind="sin5")
+    w = np.random.default_rng(1902).standard_normal((256, 256))
+    say("backward full 256x256")
+    out, codes = nd.dtw_w_codes(dev(A), dev(B), W)
+    nd.dtw_w_backward(dev(A), dev(B), W, torch.from_numpy(w).to(DEV), codes)
+    d64 = oracle.dtw(A, B, W)
+    assert np.all(np.abs(host(out) - d64) <= 1e-5 * d64)
+    sel = np.arange(0, 256, 37)
+    og, _ = oracle.dtw_grad(A[sel], B, W, gout=w[sel])
+    out64, codes64 = nd.dtw_w_codes(dev(A), dev(B), W, f64=True)
+    assert np.array_equal(host(out64), d64)
+    g64 = host(nd.dtw_w_backward(dev(A), dev(B), W, torch.from_numpy(w).to(DEV), codes64, f64=True))
+    assert np.allclose(g64[sel], og, rtol=1e-10, atol=1e-10 * np.abs(og).max())
+    # per pair, FP32, the sampled queries against every reference
+    Az, Bz = np.repeat(A[sel], 256, 0), np.tile(B, (len(sel), 1))
+    oz, cz = nd.dtw_w_codes(dev(Az), dev(Bz), W, zip_=True)
+    gz = host(nd.dtw_w_backward(dev(Az), dev(Bz), W, torch.ones(len(Az), device=DEV), cz, zip_=True))
+    ogz, odz = oracle.dtw_grad(Az, Bz, W, zip_=True)
+    same = np.all(np.abs(gz - ogz) <= 1e-4 * (np.abs(ogz).max(1, keepdims=True) + 1e-30), axis=1)
+    assert same.mean() >= 0.98, same.mean()
+    oz = host(oz)
+    assert np.all(np.abs(oz[~same] - odz[~same]) <= 4 * oracle.slack(L) * odz[~same])
