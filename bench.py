@@ -140,6 +140,46 @@ def hbm_streaming(nd, synth, torch, dev):
     return out
 
 
+def backward_bench(nd, synth, torch, dev, reps=5, cpu=True):
+    """DTW_W forward with argmin codes and the backward (gradient with
+    respect to the queries) for 256 queries x 256 references, L=256, W=26,
+    FP32, inputs resident; the oracle's FP64 gradient timed on a sample."""
+    L, W = 256, 26
+    A = torch.from_numpy(synth.random_series(256, L, seed=1900, kind="sin5")).to(dev)
+    B = torch.from_numpy(synth.random_series(256, L, seed=1901, kind="sin5")).to(dev)
+    g = torch.randn(256, 256, device=dev)
+    out, codes = nd.dtw_w_codes(A, B, W)
+    nd.dtw_w_backward(A, B, W, g, codes)
+    torch.cuda.synchronize()
+    tf, tb = [], []
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        out, codes = nd.dtw_w_codes(A, B, W)
+        e[1].record()
+        nd.dtw_w_backward(A, B, W, g, codes)
+        e[2].record()
+        e[2].synchronize()
+        tf.append(e[0].elapsed_time(e[1]) / 1e3)
+        tb.append(e[1].elapsed_time(e[2]) / 1e3)
+    tf, tb = sorted(tf)[reps // 2], sorted(tb)[reps // 2]
+    cells = 256 * 256 * (L * (2 * W + 1) - W * (W + 1))
+    res = {"config": "256 x 256 pairs, L=256, W=26, fp32", "forward_ms": tf * 1e3, "backward_ms": tb * 1e3,
+           "pairs_per_s": 65536 / (tf + tb), "forward_cells_per_s": cells / tf,
+           "forward_valu_frac": 3.0 * cells / tf / VALU_PEAK_OPS, "codes_bytes": int(codes.numel())}
+    if cpu:
+        import oracle
+        a, b = A[:4].cpu().numpy(), B.cpu().numpy()
+        t = time.perf_counter()
+        oracle.dtw_grad(a, b, W, gout=g[:4].double().cpu().numpy())
+        dt = time.perf_counter() - t
+        res["cpu_oracle"] = {"pairs_per_s": 4 * 256 / dt, "cores": oracle.max_threads(),
+                             "sample": "4 queries x 256 references, FP64 full matrix + backtrack"}
+    del codes, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def batch_bench(nd, synth, torch, dev, reps=3, tuned=None):
     """The batching workload (64 random-walk sets, L 25..1839, 26,583 queries,
     W = 0.1 L, V = 5) as one captured graph of the batched search, inputs
@@ -347,6 +387,7 @@ def main():
             tight[f"enhanced{v}"] = float((nd.lb_enhanced(A, B, U, Lo, W, v, zip_=True)[keep] / d[keep]).mean())
         res["tightness"] = tight
         res["hbm_streaming"] = hbm_streaming(nd, synth, torch, dev)
+        res["backward"] = backward_bench(nd, synth, torch, dev, cpu=not args.no_cpu)
         res["batch"] = batch_bench(nd, synth, torch, dev)
         res["batch_tuned"] = batch_bench(nd, synth, torch, dev, tuned="auto")
         log("extras done")

@@ -255,8 +255,11 @@ int nndtw_cascade_bounds(const nndtw_refset *refset, const float *Q, int64_t nQ,
  * f64 = 0 in FP32 (float).  Near-ties can make FP32 choose another path than
  * FP64 with an equal cost up to FP32 rounding. */
 
-/* Bytes of the predecessor codes of np pairs (np = nA*nB cross, nA zip):
- * one byte per (anti-diagonal pair, window diagonal pair) of each series pair. */
+/* Bytes of the buffer for the predecessor codes of np pairs (np = nA*nB
+ * cross, nA zip): four bits per (anti-diagonal pair, window diagonal pair)
+ * of each series pair and padded copies of A and B (codes: 256-byte
+ * aligned device memory).  EUNSUP for
+ * min(W, L-1) + 1 > 756. */
 int nndtw_dtw_codes_bytes(int64_t nA, int64_t nB, int32_t L, int32_t W, int32_t pairing,
                           size_t *bytes);
 
@@ -268,7 +271,9 @@ int nndtw_dtw_w_codes(const float *A, int64_t nA, const float *B, int64_t nB, in
 
 /* Backward: gA[a][i] = sum over the pairs (a, b) of gout[pair] * dDTW/dA_a[i]
  * (cross: gout [nA][nB]; zip: gout [nA]), from the codes of the forward call
- * with the same A, B, L, W, pairing and f64.  gA: device [nA][L]. */
+ * with the same A, B, L, W, pairing and f64.  gA: device [nA][L].  With
+ * cross pairing the sum over references runs in an unspecified order (the
+ * last bits of FP32 results may vary between runs). */
 int nndtw_dtw_w_backward(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L,
                          int32_t W, int32_t pairing, int32_t f64, const void *gout,
                          const uint8_t *codes, size_t codes_bytes, void *gA, void *stream);

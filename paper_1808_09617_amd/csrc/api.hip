@@ -330,7 +330,7 @@ int nndtw_dtw_codes_bytes(int64_t nA, int64_t nB, int32_t L, int32_t W, int32_t 
     TRY(check_pairing(pairing, nA, nB));
     REQUIRE(bytes != nullptr, "bytes is NULL");
     const int64_t np = pairing ? nA : nA * nB;
-    *bytes = np ? dtw_codes_bytes(np, L, W) : 0;
+    *bytes = np ? dtw_codes_bytes(nA, nB, L, W, pairing) : 0;
     if (np && *bytes == 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
     return NNDTW_OK;
 }
@@ -347,8 +347,8 @@ static int grad_common(const float *A, int64_t nA, const float *B, int64_t nB, i
     TRY(check_ptr(A, 4, "A", any));
     TRY(check_ptr(B, 4, "B", any));
     TRY(check_ptr(p, f64 ? 8 : 4, pname, any));
-    TRY(check_ptr(codes, 1, "codes", any));
-    const size_t need = any ? dtw_codes_bytes(np, L, W) : 0;
+    TRY(check_ptr(codes, 256, "codes", any));
+    const size_t need = any ? dtw_codes_bytes(nA, nB, L, W, pairing) : 0;
     REQUIRE(!any || need > 0, "window %d too wide for the DTW engine", W);
     REQUIRE(codes_bytes >= need, "codes buffer too small: %zu bytes given, %zu needed", codes_bytes, need);
     return NNDTW_OK;

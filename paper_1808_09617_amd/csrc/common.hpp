@@ -55,7 +55,7 @@ int launch_batch_bounds(const BatchSet *sets, int nsets, const int64_t *tile_sta
 int launch_dtw_pairs(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L,
                      int W, const double *cutoff, int pairing, void *out, hipStream_t s);
 // grad.hip
-size_t dtw_codes_bytes(int64_t np, int L, int W);
+size_t dtw_codes_bytes(int64_t nA, int64_t nB, int L, int W, int pairing);
 int launch_dtw_codes(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L, int W, int pairing,
                      void *out, uint8_t *codes, hipStream_t s);
 int launch_dtw_backward(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L, int W, int pairing,

@@ -164,13 +164,14 @@ template <typename T> struct TaskOut {
 };
 
 // Optional per-cell record of the minimising predecessor (for the argmin
-// warping path): codes(task) is the task's byte array [T][W'+1]; byte
-// (t, p) holds the code of pair p's bottom cell at super-step t in bits 0-1
-// and of its top cell in bits 2-3: 0 = (i-1, j-1), 1 = (i-1, j),
-// 2 = (i, j-1), the first of them that attains the minimum.
+// warping path): codes(task) is the task's word array [T/8][W'+1]; the
+// nibble 4*(t%8) of word (t/8, p) holds the code of pair p's bottom cell at
+// super-step t in its bits 0-1 and of its top cell in bits 2-3:
+// 0 = (i-1, j-1), 1 = (i-1, j), 2 = (i, j-1), the first of them that
+// attains the minimum.  Needs M % 8 == 0 (then T % 8 == 0 too).
 struct NoCodes {
     static constexpr bool on = false;
-    __device__ uint8_t *operator()(int) const { return nullptr; }
+    __device__ uint32_t *operator()(int) const { return nullptr; }
 };
 
 __device__ __forceinline__ unsigned argmin_code(float dg, float up, float lf)
@@ -233,8 +234,12 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
 
     int task = -1, tl = 0;
     bool dead = true, exhausted = false;
-    uint8_t *cb = nullptr;                           // this lane's codes of super-step 0 (Codes::on)
+    static_assert(!Codes::on || M % 8 == 0, "codes need blocks of whole words");
+    uint32_t *cb = nullptr;                          // this lane's code words (Codes::on)
     const int cpitch = Wp + 1;
+    uint32_t cw[C];
+#pragma unroll
+    for (int m = 0; m < C; ++m) cw[m] = 0u;
     T thr = INF;
     while (true) {
         // retire the tasks that ended
@@ -315,10 +320,16 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
                 X1[m] = cell(d, min3(X1[m], X0[m], hi));
             }
             if constexpr (Codes::on) {
-                if (task >= 0) {
 #pragma unroll
-                    for (int m = 0; m < C; ++m)
-                        if (glc + m <= Wp) cb[(int64_t)(tl + u) * cpitch + m] = (uint8_t)code[m];
+                for (int m = 0; m < C; ++m) cw[m] |= code[m] << (4 * (u % 8));
+                if (u % 8 == 7) {
+                    if (task >= 0) {
+#pragma unroll
+                        for (int m = 0; m < C; ++m)
+                            if (glc + m <= Wp) cb[(int64_t)((tl + u) / 8) * cpitch + m] = cw[m];
+                    }
+#pragma unroll
+                    for (int m = 0; m < C; ++m) cw[m] = 0u;
                 }
             }
             if (EXACT) {

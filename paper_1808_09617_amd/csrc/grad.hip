@@ -5,86 +5,126 @@
 //     dDTW/dA_i = sum over the cells (i, j) of P* of 2 (A_i - B_j).
 //
 // Two kernels:
-//   1. forward: the DTW engine without abandoning, recording for every band
+//   1. forward: the DTW engine of the search (rows streamed from padded
+//      copies kept in the caller's code buffer) without abandoning, recording for every band
 //      cell which predecessor attains the minimum (first of (i-1,j-1),
-//      (i-1,j), (i,j-1), the order that also resolves exact ties), one byte
-//      per (super-step, diagonal pair) and series pair;
+//      (i-1,j), (i,j-1), the order that also resolves exact ties), four bits
+//      per (super-step, diagonal pair) and series pair, packed in 32-bit
+//      words of 8 super-steps (one store per 8 super-steps and slot);
 //   2. backtrack: from (L-1, L-1) the recorded predecessors lead back to
 //      (0, 0); every cell adds gout * 2 (A_i - B_j) to the query's gradient.
-//      One workgroup per query (cross pairing): its threads walk the paths of
-//      different references and accumulate into an LDS row with atomics.
+//      Cross pairing: one workgroup per query, its threads walk the paths of
+//      different references and add into an LDS row with atomics (the order
+//      of the additions, hence the last bits of an FP32 sum, varies from run
+//      to run); zip pairing: one thread per pair.
 #include "dtw_engine.hpp"
 
 namespace nndtw {
 
 namespace {
 
-// Codes geometry: the engine shape of the forward pass (LDS-staged rows) and
-// the bytes per series pair (T rows of W'+1 pairs, rounded up to 16).
+// Forward geometry: the engine shape of the search (rows streamed from
+// padded global copies, blocks of M super-steps rounded up to a multiple of
+// 8 for whole code words) and the buffer layout: padded copies of A and B,
+// then the code words, 32-bit words per series pair (T/8 rows of W'+1 pairs,
+// rounded up to 4).
 struct CodesGeom {
     EngineGeom g;
-    int64_t pitch;
+    int padl;
+    int64_t ppitch;      // floats per padded row
+    int64_t pitch;       // code words per series pair
+    size_t offA, offB, offC, total;
 };
 
-int codes_geom(int L, int W, CodesGeom *cg)
+// Prefetch distance and block length (a multiple of 8): FP32 fills a block
+// of 8 with prefetch for up to 6 pairs per lane; FP64 keeps the short
+// prefetch (double windows cost two registers per value).
+__host__ __device__ constexpr int codes_prefetch(bool f64, int C)
+{
+    return f64 ? prefetch_lds(C) : (C <= 6 ? 8 - C : prefetch_global(C));
+}
+__host__ __device__ constexpr int codes_window(bool f64, int C) { return (C + codes_prefetch(f64, C) + 7) / 8 * 8; }
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int codes_geom(int64_t nA, int64_t nB, int L, int W, int pairing, bool f64, CodesGeom *cg)
 {
     const int Wp = W < L - 1 ? W : L - 1;
-    const int C = choose_cpl(Wp, 16, 0);
+    const int C = choose_cpl(Wp, 4, 0, 12);
     if (C < 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
-    cg->g = make_geom(L, W, C, prefetch_lds(C), window_lds(C));
-    cg->pitch = ((int64_t)cg->g.T * (Wp + 1) + 15) / 16 * 16;
+    cg->g = make_geom(L, W, C, codes_prefetch(f64, C), codes_window(f64, C));
+    cg->padl = padded_row_margin_left(Wp);
+    cg->ppitch = ((int64_t)cg->padl + L + padded_row_margin_right(Wp) + 63) / 64 * 64;
+    const int64_t boff = cg->padl + cg->g.base0 - C;
+    if (boff < 0 || boff + cg->g.LEN > cg->ppitch)
+        return fail(NNDTW_EUNSUP, "row margins too narrow for the DTW engine shape");
+    cg->pitch = ((int64_t)(cg->g.T / 8) * (Wp + 1) + 3) / 4 * 4;
+    const int64_t np = pairing ? nA : nA * nB;
+    size_t o = 0;
+    cg->offA = o; o = al256(o + (size_t)nA * cg->ppitch * 4);
+    cg->offB = o; o = al256(o + (size_t)nB * cg->ppitch * 4);
+    cg->offC = o; o = al256(o + (size_t)np * cg->pitch * 4);
+    cg->total = o;
     return NNDTW_OK;
 }
 
 struct CodesAt {
     static constexpr bool on = true;
-    uint8_t *base;
+    uint32_t *base;
     int64_t pitch, first;
-    __device__ uint8_t *operator()(int i) const { return base + (first + i) * pitch; }
+    __device__ uint32_t *operator()(int i) const { return base + (first + i) * pitch; }
 };
+
+constexpr int CODES_WAVES = 4;
 
 }  // namespace
 
+// One workgroup of CODES_WAVES waves per K consecutive series pairs: the
+// rows of both series are read from their padded copies (L2-resident), the
+// pairs are dealt to the groups of all waves from an LDS counter, and every
+// band cell's predecessor code is written to the pair's code words.
 template <typename T, int C, bool EXACT>
-__global__ void __launch_bounds__(WAVE)
-dtw_codes_kernel(EngineGeom geo, int NB, const float *__restrict__ A, int64_t nA, const float *__restrict__ B,
-                 int64_t nB, int pairing, T *__restrict__ out, uint8_t *__restrict__ codes, int64_t cpitch)
+__global__ void __launch_bounds__(WAVE * CODES_WAVES)
+dtw_codes_kernel(EngineGeom geo, int K, int64_t np, int64_t nB, int pairing, const float *__restrict__ Ap,
+                 const float *__restrict__ Bp, int64_t ppitch, int padl, T *__restrict__ out,
+                 uint32_t *__restrict__ codes, int64_t cpitch)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    T *aR = reinterpret_cast<T *>(smem);
-    T *bR = aR + (size_t)NB * geo.LEN;
-    T *res = bR + (size_t)NB * geo.LEN;
-    int *trun = reinterpret_cast<int *>(res + NB);
-    int *next_task = trun + NB;
-    const int lane = threadIdx.x;
-    const int LEN = geo.LEN;
-    const int64_t np = pairing ? nA : nA * nB;
-    for (int64_t base = (int64_t)blockIdx.x * NB; base < np; base += (int64_t)gridDim.x * NB) {
-        const int nt = (int)((np - base) < NB ? (np - base) : NB);
-        stage_rows<T, C>(aR, A, [&](int i) { const int64_t p = base + i; return pairing ? p : p / nB; }, nt, geo,
-                         lane);
-        stage_rows<T, C>(bR, B, [&](int i) { const int64_t p = base + i; return pairing ? p : p % nB; }, nt, geo,
-                         lane);
-        if (lane == 0) *next_task = 0;
-        __syncthreads();
-        engine_run<T, C, prefetch_lds(C), window_lds(C), EXACT>(
-            geo, nt, next_task, [&](int i) { return (const T *)(aR + (size_t)i * LEN); },
-            [&](int i) { return (const T *)(bR + (size_t)i * LEN); }, [&](int) { return inf_of<T>(); },
-            TaskOut<T>{res, trun}, CodesAt{codes, cpitch, base});
-        __syncthreads();
-        if (lane < nt) out[base + lane] = res[lane];
-        __syncthreads();
-    }
+    T *res = reinterpret_cast<T *>(smem);
+    int *trun = reinterpret_cast<int *>(res + K);
+    int *next_task = trun + K;
+    const int64_t p0 = (int64_t)blockIdx.x * K;
+    const int nt = (int)((np - p0) < K ? (np - p0) : K);
+    // element e of a row the engine sees is series index base0 - PADL + e
+    const int64_t off = padl + geo.base0 - Stage<C>::PADL;
+    if (threadIdx.x == 0) *next_task = 0;
+    __syncthreads();
+    constexpr bool F64 = sizeof(T) == 8;
+    engine_run<T, C, codes_prefetch(F64, C), codes_window(F64, C), EXACT>(
+        geo, nt, next_task,
+        [&](int i) {
+            const int64_t p = p0 + i;
+            return Ap + (pairing ? p : p / nB) * ppitch + off;
+        },
+        [&](int i) {
+            const int64_t p = p0 + i;
+            return Bp + (pairing ? p : p % nB) * ppitch + off;
+        },
+        [&](int) { return inf_of<T>(); }, TaskOut<T>{res, trun}, CodesAt{codes, cpitch, p0});
+    __syncthreads();
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) out[p0 + i] = res[i];
 }
 
 // Walk back one pair's path, calling add(i, j) for every cell from (L-1,L-1)
 // to (0,0).  The bounds tests only guard memory against corrupt codes.
 template <typename Add>
-__device__ __forceinline__ void walk_path(const EngineGeom &geo, const uint8_t *__restrict__ codes, Add add)
+__device__ __forceinline__ void walk_path(const EngineGeom &geo, const uint32_t *__restrict__ codes, Add add)
 {
     const int L = geo.L, Wp = geo.Wp;
     const int s_start = 2 * geo.base0 + Wp;
     int i = L - 1, j = L - 1;
+    int64_t widx = -1;                           // index of the code word held in `word`
+    uint32_t word = 0u;
     for (int step = 0; step < 2 * L - 1; ++step) {
         add(i, j);
         if (i == 0 && j == 0) break;
@@ -92,7 +132,13 @@ __device__ __forceinline__ void walk_path(const EngineGeom &geo, const uint8_t *
         const int p = k >> 1, top = k & 1;
         const int t = (i + j - top - s_start) >> 1;
         if (t < 0 || t >= geo.T || p > Wp) break;
-        const unsigned c = (codes[(int64_t)t * (Wp + 1) + p] >> (top ? 2 : 0)) & 3u;
+        // consecutive steps mostly stay in one word (8 super-steps of a pair)
+        const int64_t wi = (int64_t)(t >> 3) * (Wp + 1) + p;
+        if (wi != widx) {
+            widx = wi;
+            word = codes[wi];
+        }
+        const unsigned c = (word >> (4 * (t & 7) + (top ? 2 : 0))) & 3u;
         if (c == 0) { --i; --j; }
         else if (c == 1) { --i; }
         else { --j; }
@@ -107,7 +153,7 @@ constexpr int BT_THREADS = 256;
 template <typename T>
 __global__ void __launch_bounds__(BT_THREADS)
 dtw_backtrack_kernel(EngineGeom geo, const float *__restrict__ A, int64_t nA, const float *__restrict__ B,
-                     int64_t nB, int pairing, const T *__restrict__ gout, const uint8_t *__restrict__ codes,
+                     int64_t nB, int pairing, const T *__restrict__ gout, const uint32_t *__restrict__ codes,
                      int64_t cpitch, T *__restrict__ gA)
 {
     const int L = geo.L;
@@ -137,45 +183,43 @@ dtw_backtrack_kernel(EngineGeom geo, const float *__restrict__ A, int64_t nA, co
     for (int i = threadIdx.x; i < L; i += BT_THREADS) gA[q * L + i] = acc[i];
 }
 
-size_t dtw_codes_bytes(int64_t np, int L, int W)
+size_t dtw_codes_bytes(int64_t nA, int64_t nB, int L, int W, int pairing)
 {
-    CodesGeom cg;
-    if (codes_geom(L, W, &cg)) return 0;
-    return (size_t)(np * cg.pitch);
+    // the larger of the two precisions' layouts (they differ in T only)
+    CodesGeom cg, cd;
+    if (codes_geom(nA, nB, L, W, pairing, false, &cg) || codes_geom(nA, nB, L, W, pairing, true, &cd)) return 0;
+    return cg.total > cd.total ? cg.total : cd.total;
 }
 
-static size_t codes_lds(const EngineGeom &g, int NB, size_t esz)
-{
-    return (size_t)2 * NB * g.LEN * esz + (size_t)NB * (esz + sizeof(int)) + 32;
-}
 
 template <typename T>
 static int launch_codes_t(const float *A, int64_t nA, const float *B, int64_t nB, int L, int W, int pairing, T *out,
-                          uint8_t *codes, hipStream_t st)
+                          uint8_t *buf, hipStream_t st)
 {
     const int64_t np = pairing ? nA : nA * nB;
     if (np == 0) return NNDTW_OK;
     CodesGeom cg;
-    if (int r = codes_geom(L, W, &cg)) return r;
-    EngineGeom g = cg.g;
-    int NB = 2 * g.P < 64 ? 2 * g.P : 64;
-    while (NB > 1 && codes_lds(g, NB, sizeof(T)) > 64 * 1024) --NB;
-    if (NB < g.P) g.P = NB;
-    const size_t lds = codes_lds(g, NB, sizeof(T));
-    if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the DTW engine", L);
-    int64_t blocks = ceil_div(np, NB);
-    if (blocks > 256 * 16) blocks = 256 * 16;
-    switch (g.C) {
-#define X(c)                                                                                                  \
-    case c:                                                                                                   \
-        if (g.exact)                                                                                          \
-            hipLaunchKernelGGL((dtw_codes_kernel<T, c, true>), dim3((unsigned)blocks), dim3(WAVE), lds, st, g, NB, \
-                               A, nA, B, nB, pairing, out, codes, cg.pitch);                                  \
-        else                                                                                                  \
-            hipLaunchKernelGGL((dtw_codes_kernel<T, c, false>), dim3((unsigned)blocks), dim3(WAVE), lds, st, g, NB, \
-                               A, nA, B, nB, pairing, out, codes, cg.pitch);                                  \
+    if (int r = codes_geom(nA, nB, L, W, pairing, sizeof(T) == 8, &cg)) return r;
+    const EngineGeom &g = cg.g;
+    float *Ap = (float *)(buf + cg.offA), *Bp = (float *)(buf + cg.offB);
+    uint32_t *codes = (uint32_t *)(buf + cg.offC);
+    if (int r = launch_pad_rows(A, nA, L, cg.padl, cg.ppitch, Ap, st)) return r;
+    if (int r = launch_pad_rows(B, nB, L, cg.padl, cg.ppitch, Bp, st)) return r;
+    // two tasks per group of every wave: all pairs cost the same
+    const int K = 2 * g.P * CODES_WAVES;
+    const size_t lds = (size_t)K * (sizeof(T) + sizeof(int)) + 16;
+    const unsigned blocks = (unsigned)ceil_div(np, K);
+    switch (g.C * 2 + (g.exact ? 1 : 0)) {
+#define X(c)                                                                                                   \
+    case c * 2 + 1:                                                                                            \
+        hipLaunchKernelGGL((dtw_codes_kernel<T, c, true>), dim3(blocks), dim3(WAVE * CODES_WAVES), lds, st, g, K, \
+                           np, nB, pairing, Ap, Bp, cg.ppitch, cg.padl, out, codes, cg.pitch);                 \
+        break;                                                                                                 \
+    case c * 2:                                                                                                \
+        hipLaunchKernelGGL((dtw_codes_kernel<T, c, false>), dim3(blocks), dim3(WAVE * CODES_WAVES), lds, st, g, K, \
+                           np, nB, pairing, Ap, Bp, cg.ppitch, cg.padl, out, codes, cg.pitch);                 \
         break;
-        X(1) X(2) X(3) X(4) X(6) X(8) X(9) X(12) X(16)
+        X(1) X(2) X(3) X(4) X(6) X(8) X(9) X(12)
 #undef X
     default:
         return fail(NNDTW_EUNSUP, "no DTW engine for %d pairs per lane", g.C);
@@ -196,16 +240,16 @@ int launch_dtw_backward(bool f64, const float *A, int64_t nA, const float *B, in
 {
     if (nA == 0 || (!pairing && nB == 0)) return NNDTW_OK;
     CodesGeom cg;
-    if (int r = codes_geom(L, W, &cg)) return r;
+    if (int r = codes_geom(nA, nB, L, W, pairing, f64, &cg)) return r;
+    const uint32_t *cw = (const uint32_t *)(codes + cg.offC);
     const unsigned blocks = (unsigned)(pairing ? ceil_div(nA, BT_THREADS) : nA);
-    const size_t esz = f64 ? 8 : 4;
-    const size_t lds = pairing ? 0 : (size_t)L * esz;
+    const size_t lds = pairing ? 0 : (size_t)L * (f64 ? 8 : 4);
     if (f64)
         hipLaunchKernelGGL(dtw_backtrack_kernel<double>, dim3(blocks), dim3(BT_THREADS), lds, st, cg.g, A, nA, B, nB,
-                           pairing, (const double *)gout, codes, cg.pitch, (double *)gA);
+                           pairing, (const double *)gout, cw, cg.pitch, (double *)gA);
     else
         hipLaunchKernelGGL(dtw_backtrack_kernel<float>, dim3(blocks), dim3(BT_THREADS), lds, st, cg.g, A, nA, B, nB,
-                           pairing, (const float *)gout, codes, cg.pitch, (float *)gA);
+                           pairing, (const float *)gout, cw, cg.pitch, (float *)gA);
     NNDTW_LAUNCH_CHECK("dtw backtrack kernel launch");
     return NNDTW_OK;
 }
