@@ -180,6 +180,35 @@ def backward_bench(nd, synth, torch, dev, reps=5, cpu=True):
     return res
 
 
+def serving_bench(nd, synth, torch, dev, rate=2000.0, duration=3.0):
+    """A seeded Poisson stream of NN-DTW requests at `rate` per second for
+    `duration` seconds against 8 resident reference sets of 4000 random walks
+    (lengths 64 .. 1024, W = 0.1 L, V = 5), served by continuous batching on
+    3 streams; queries resident on the device before the session."""
+    from paper_1808_09617_amd import serve
+    sets = synth.serving_sets()
+    rss = [nd.RefSet(torch.from_numpy(refs).to(dev), W) for refs, W in sets]
+    Ls = [refs.shape[1] for refs, _ in sets]
+    warm = serve.poisson_requests(Ls, rate=rate, duration=0.2, seed=1, device=dev,
+                                  make_query=lambda s, L, k: synth.serving_query(s, L, 10 ** 6 + k))
+    reqs = serve.poisson_requests(Ls, rate=rate, duration=duration, seed=2, device=dev,
+                                  make_query=lambda s, L, k: synth.serving_query(s, L, k))
+    torch.cuda.synchronize()
+    # per-set round size and engine shape, tuned on 16 sample queries per set
+    from paper_1808_09617_amd import tune
+    sample = [(rs, torch.stack([torch.from_numpy(synth.serving_query(s, Ls[s], 2 * 10 ** 6 + k)).to(dev)
+                                for k in range(16)])) for s, rs in enumerate(rss)]
+    R, cpl, _ = tune.autotune(sample, V=5)
+    server = serve.Server(rss, n_streams=3, R=R, cpl=cpl)
+    server.run(warm)
+    _, summary = server.run(reqs)
+    summary.update({"offered_rps": rate, "sets": len(sets), "refs_per_set": sets[0][0].shape[0],
+                    "lengths": Ls, "R": R, "cpl": cpl})
+    del rss
+    torch.cuda.empty_cache()
+    return summary
+
+
 def batch_bench(nd, synth, torch, dev, reps=3, tuned=None):
     """The batching workload (64 random-walk sets, L 25..1839, 26,583 queries,
     W = 0.1 L, V = 5) as one captured graph of the batched search, inputs
@@ -388,6 +417,7 @@ def main():
         res["tightness"] = tight
         res["hbm_streaming"] = hbm_streaming(nd, synth, torch, dev)
         res["backward"] = backward_bench(nd, synth, torch, dev, cpu=not args.no_cpu)
+        res["serving"] = serving_bench(nd, synth, torch, dev)
         res["batch"] = batch_bench(nd, synth, torch, dev)
         res["batch_tuned"] = batch_bench(nd, synth, torch, dev, tuned="auto")
         log("extras done")

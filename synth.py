@@ -164,6 +164,26 @@ def batch_workload(n_sets: int = 64, L_range=(24, 2048), N_range=(50, 8000), q_f
     return out
 
 
+def serving_sets(n_sets: int = 8, n_refs: int = 4000, L_range=(64, 1024), w_frac: float = 0.1,
+                 config_id: int = 5):
+    """Reference sets of the serving workload: set s has the fixed length
+    L_s = round(L_lo + (L_hi - L_lo) s / (n_sets - 1)) (equal lengths within
+    a set), n_refs random walks, W = round-half-up(w_frac L_s); drawn from
+    SeedSequence([180809617, config_id, 200 + s, 0])."""
+    out = []
+    for s in range(n_sets):
+        L = int(round(L_range[0] + (L_range[1] - L_range[0]) * s / max(1, n_sets - 1)))
+        rng = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, config_id, 200 + s, STREAM_REFS]))
+        out.append((rw(n_refs, L, rng), window_from_fraction(w_frac, L)))
+    return out
+
+
+def serving_query(set_id: int, L: int, k: int, config_id: int = 5) -> np.ndarray:
+    """Request k's query (a random walk of the set's length)."""
+    rng = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, config_id, 300 + k, set_id]))
+    return rw(1, L, rng)[0]
+
+
 def tightness_pairs(n_pairs: int = 250_000, L: int = 256, config_id: int = 2):
     """Independent sin5 pairs (A_k, B_k) for LB/DTW tightness (Figure 1 workload shape)."""
     rng = rng_for(config_id, STREAM_PAIRS)

@@ -528,3 +528,31 @@ def test_dtw_backward_full_config():
     assert same.mean() >= 0.98, same.mean()
     oz = host(oz)
     assert np.all(np.abs(oz[~same] - odz[~same]) <= 4 * oracle.slack(L) * odz[~same])
+
+
+# ------------------------------------------------------------------ serving
+def test_serving_results_equal_alone():
+    """Requests served in the mix (continuous batching on several streams)
+    give exactly the result of each query searched alone; a sample is also
+    checked against the oracle."""
+    from paper_1808_09617_amd import serve
+    sets = synth.serving_sets(n_sets=6, n_refs=300, L_range=(48, 256))
+    rss = [nd.RefSet(dev(refs), W) for refs, W in sets]
+    Ls = [refs.shape[1] for refs, _ in sets]
+    reqs = serve.poisson_requests(Ls, rate=4000.0, duration=0.1, seed=11, device=DEV,
+                                  make_query=lambda s, L, k: synth.serving_query(s, L, k))
+    torch.cuda.synchronize()
+    say("serving", len(reqs), "requests")
+    done, summary = serve.Server(rss, n_streams=3, max_batch=64).run(reqs)
+    assert summary["batches"] > 1
+    for r in done:
+        q = r.query[None]
+        i, d, c, R = nd.search(rss[r.set_id], q, V=5)
+        assert r.result[0] == int(host(i)[0]) and r.result[1] == float(host(d)[0])
+        assert r.result[2][:5] == host(c)[0, :5].tolist()
+    for r in done[::25]:
+        refs, W = sets[r.set_id]
+        q = host(r.query)[None]
+        _, _, _, R = nd.search(rss[r.set_id], r.query[None], V=5)
+        oi, od, oc = oracle.search(refs, q, W, 5, "keogh_enh", R, True)
+        assert r.result[0] == oi[0] and r.result[1] == od[0] and r.result[2][:5] == oc[0, :5].tolist()
