@@ -26,7 +26,8 @@ LIB = os.path.join(HERE, "_nndtw_oracle.so")
 # A planted-mistake build of the oracle (mutation tests only) may be loaded instead.
 _ALT = os.environ.get("NNDTW_ORACLE_LIB")
 
-CASCADE = {"none": 0, "keogh": 1, "keogh_enh": 2, "enh": 3}
+CASCADE = {"none": 0, "keogh": 1, "keogh_enh": 2, "enh": 3,
+           "kim": 4, "improved": 5, "new": 6, "enh_sym": 7}
 COUNT_NAMES = ("n", "pruned_keogh", "pruned_enh_bands", "pruned_enh", "dtw_started",
                "dtw_abandoned", "cells", "fp64_rechecks")
 
@@ -72,6 +73,11 @@ def lib():
             "oracle_lb_keogh_batch": (None, [p, i64, p, p, i64, i32, i32, p]),
             "oracle_lb_enhanced_batch": (None, [p, i64, p, p, p, i64, i32, i32, i32, p, i32, i32, p]),
             "oracle_dtw_batch": (None, [p, i64, p, i64, i32, i32, p, i32, p]),
+            "oracle_lb_kim": (d, [p, p, i32]),
+            "oracle_lb_improved": (d, [p, p, p, p, i32, i32, d]),
+            "oracle_lb_new": (d, [p, p, i32, i32]),
+            "oracle_lb_enhanced_sym": (d, [p, p, p, p, p, p, i32, i32, i32]),
+            "oracle_lb_compare_batch": (None, [i32, p, p, p, i64, p, p, p, i64, i32, i32, i32, p, i32, p]),
             "oracle_dtw_path": (ctypes.c_double, [p, p, i32, i32, p, p, p]),
             "oracle_dtw_grad_batch": (None, [p, i64, p, i64, i32, i32, i32, p, p, p]),
             "oracle_brute_nn": (None, [p, i64, p, i64, i32, i32, p, p]),
@@ -152,6 +158,41 @@ def lb_enhanced(A, B, U, Lo, W, V, cutoff=None, zip_=False, variant="alg1"):
     lib().oracle_lb_enhanced_batch(_ptr(A), A.shape[0], _ptr(B), _ptr(U), _ptr(Lo), B.shape[0],
                                    A.shape[1], int(W), int(V), _ptr(cut), int(zip_), v, _ptr(out))
     return out
+
+
+def _compare(what, A, B, W=0, V=1, cutoff=None, zip_=False):
+    A, B = _one(A), _one(B)
+    out = np.empty(_pairing(A, B, zip_), np.float64)
+    UA = LA = UB = LB = None
+    if what == 3:
+        UA, LA = envelopes(A, W)
+    if what in (1, 3):
+        UB, LB = envelopes(B, W)
+    cut = None if cutoff is None else np.ascontiguousarray(np.broadcast_to(
+        np.asarray(cutoff, np.float64), (A.shape[0],)))
+    lib().oracle_lb_compare_batch(what, _ptr(A), _ptr(UA), _ptr(LA), A.shape[0], _ptr(B), _ptr(UB), _ptr(LB),
+                                  B.shape[0], A.shape[1], int(W), int(V), _ptr(cut), int(zip_), _ptr(out))
+    return out
+
+
+def lb_kim(A, B, zip_=False):
+    """LB_Kim, sum of the first, last, minimum and maximum features without repetitions."""
+    return _compare(0, A, B, zip_=zip_)
+
+
+def lb_improved(A, B, W, cutoff=None, zip_=False):
+    """LB_Improved = LB_Keogh(A, B) + LB_Keogh(B, A'); +inf where LB_Keogh(A, B) > cutoff."""
+    return _compare(1, A, B, W, cutoff=cutoff, zip_=zip_)
+
+
+def lb_new(A, B, W, zip_=False):
+    """LB_New: corner costs plus, per interior point, the nearest point of B in its window."""
+    return _compare(2, A, B, W, zip_=zip_)
+
+
+def lb_enhanced_sym(A, B, W, V, zip_=False):
+    """max(LB_Enhanced^V(A, B), LB_Enhanced^V(B, A))."""
+    return _compare(3, A, B, W, V, zip_=zip_)
 
 
 def dtw(A, B, W, cutoff=None, zip_=False):

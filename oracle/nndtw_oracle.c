@@ -30,7 +30,8 @@
 
 #define OINF INFINITY
 
-enum { CASCADE_NONE = 0, CASCADE_KEOGH = 1, CASCADE_KEOGH_ENH = 2, CASCADE_ENH = 3 };
+enum { CASCADE_NONE = 0, CASCADE_KEOGH = 1, CASCADE_KEOGH_ENH = 2, CASCADE_ENH = 3,
+       CASCADE_KIM = 4, CASCADE_IMPROVED = 5, CASCADE_NEW = 6, CASCADE_ENH_SYM = 7 };
 enum { C_N = 0, C_PRUNED_KEOGH, C_PRUNED_ENH_BANDS, C_PRUNED_ENH, C_DTW_STARTED,
        C_DTW_ABANDONED, C_CELLS, C_RECHECKS, C_NCOUNTS };
 
@@ -222,6 +223,87 @@ double oracle_lb_enhanced_alg1(const float *A, const float *B, const float *U,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Comparison bounds: the existing lower bounds the paper reviews (Section
+ * 2.2) and measures against (Section 4), and the symmetric variant its
+ * conclusion suggests.                                                      */
+
+/* LB_Kim in the sum form of the experiments (Section 4): the point costs of
+ * the first points, of the last points, of the two minima and of the two
+ * maxima, summed "without repetitions".  Reading: the min feature
+ * delta(min A, min B) is added only when neither series takes its minimum
+ * value at its first or last point, and likewise the max feature; the sum
+ * runs first, last, min, max (the order of the feature list).  With that
+ * rule each feature is paid by a different link of every warping path (the
+ * corners, a link in an interior row or column holding an extreme), so the
+ * sum is a lower bound on DTW_W for every W.                               */
+double oracle_lb_kim(const float *A, const float *B, int L)
+{
+    float amin = A[0], amax = A[0], bmin = B[0], bmax = B[0];
+    for (int i = 1; i < L; ++i) {
+        if (A[i] < amin) amin = A[i];
+        if (A[i] > amax) amax = A[i];
+        if (B[i] < bmin) bmin = B[i];
+        if (B[i] > bmax) bmax = B[i];
+    }
+    double s = delta(A[0], B[0]) + delta(A[L - 1], B[L - 1]);
+    int min_at_end = A[0] == amin || A[L - 1] == amin || B[0] == bmin || B[L - 1] == bmin;
+    int max_at_end = A[0] == amax || A[L - 1] == amax || B[0] == bmax || B[L - 1] == bmax;
+    if (!min_at_end) s += delta(amin, bmin);
+    if (!max_at_end) s += delta(amax, bmax);
+    return s;
+}
+
+/* LB_Improved (Section 2.2): LB_Keogh(A, B), then the projection A' of A on
+ * B's envelope (Equation 5: A_i clamped to [Lo_i, U_i]), the envelope of A'
+ * for the same W, and LB_Keogh(B, A') against it; the result is the sum of
+ * the two.  Second-pass skip: when the first pass already exceeds cutoff
+ * (strictly) the second is not computed and the result is +inf.          */
+double oracle_lb_improved(const float *A, const float *B, const float *U, const float *Lo,
+                          int L, int W, double cutoff)
+{
+    double k1 = oracle_lb_keogh(A, U, Lo, L);
+    if (k1 > cutoff) return OINF;
+    float *P = (float *)malloc(sizeof(float) * (size_t)L * 3);
+    float *UP = P + L, *LP = P + 2 * L;
+    for (int i = 0; i < L; ++i) {
+        if (A[i] > U[i])       P[i] = U[i];
+        else if (A[i] < Lo[i]) P[i] = Lo[i];
+        else                   P[i] = A[i];
+    }
+    oracle_envelopes(P, 1, L, W, UP, LP);
+    double k2 = oracle_lb_keogh(B, UP, LP, L);
+    free(P);
+    return k1 + k2;
+}
+
+/* LB_New (Section 2.2): the two corner costs, then for every interior point
+ * i = 2..L-1 (ascending) the smallest cost of A_i against a point of B
+ * inside its window, max(1, i-W) <= j <= min(L, i+W).                      */
+double oracle_lb_new(const float *A, const float *B, int L, int W)
+{
+    int w = eff_window(L, W);
+    double s = delta(A[0], B[0]) + delta(A[L - 1], B[L - 1]);
+    for (int i = 1; i < L - 1; ++i) {
+        double m = OINF;
+        for (int j = imax(0, i - w); j <= imin(L - 1, i + w); ++j) m = dmin(m, delta(A[i], B[j]));
+        s += m;
+    }
+    return s;
+}
+
+/* max(LB_Enhanced^V(A, B), LB_Enhanced^V(B, A)) (the conclusion: LB_Enhanced
+ * is not symmetric, so the larger of the two directions is also a bound).
+ * UA/LoA and UB/LoB are the envelopes of A and B for window W; each
+ * direction is Algorithm 1 without early exit.                            */
+double oracle_lb_enhanced_sym(const float *A, const float *UA, const float *LoA, const float *B,
+                              const float *UB, const float *LoB, int L, int W, int V)
+{
+    double ab = oracle_lb_enhanced_alg1(A, B, UB, LoB, L, W, V, OINF);
+    double ba = oracle_lb_enhanced_alg1(B, A, UA, LoA, L, W, V, OINF);
+    return ab > ba ? ab : ba;
+}
+
+/* ------------------------------------------------------------------------ */
 /* DTW_W by the cost-matrix recurrence, Equation (1):
  *   D(i,j) = delta(A_i, B_j) + min(D(i-1,j-1), D(i,j-1), D(i-1,j))
  * for |i - j| <= W, +inf outside the window, D(0,0) = 0 before the first
@@ -311,6 +393,28 @@ void oracle_lb_enhanced_batch(const float *A, int64_t nA, const float *B, const 
     }
 }
 
+/* Comparison bounds over pairs.  what: 0 LB_Kim, 1 LB_Improved (second pass
+ * skipped above cutoff[a] when cutoff is given), 2 LB_New, 3 the symmetric
+ * LB_Enhanced^V.  U/Lo are the envelopes of B; UA/LoA those of A (what = 3
+ * only).                                                                   */
+void oracle_lb_compare_batch(int what, const float *A, const float *UA, const float *LoA, int64_t nA,
+                             const float *B, const float *U, const float *Lo, int64_t nB, int L,
+                             int W, int V, const double *cutoff, int pairing, double *out)
+{
+    int64_t np = pairing ? nA : nA * nB;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < np; ++p) {
+        int64_t a = pairing ? p : p / nB, b = pairing ? p : p % nB;
+        const float *x = A + a * L, *y = B + b * L;
+        if (what == 0)      out[p] = oracle_lb_kim(x, y, L);
+        else if (what == 1) out[p] = oracle_lb_improved(x, y, U + b * L, Lo + b * L, L, W,
+                                                        cutoff ? cutoff[a] : OINF);
+        else if (what == 2) out[p] = oracle_lb_new(x, y, L, W);
+        else                out[p] = oracle_lb_enhanced_sym(x, UA + a * L, LoA + a * L, y, U + b * L,
+                                                            Lo + b * L, L, W, V);
+    }
+}
+
 void oracle_dtw_batch(const float *A, int64_t nA, const float *B, int64_t nB, int L, int W,
                       const double *cutoff, int pairing, double *out)
 {
@@ -377,9 +481,14 @@ static int lexless(double d, int64_t k, double bd, int64_t bk)
  * on the answer; with R = 1 both choices give identical results).  A bound
  * prunes iff bound > thr (strict).  The stage of the first bound that prunes
  * is counted.  Cascades: 0 none, 1 LB_Keogh, 2 LB_Keogh then LB_Enhanced^V
- * (bands part, then full), 3 LB_Enhanced^V only (bands, then full).
- * counts[q*8 + .] = {N, pruned_keogh, pruned_enh_bands, pruned_enh,
- *                    dtw_started, dtw_abandoned, cells, fp64_rechecks}.     */
+ * (bands part, then full), 3 LB_Enhanced^V only (bands, then full); the
+ * comparison cascades 4 LB_Kim, 5 LB_Improved (LB_Keogh as its first pass,
+ * then the full bound), 6 LB_New, 7 the symmetric LB_Enhanced^V (bands part
+ * of LB_Enhanced^V(A, B), then the larger of both directions).
+ * counts[q*8 + .] = {N, pruned by stage 1, 2, 3, dtw_started, dtw_abandoned,
+ * cells, fp64_rechecks}; stage 1 is LB_Keogh (cascades 1, 2, 5), LB_Kim (4)
+ * or LB_New (6); stage 2 the bands part of LB_Enhanced (2, 3, 7); stage 3
+ * the full LB_Enhanced (2, 3), LB_Improved (5) or the symmetric bound (7). */
 void oracle_search(const float *refs, int64_t N, const float *queries, int64_t Q, int L,
                    int W, int V, int cascade, int64_t R, int init_ub,
                    int64_t *nn_idx, double *nn_dist, int64_t *counts)
@@ -392,6 +501,8 @@ void oracle_search(const float *refs, int64_t N, const float *queries, int64_t Q
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t q = 0; q < Q; ++q) {
         const float *A = queries + q * L;
+        float *UA = (float *)malloc(sizeof(float) * (size_t)L * 2), *LoA = UA + L;
+        oracle_envelopes(A, 1, L, W, UA, LoA);
         okey *order = (okey *)malloc(sizeof(okey) * (size_t)N);
         double *rd = (double *)malloc(sizeof(double) * (size_t)R);
         int64_t *rk = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
@@ -419,6 +530,16 @@ void oracle_search(const float *refs, int64_t N, const float *queries, int64_t Q
                     if (oracle_lb_enhanced_bands(A, Bk, L, W, V) > thr) { c[C_PRUNED_ENH_BANDS]++; continue; }
                     if (oracle_lb_enhanced_alg1(A, Bk, Uk, Lk, L, W, V, OINF) > thr) { c[C_PRUNED_ENH]++; continue; }
                 }
+                if (cascade == CASCADE_KIM && oracle_lb_kim(A, Bk, L) > thr) { c[C_PRUNED_KEOGH]++; continue; }
+                if (cascade == CASCADE_IMPROVED) {
+                    if (oracle_lb_keogh(A, Uk, Lk, L) > thr) { c[C_PRUNED_KEOGH]++; continue; }
+                    if (oracle_lb_improved(A, Bk, Uk, Lk, L, W, OINF) > thr) { c[C_PRUNED_ENH]++; continue; }
+                }
+                if (cascade == CASCADE_NEW && oracle_lb_new(A, Bk, L, W) > thr) { c[C_PRUNED_KEOGH]++; continue; }
+                if (cascade == CASCADE_ENH_SYM) {
+                    if (oracle_lb_enhanced_bands(A, Bk, L, W, V) > thr) { c[C_PRUNED_ENH_BANDS]++; continue; }
+                    if (oracle_lb_enhanced_sym(A, UA, LoA, Bk, Uk, Lk, L, W, V) > thr) { c[C_PRUNED_ENH]++; continue; }
+                }
                 c[C_DTW_STARTED]++;
                 int64_t nc = 0;
                 double d = dtw_rows(A, Bk, L, W, thr, &nc);
@@ -435,6 +556,7 @@ void oracle_search(const float *refs, int64_t N, const float *queries, int64_t Q
         nn_idx[q] = bk;
         nn_dist[q] = bsf;
         free(order);
+        free(UA);
         free(rd);
         free(rk);
     }

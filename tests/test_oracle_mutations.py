@@ -35,6 +35,13 @@ MUTATIONS = [
     ("grad: factor 2 dropped", "g * (2.0 * ((double)A[pi[k]] - (double)B[pj[k]]))", "g * (((double)A[pi[k]] - (double)B[pj[k]]))"),
     ("grad: accumulated at the reference index", "gA[pi[k]] += g * (2.0", "gA[pj[k]] += g * (2.0"),
     ("grad: output weight ignored", "gA[pi[k]] += g * (2.0", "gA[pi[k]] += 1.0 * (2.0"),
+    ("kim: extremes counted with repetitions", "if (!min_at_end) s += delta(amin, bmin);", "s += delta(amin, bmin);"),
+    ("kim: max feature against the other minimum", "if (!max_at_end) s += delta(amax, bmax);", "if (!max_at_end) s += delta(amax, bmin);"),
+    ("improved: second pass without the projection", "if (A[i] > U[i])       P[i] = U[i];", "if (A[i] > U[i])       P[i] = A[i];"),
+    ("new: first point also takes a window minimum", "for (int i = 1; i < L - 1; ++i) {\n        double m = OINF;", "for (int i = 0; i < L - 1; ++i) {\n        double m = OINF;"),
+    ("new: window one short", "j <= imin(L - 1, i + w); ++j) m = dmin(m, delta(A[i], B[j]));", "j < imin(L - 1, i + w); ++j) m = dmin(m, delta(A[i], B[j]));"),
+    ("sym: smaller direction", "return ab > ba ? ab : ba;", "return ab < ba ? ab : ba;"),
+    ("search: improved second pass counted at stage 1", "if (oracle_lb_improved(A, Bk, Uk, Lk, L, W, OINF) > thr) { c[C_PRUNED_ENH]++;", "if (oracle_lb_improved(A, Bk, Uk, Lk, L, W, OINF) > thr) { c[C_PRUNED_KEOGH]++;"),
     ("grad: last path cell dropped", "    for (int k = 0; k < n; ++k)\n        gA[pi[k]]", "    for (int k = 0; k < n - 1; ++k)\n        gA[pi[k]]"),
 ]
 

@@ -508,3 +508,175 @@ def test_grad_is_linear_in_the_output_weights(orc):
             gy, _ = orc.dtw_grad(A[x], B[y], 5)
             want += w[x, y] * gy[0]
         assert np.allclose(g[x], want, rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------- comparison bounds
+# LB_Kim (sum form), LB_Improved, LB_New (Section 2.2 and the experiments of
+# Section 4) and the symmetric LB_Enhanced of the conclusion.  Pinned against
+# a hand-derived fixture, path enumeration, dominance relations that follow
+# from the definitions, the W = 0 and unconstrained special cases, and the
+# brute-force nearest neighbour.
+
+def _fixture(name):
+    fx = {}
+    for line in open(os.path.join(GOLD, name)):
+        if not line.strip() or line.startswith("#"):
+            continue
+        parts = line.split()
+        key = " ".join(p for p in parts if not _isnum(p))
+        fx[key] = [float(p) for p in parts if _isnum(p)]
+    return fx
+
+
+def test_comparison_bounds_worked_example(orc):
+    fx = _fixture("comparison_bounds.txt")
+    s = {k: np.array(fx[k], np.float32) for k in "ABCDEF"}
+    for x, y in ("AB", "CD", "EF"):
+        assert orc.dtw(s[x], s[y], 1)[0, 0] == fx["dtw " + x + y][0]
+        assert orc.lb_kim(s[x], s[y])[0, 0] == fx["kim " + x + y][0]
+    for x, y in ("AB", "CD"):
+        assert orc.lb_new(s[x], s[y], 1)[0, 0] == fx["new " + x + y][0]
+        assert orc.lb_improved(s[x], s[y], 1)[0, 0] == fx["improved " + x + y][0]
+        assert orc.lb_enhanced_sym(s[x], s[y], 1, 1)[0, 0] == fx["sym " + x + y][0]
+        for p, q in ((x, y), (y, x)):
+            U, Lo = orc.envelopes(s[q], 1)
+            assert orc.lb_enhanced(s[p], s[q], U, Lo, 1, 1)[0, 0] == fx["enh1 " + p + q][0]
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6, 7])
+def test_comparison_bounds_below_every_path(orc, L):
+    """Each bound is at most the cheapest enumerated warping path, at every W,
+    on random series and on series shifted far apart (where counting an
+    extreme feature twice would exceed the path cost)."""
+    A, B = _pairs(4, L, seed=500 + L, kind="normal")
+    A = np.concatenate([A, A[:2] + 10.0]).astype(np.float32)
+    B = np.concatenate([B, B[:2] * 0.25]).astype(np.float32)
+    for a, b in zip(A, B):
+        for W in range(L):
+            best = paths.dtw_brute(a, b, W)
+            tol = best * 1e-12
+            assert orc.lb_kim(a, b)[0, 0] <= best + tol
+            assert orc.lb_new(a, b, W)[0, 0] <= best + tol
+            assert orc.lb_improved(a, b, W)[0, 0] <= best + tol
+            for V in (1, 2, 3):
+                assert orc.lb_enhanced_sym(a, b, W, V)[0, 0] <= best + tol
+
+
+def test_kim_without_repetitions_is_needed(orc):
+    """Constant series 10 and 0: every point is both minimum and maximum, so
+    both extreme features coincide with the corners.  The bound must equal
+    the two corner costs (= DTW = 200); counting the extremes would give 400."""
+    a = np.full(2, 10.0, np.float32)
+    b = np.zeros(2, np.float32)
+    assert orc.dtw(a, b, 1)[0, 0] == 200.0
+    assert orc.lb_kim(a, b)[0, 0] == 200.0
+
+
+def test_comparison_bounds_properties(orc):
+    A, B = _pairs(12, 40, seed=611, kind="sin5")
+    ed = orc.ed2(A, B, zip_=True)
+    kim_ab, kim_ba = orc.lb_kim(A, B, zip_=True), orc.lb_kim(B, A, zip_=True)
+    assert np.array_equal(kim_ab, kim_ba)                      # the definition is symmetric
+    for W in (0, 1, 4, 13, 39, 60):
+        d = orc.dtw(A, B, W, zip_=True)
+        U, Lo = orc.envelopes(B, W)
+        k = orc.lb_keogh(A, U, Lo, zip_=True)
+        imp = orc.lb_improved(A, B, W, zip_=True)
+        new = orc.lb_new(A, B, W, zip_=True)
+        assert np.all(imp >= k)                                # LB_Keogh plus a non-negative pass
+        assert np.all(new >= k * (1 - 1e-12))                  # every term dominates the Keogh term
+        assert np.all(imp <= d * (1 + 1e-12)) and np.all(new <= d * (1 + 1e-12))
+        Ua, La = orc.envelopes(A, W)
+        for V in (1, 3, 20):
+            ab = orc.lb_enhanced(A, B, U, Lo, W, V, zip_=True)
+            ba = orc.lb_enhanced(B, A, Ua, La, W, V, zip_=True)
+            sym = orc.lb_enhanced_sym(A, B, W, V, zip_=True)
+            assert np.all(sym >= ab) and np.all(sym >= ba) and np.all((sym == ab) | (sym == ba))
+            assert np.all(sym <= d * (1 + 1e-12))
+        if W == 0:
+            assert np.array_equal(imp, ed)                     # A' = B, second pass 0
+            assert np.allclose(new, ed, rtol=1e-12, atol=0)
+        if W >= 39:
+            # unconstrained: nearest value of the whole of B (sorted search)
+            for a, b, v in zip(A, B, new):
+                sb = np.sort(b.astype(np.float64))
+                want = (float(a[0]) - float(b[0])) ** 2 + (float(a[-1]) - float(b[-1])) ** 2
+                for x in a[1:-1].astype(np.float64):
+                    t = np.searchsorted(sb, x)
+                    want += min((x - sb[max(t - 1, 0)]) ** 2, (x - sb[min(t, sb.size - 1)]) ** 2)
+                assert abs(v - want) <= 1e-12 * want
+
+
+def test_improved_cutoff_skips_the_second_pass(orc):
+    A, B = _pairs(10, 33, seed=612)
+    W = 3
+    U, Lo = orc.envelopes(B, W)
+    k = orc.lb_keogh(A, U, Lo, zip_=True)
+    full = orc.lb_improved(A, B, W, zip_=True)
+    cut = np.median(k)
+    got = np.array([orc.lb_improved(A[i], B[i], W, cutoff=cut)[0, 0] for i in range(10)])
+    assert np.all(np.isinf(got[k > cut]))
+    assert np.array_equal(got[k <= cut], full[k <= cut])
+
+
+def _compare_matrices(orc, refs, queries, W, V):
+    U, Lo = orc.envelopes(refs, W)
+    Ua, La = orc.envelopes(queries, W)
+    return {
+        "lbk": orc.lb_keogh(queries, U, Lo),
+        "lbb": orc.lb_enhanced(queries, refs, U, Lo, W, V, variant="bands"),
+        "kim": orc.lb_kim(queries, refs),
+        "imp": orc.lb_improved(queries, refs, W),
+        "new": orc.lb_new(queries, refs, W),
+        "sym": np.maximum(orc.lb_enhanced(queries, refs, U, Lo, W, V),
+                          np.stack([orc.lb_enhanced(refs, queries[q], Ua[q], La[q], W, V)[:, 0]
+                                    for q in range(queries.shape[0])])),
+    }
+
+
+@pytest.mark.parametrize("cascade", ["kim", "improved", "new", "enh_sym"])
+@pytest.mark.parametrize("R", [1, 5])
+def test_search_comparison_cascades(orc, cascade, R):
+    """The search with each comparison bound returns the brute-force nearest
+    neighbour, and its stage counts equal the closed form recomputed from full
+    bound matrices (bsf after each round = min over the visited DTWs)."""
+    refs = synth.random_series(50, 28, seed=71, kind="sin5")
+    queries = synth.random_series(6, 28, seed=72, kind="sin5")
+    for W in (0, 3, 27):
+        bi, bd = orc.brute_nn(refs, queries, W)
+        V = 3
+        m = _compare_matrices(orc, refs, queries, W, V)
+        stages = {"kim": [("kim", 1)], "improved": [("lbk", 1), ("imp", 3)], "new": [("new", 1)],
+                  "enh_sym": [("lbb", 2), ("sym", 3)]}[cascade]
+        ed = orc.ed2(queries, refs)
+        d = orc.dtw(queries, refs, W)
+        eps = orc.slack(refs.shape[1])
+        si, sd, cnt = orc.search(refs, queries, W, V, cascade, R, True)
+        assert np.array_equal(si, bi) and np.array_equal(sd, bd)
+        for q in range(queries.shape[0]):
+            order = sorted(range(refs.shape[0]), key=lambda k: (ed[q, k], k))
+            ub, best = ed[q, order[0]], (math.inf, -1)
+            c = [refs.shape[0], 0, 0, 0, 0]
+            for r0 in range(0, len(order), R):
+                thr = min(best[0], ub) * (1.0 + eps)
+                rnd = order[r0:r0 + R]
+                for k in rnd:
+                    hit = next((slot for name, slot in stages if m[name][q, k] > thr), 4)
+                    c[hit] += 1
+                for k in rnd:
+                    if d[q, k] <= thr and (best[1] < 0 or (d[q, k], k) < best):
+                        best = (d[q, k], k)
+            assert cnt[q, :5].tolist() == c, (cascade, W, q, cnt[q], c)
+
+
+def test_search_comparison_dominance(orc):
+    """Pointwise dominance of the bounds gives fewer DTW calls at any R:
+    LB_Improved and LB_New over LB_Keogh, the symmetric bound over LB_Enhanced."""
+    wl = synth.workload("nndtw-small")
+    W = wl.windows[0]
+    for R in (1, 8):
+        started = {c: orc.search(wl.refs, wl.queries, W, 2, c, R)[2][:, 4]
+                   for c in ("keogh", "improved", "new", "enh", "enh_sym")}
+        assert np.all(started["improved"] <= started["keogh"])
+        assert np.all(started["new"] <= started["keogh"])
+        assert np.all(started["enh_sym"] <= started["enh"])
