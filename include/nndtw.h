@@ -63,12 +63,22 @@ extern "C" {
 #define NNDTW_CASCADE_KEOGH     1  /* LB_Keogh                                        */
 #define NNDTW_CASCADE_KEOGH_ENH 2  /* LB_Keogh, then LB_Enhanced^V bands, then full   */
 #define NNDTW_CASCADE_ENH       3  /* LB_Enhanced^V bands, then full                  */
+/* Comparison cascades (the bounds the paper measures LB_Enhanced against,
+ * Section 4, and the symmetric variant of its conclusion); nndtw_search only,
+ * the batched search rejects them with NNDTW_EUNSUP. */
+#define NNDTW_CASCADE_KIM       4  /* LB_Kim (sum form)                               */
+#define NNDTW_CASCADE_IMPROVED  5  /* LB_Keogh (first pass), then LB_Improved         */
+#define NNDTW_CASCADE_NEW       6  /* LB_New                                          */
+#define NNDTW_CASCADE_ENH_SYM   7  /* LB_Enhanced^V(A,B) bands, then
+                                      max(LB_Enhanced^V(A,B), LB_Enhanced^V(B,A))     */
 
 /* Layout of the per-query counts written by nndtw_search (int64 each). */
 #define NNDTW_COUNT_N              0  /* references visited (= n)                        */
-#define NNDTW_COUNT_PRUNED_KEOGH   1  /* pruned by LB_Keogh                              */
+#define NNDTW_COUNT_PRUNED_KEOGH   1  /* pruned by LB_Keogh (LB_Kim, LB_New in their
+                                         cascades)                                       */
 #define NNDTW_COUNT_PRUNED_BANDS   2  /* pruned by the band part of LB_Enhanced          */
-#define NNDTW_COUNT_PRUNED_ENH     3  /* pruned by full LB_Enhanced                      */
+#define NNDTW_COUNT_PRUNED_ENH     3  /* pruned by full LB_Enhanced (LB_Improved, the
+                                         symmetric LB_Enhanced in their cascades)        */
 #define NNDTW_COUNT_DTW_STARTED    4  /* DTW_W started (not pruned)                      */
 #define NNDTW_COUNT_DTW_ABANDONED  5  /* implementation-defined: DTWs stopped early      */
 #define NNDTW_COUNT_CELLS          6  /* implementation-defined: band cells evaluated    */
@@ -130,6 +140,45 @@ int nndtw_lb_keogh(const float *A, int64_t nA, const float *U, const float *Lo,
 int nndtw_lb_enhanced(const float *A, int64_t nA, const float *B, const float *U,
                       const float *Lo, int64_t nB, int32_t L, int32_t W, int32_t V,
                       const double *cutoff, int32_t pairing, double *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Comparison lower bounds: the existing bounds reviewed in Section 2.2 and
+ * measured against LB_Enhanced in Section 4, and the symmetric LB_Enhanced
+ * of the conclusion.  FP64 from float32 inputs, sums in ascending point
+ * order; each is at most DTW_W(A, B) for the same W.  Array and pairing
+ * conventions as for nndtw_lb_enhanced; out: double (CROSS/ZIP).  Pointers
+ * that a bound does not read may be NULL (U, Lo for nndtw_lb_kim).
+ *
+ * LB_Kim in the sum form of the experiments (Section 4): (A_1 - B_1)^2 +
+ * (A_L - B_L)^2, plus (min A - min B)^2 unless either series takes its
+ * minimum at its first or last point, plus (max A - max B)^2 under the same
+ * rule for maxima ("without repetitions": each counted feature is then paid
+ * by a different link of every warping path).  A, B: float[n][L].
+ */
+int nndtw_lb_kim(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L,
+                 int32_t pairing, double *out, void *stream);
+
+/* LB_Improved (Section 2.2): LB_Keogh(A, B) + LB_Keogh(B, A'), where A' is
+ * A projected on B's envelope (Equation 5: A_i clamped to [Lo_i, U_i]) and
+ * the second LB_Keogh uses the envelope of A' for window W.  U, Lo: B's
+ * envelopes for W (nndtw_envelopes).  cutoff: NULL, or device double[nA]:
+ * where LB_Keogh(A, B) > cutoff[a] (strictly) the second pass is skipped
+ * and the result is +inf. */
+int nndtw_lb_improved(const float *A, int64_t nA, const float *B, const float *U,
+                      const float *Lo, int64_t nB, int32_t L, int32_t W,
+                      const double *cutoff, int32_t pairing, double *out, void *stream);
+
+/* LB_New (Section 2.2): (A_1 - B_1)^2 + (A_L - B_L)^2 plus, for i = 2..L-1,
+ * the smallest (A_i - B_j)^2 over max(1, i-W) <= j <= min(L, i+W). */
+int nndtw_lb_new(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L,
+                 int32_t W, int32_t pairing, double *out, void *stream);
+
+/* max(LB_Enhanced^V(A, B), LB_Enhanced^V(B, A)) (the conclusion: LB_Enhanced
+ * is not symmetric), each direction as nndtw_lb_enhanced without cutoff.
+ * U, Lo: B's envelopes for W; A's envelopes are computed internally. */
+int nndtw_lb_enhanced_sym(const float *A, int64_t nA, const float *B, const float *U,
+                          const float *Lo, int64_t nB, int32_t L, int32_t W, int32_t V,
+                          int32_t pairing, double *out, void *stream);
 
 /* ---------------------------------------------------------------------------
  * DTW_W (Equation 1 over the window of Section 2.1), FP32 cost matrix:
@@ -225,6 +274,13 @@ typedef struct nndtw_search_opts {
 /* Workspace bytes nndtw_search needs for nQ queries against refset. */
 int nndtw_search_workspace_bytes(const nndtw_refset *refset, int64_t nQ,
                                  const nndtw_search_opts *opts, size_t *bytes);
+
+/* The launch plan nndtw_search would use for this reference set and these
+ * options, decided on the host without enqueuing anything: writes opts->R
+ * (round size, >= 1), opts->cpl (diagonal pairs per lane of the DTW engine)
+ * and opts->waves.  The search runs windows with min(W, L-1) + 1 <= 567
+ * (63 lanes x 9 pairs); wider windows are EUNSUP. */
+int nndtw_search_plan(const nndtw_refset *refset, nndtw_search_opts *opts);
 
 /* Q: device float[nQ][L] (L of the reference set); outputs: nn_idx int64[nQ],
  * nn_dist double[nQ], counts int64[nQ][NNDTW_NCOUNTS] (NULL allowed).

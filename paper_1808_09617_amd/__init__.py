@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(PKG, "libnndtw.so")
 
 OK, EINVAL, EHIP, EUNSUP = 0, -1, -2, -3
 CROSS, ZIP = 0, 1
-CASCADES = {"none": 0, "keogh": 1, "keogh_enh": 2, "enh": 3}
+CASCADES = {"none": 0, "keogh": 1, "keogh_enh": 2, "enh": 3,
+            "kim": 4, "improved": 5, "new": 6, "enh_sym": 7}
 COUNT_NAMES = ("n", "pruned_keogh", "pruned_enh_bands", "pruned_enh", "dtw_started",
                "dtw_abandoned", "cells", "fp64_rechecks")
 MAX_L = 2048
@@ -74,6 +75,10 @@ SIGNATURES = {
     "nndtw_ed2": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _P]),
     "nndtw_lb_keogh": (ctypes.c_int, [_P, _I64, _P, _P, _I64, _I32, _I32, _P, _P]),
     "nndtw_lb_enhanced": (ctypes.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _I32, _I32, _P, _I32, _P, _P]),
+    "nndtw_lb_kim": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _P]),
+    "nndtw_lb_improved": (ctypes.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _I32, _P, _I32, _P, _P]),
+    "nndtw_lb_new": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _I32, _P, _P]),
+    "nndtw_lb_enhanced_sym": (ctypes.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P]),
     "nndtw_dtw_w": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _I32, _P, _P]),
     "nndtw_dtw_w_f64": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _I32, _P, _P]),
     "nndtw_dtw_codes_bytes": (ctypes.c_int, [_I64, _I64, _I32, _I32, _I32, ctypes.POINTER(_SZ)]),
@@ -85,6 +90,7 @@ SIGNATURES = {
                                                     ctypes.POINTER(_SearchOpts), ctypes.POINTER(_SZ)]),
     "nndtw_search": (ctypes.c_int, [ctypes.POINTER(_Refset), _P, _I64, ctypes.POINTER(_SearchOpts), _P, _P,
                                     _P, _P, _SZ, _P]),
+    "nndtw_search_plan": (ctypes.c_int, [ctypes.POINTER(_Refset), ctypes.POINTER(_SearchOpts)]),
     "nndtw_cascade_bounds": (ctypes.c_int, [ctypes.POINTER(_Refset), _P, _I64, _I32, _P, _P, _P, _P, _P]),
     "nndtw_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(_BatchSet), _I32, ctypes.POINTER(_SearchOpts),
                                                    ctypes.POINTER(_SZ)]),
@@ -183,6 +189,43 @@ def lb_enhanced(A, B, U, Lo, W: int, V: int, cutoff=None, zip_: bool = False):
     cut = _cutoff(cutoff, A.shape[0], A.device)
     _check(lib().nndtw_lb_enhanced(_ptr(A), A.shape[0], _ptr(B), _ptr(U), _ptr(Lo), B.shape[0], A.shape[1],
                                    int(W), int(V), _ptr(cut), int(zip_), _ptr(out), _stream()))
+    return out
+
+
+def lb_kim(A, B, zip_: bool = False):
+    """LB_Kim, sum of the corner, minimum and maximum features without repetitions."""
+    A, B = _series(A, "A"), _series(B, "B")
+    out = torch.empty(_pair_shape(A.shape[0], B.shape[0], zip_), dtype=torch.float64, device=A.device)
+    _check(lib().nndtw_lb_kim(_ptr(A), A.shape[0], _ptr(B), B.shape[0], A.shape[1], int(zip_), _ptr(out),
+                              _stream()))
+    return out
+
+
+def lb_improved(A, B, U, Lo, W: int, cutoff=None, zip_: bool = False):
+    """LB_Improved = LB_Keogh(A, B) + LB_Keogh(B, A'); +inf where LB_Keogh(A, B) > cutoff."""
+    A, B, U, Lo = _series(A, "A"), _series(B, "B"), _series(U, "U"), _series(Lo, "Lo")
+    out = torch.empty(_pair_shape(A.shape[0], B.shape[0], zip_), dtype=torch.float64, device=A.device)
+    cut = _cutoff(cutoff, A.shape[0], A.device)
+    _check(lib().nndtw_lb_improved(_ptr(A), A.shape[0], _ptr(B), _ptr(U), _ptr(Lo), B.shape[0], A.shape[1],
+                                   int(W), _ptr(cut), int(zip_), _ptr(out), _stream()))
+    return out
+
+
+def lb_new(A, B, W: int, zip_: bool = False):
+    """LB_New: corner costs plus, per interior point, the nearest value of B in its window."""
+    A, B = _series(A, "A"), _series(B, "B")
+    out = torch.empty(_pair_shape(A.shape[0], B.shape[0], zip_), dtype=torch.float64, device=A.device)
+    _check(lib().nndtw_lb_new(_ptr(A), A.shape[0], _ptr(B), B.shape[0], A.shape[1], int(W), int(zip_),
+                              _ptr(out), _stream()))
+    return out
+
+
+def lb_enhanced_sym(A, B, U, Lo, W: int, V: int, zip_: bool = False):
+    """max(LB_Enhanced^V(A, B), LB_Enhanced^V(B, A)); U, Lo are B's envelopes."""
+    A, B, U, Lo = _series(A, "A"), _series(B, "B"), _series(U, "U"), _series(Lo, "Lo")
+    out = torch.empty(_pair_shape(A.shape[0], B.shape[0], zip_), dtype=torch.float64, device=A.device)
+    _check(lib().nndtw_lb_enhanced_sym(_ptr(A), A.shape[0], _ptr(B), _ptr(U), _ptr(Lo), B.shape[0], A.shape[1],
+                                       int(W), int(V), int(zip_), _ptr(out), _stream()))
     return out
 
 

@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -33,13 +34,37 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
+RESOURCES = os.path.join(BUILD, "kernel_resources.txt")
+
+
+def _compile(src: str):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, "-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
-    return obj
+    return obj, _resources(r.stderr)
+
+
+def _resources(remarks: str):
+    """(kernel, VGPRs, AGPRs, scratch bytes per lane) from the compiler's
+    kernel-resource-usage remarks."""
+    out, cur = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            cur = {"name": m.group(1)}
+            continue
+        if cur is None:
+            continue
+        for key, pat in (("v", r"VGPRs: (\d+)"), ("a", r"AGPRs: (\d+)"), ("s", r"ScratchSize \[bytes/lane\]: (\d+)")):
+            m = re.search(pat, line)
+            if m:
+                cur[key] = int(m.group(1))
+        if all(k in cur for k in "vas"):
+            out.append((cur["name"], cur["v"], cur["a"], cur["s"]))
+            cur = None
+    return out
 
 
 def build(verbose: bool = False) -> str:
@@ -47,7 +72,13 @@ def build(verbose: bool = False) -> str:
     srcs = sources()
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, srcs))
+        done = list(ex.map(_compile, srcs))
+    objs = [o for o, _ in done]
+    with open(RESOURCES, "w") as f:
+        f.write("# kernel VGPRs AGPRs scratch_bytes_per_lane (gfx950)\n")
+        for _, res in done:
+            for name, v, a, sc in res:
+                f.write(f"{name} {v} {a} {sc}\n")
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -146,6 +146,52 @@ int nndtw_lb_enhanced(const float *A, int64_t nA, const float *B, const float *U
     return launch_pair_bounds(2, A, nA, B, U, Lo, nB, L, W, V, cutoff, pairing, out, (hipStream_t)stream);
 }
 
+// Comparison bounds: what = 0 LB_Kim, 1 LB_Improved, 2 LB_New, 3 symmetric LB_Enhanced.
+static int compare_common(int what, const float *A, int64_t nA, const float *B, const float *U, const float *Lo,
+                          int64_t nB, int32_t L, int32_t W, int32_t V, const double *cutoff, int32_t pairing,
+                          double *out, void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_len_w(L, W));
+    REQUIRE(V >= 1, "V=%d: the number of bands must be >= 1", V);
+    TRY(check_pairing(pairing, nA, nB));
+    const bool any = nA > 0 && nB > 0;
+    const bool env = what == 1 || what == 3;
+    TRY(check_ptr(A, 4, "A", any));
+    TRY(check_ptr(B, 4, "B", any));
+    TRY(check_ptr(U, 4, "U", any && env));
+    TRY(check_ptr(Lo, 4, "Lo", any && env));
+    TRY(check_ptr(out, 8, "out", any));
+    if (cutoff) TRY(check_ptr(cutoff, 8, "cutoff", any));
+    if (compare_lds_bytes(L, W) > 160 * 1024)
+        return fail(NNDTW_EUNSUP, "series length %d too long for the comparison bounds", L);
+    return launch_compare_bounds(what, A, nA, B, U, Lo, nB, L, W, V, cutoff, pairing, out, (hipStream_t)stream);
+}
+
+int nndtw_lb_kim(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L, int32_t pairing, double *out,
+                 void *stream)
+{
+    return compare_common(0, A, nA, B, nullptr, nullptr, nB, L, 0, 1, nullptr, pairing, out, stream);
+}
+
+int nndtw_lb_improved(const float *A, int64_t nA, const float *B, const float *U, const float *Lo, int64_t nB,
+                      int32_t L, int32_t W, const double *cutoff, int32_t pairing, double *out, void *stream)
+{
+    return compare_common(1, A, nA, B, U, Lo, nB, L, W, 1, cutoff, pairing, out, stream);
+}
+
+int nndtw_lb_new(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L, int32_t W, int32_t pairing,
+                 double *out, void *stream)
+{
+    return compare_common(2, A, nA, B, nullptr, nullptr, nB, L, W, 1, nullptr, pairing, out, stream);
+}
+
+int nndtw_lb_enhanced_sym(const float *A, int64_t nA, const float *B, const float *U, const float *Lo, int64_t nB,
+                          int32_t L, int32_t W, int32_t V, int32_t pairing, double *out, void *stream)
+{
+    return compare_common(3, A, nA, B, U, Lo, nB, L, W, V, nullptr, pairing, out, stream);
+}
+
 static int dtw_common(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int32_t L, int32_t W,
                       const double *cutoff, int32_t pairing, void *out, void *stream)
 {
@@ -261,7 +307,8 @@ static int check_opts(const nndtw_search_opts *o)
 {
     REQUIRE(o != nullptr, "opts is NULL");
     REQUIRE(o->V >= 1, "V=%d: the number of bands must be >= 1", o->V);
-    REQUIRE(o->cascade >= NNDTW_CASCADE_NONE && o->cascade <= NNDTW_CASCADE_ENH, "cascade=%d unknown", o->cascade);
+    REQUIRE(o->cascade >= NNDTW_CASCADE_NONE && o->cascade <= NNDTW_CASCADE_ENH_SYM, "cascade=%d unknown",
+            o->cascade);
     REQUIRE(o->R >= 0, "R=%lld must be >= 0", (long long)o->R);
     REQUIRE(o->cpl >= 0, "cpl=%d must be >= 0", o->cpl);
     REQUIRE(o->waves >= 0 && o->waves <= NNDTW_SEARCH_MAX_WAVES, "waves=%d must be in 0..%d", o->waves,
@@ -278,6 +325,19 @@ int nndtw_search_workspace_bytes(const nndtw_refset *refset, int64_t nQ, const n
     REQUIRE(nQ >= 0, "nQ=%lld must be >= 0", (long long)nQ);
     REQUIRE(bytes != nullptr, "bytes is NULL");
     *bytes = search_ws_bytes(nQ, refset->n, refset->L);
+    return NNDTW_OK;
+}
+
+int nndtw_search_plan(const nndtw_refset *refset, nndtw_search_opts *opts)
+{
+    g_err[0] = 0;
+    TRY(check_refset(refset));
+    TRY(check_opts(opts));
+    SearchPlan plan;
+    TRY(plan_search(refset, opts, &plan));
+    opts->R = plan.R;
+    opts->cpl = plan.C;
+    opts->waves = plan.NW;
     return NNDTW_OK;
 }
 
@@ -299,6 +359,8 @@ int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ, nndtw_s
     TRY(check_ptr(ws, 256, "ws", any));
     const size_t need = search_ws_bytes(nQ, refset->n, refset->L);
     REQUIRE(!any || ws_bytes >= need, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    if (opts->cascade > NNDTW_CASCADE_ENH && compare_lds_bytes(refset->L, refset->W) > 160 * 1024)
+        return fail(NNDTW_EUNSUP, "series length %d too long for the comparison bounds", refset->L);
     SearchPlan plan;
     TRY(plan_search(refset, opts, &plan));
     opts->R = plan.R;
@@ -386,6 +448,8 @@ static int check_batch(const nndtw_batch_set *sets, int32_t nsets, const nndtw_s
     REQUIRE(nsets >= 1, "nsets=%d must be >= 1", nsets);
     TRY(check_opts(opts));
     REQUIRE(opts->events == nullptr, "opts->events must be NULL for a batch");
+    if (opts->cascade > NNDTW_CASCADE_ENH)
+        return fail(NNDTW_EUNSUP, "cascade=%d: the batched search runs the paper's cascades only", opts->cascade);
     for (int d = 0; d < nsets; ++d) {
         const nndtw_batch_set &s = sets[d];
         if (int r = check_refset(s.refset)) return set_error(r, d);

@@ -51,6 +51,11 @@ struct BatchHdr;
 struct EngineGeom;
 int launch_batch_bounds(const BatchSet *sets, int nsets, const int64_t *tile_start, int64_t tiles,
                         BatchHdr *hdr, hipStream_t s);
+// compare.hip: what = 0 LB_Kim, 1 LB_Improved, 2 LB_New, 3 symmetric LB_Enhanced
+int launch_compare_bounds(int what, const float *A, int64_t nA, const float *B, const float *U,
+                          const float *Lo, int64_t nB, int L, int W, int V, const double *cutoff,
+                          int pairing, double *out, hipStream_t s);
+size_t compare_lds_bytes(int L, int W);
 // dtw.hip
 int launch_dtw_pairs(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L,
                      int W, const double *cutoff, int pairing, void *out, hipStream_t s);

@@ -42,7 +42,8 @@ int choose_cpl(int Wp, int cmax, int prefer, int chard)
         for (int C : cands) {
             if (C > chard || (pass == 0 && C > cmax)) continue;
             double s = cpl_score(Wp, C);
-            if (s > bs * 1.02) {   // a larger C must pay for its latency
+            if (s <= 0.0) continue;  // a group wider than the wave: no shape
+            if (s > bs * 1.02) {     // a larger C must pay for its latency
                 bs = s;
                 best = C;
             }
@@ -130,6 +131,7 @@ static int launch_pairs_t(const float *A, int64_t nA, const float *B, int64_t nB
     const int C = choose_cpl(Wp, 16, 0);
     if (C < 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
     EngineGeom g = make_geom(L, W, C, prefetch_lds(C), window_lds(C));
+    if (g.P < 1) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
     // Tasks staged per batch: two per group so that groups refill, within
     // 64 KB of LDS (at least one).
     int NB = 2 * g.P < 64 ? 2 * g.P : 64;

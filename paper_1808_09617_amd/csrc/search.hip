@@ -34,7 +34,11 @@
 
 namespace nndtw {
 
-#define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(9) X(12)
+// Engine shapes of the search kernel: every one compiles within the
+// register file at 8 waves per workgroup (no spill to scratch memory), so
+// the search takes windows with min(W, L-1) + 1 <= 63 * SEARCH_MAX_CPL.
+#define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(9)
+constexpr int SEARCH_MAX_CPL = 9;
 
 constexpr int QCAP = 128;        // survivor ring (>= 64 + max staged rows)
 constexpr int SEARCH_MAX_WAVES = NNDTW_SEARCH_MAX_WAVES;
@@ -289,16 +293,28 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v)
     return v;
 }
 
-// 0 survives, 1 LB_Keogh, 2 LB_Enhanced bands, 3 LB_Enhanced
-__device__ __forceinline__ int stage_of(int cascade, double lbk, double lbb, double lbe, double thr)
+// The stage whose bound prunes (0: the candidate survives).  b1, b2, b3 are
+// the cascade's bounds in the order they are tested: LB_Keogh, LB_Enhanced
+// bands part, full LB_Enhanced for the paper's cascades; for the comparison
+// cascades b1 holds LB_Kim / LB_New / LB_Keogh (LB_Improved's first pass) and
+// b3 LB_Improved / the symmetric LB_Enhanced.
+__device__ __forceinline__ int stage_of(int cascade, double b1, double b2, double b3, double thr)
 {
-    if (cascade == NNDTW_CASCADE_KEOGH || cascade == NNDTW_CASCADE_KEOGH_ENH)
-        if (lbk > thr) return 1;
-    if (cascade == NNDTW_CASCADE_KEOGH_ENH || cascade == NNDTW_CASCADE_ENH) {
-        if (lbb > thr) return 2;
-        if (lbe > thr) return 3;
+    switch (cascade) {
+    case NNDTW_CASCADE_KEOGH:
+    case NNDTW_CASCADE_KIM:
+    case NNDTW_CASCADE_NEW:
+        return b1 > thr ? 1 : 0;
+    case NNDTW_CASCADE_KEOGH_ENH:
+        return b1 > thr ? 1 : (b2 > thr ? 2 : (b3 > thr ? 3 : 0));
+    case NNDTW_CASCADE_ENH:
+    case NNDTW_CASCADE_ENH_SYM:
+        return b2 > thr ? 2 : (b3 > thr ? 3 : 0);
+    case NNDTW_CASCADE_IMPROVED:
+        return b1 > thr ? 1 : (b3 > thr ? 3 : 0);
+    default:
+        return 0;
     }
-    return 0;
 }
 
 // One workgroup of NW waves per query.  All waves run the same control flow
@@ -568,15 +584,19 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
 {
     const int L = rs->L;
     const int Wp = rs->W < L - 1 ? rs->W : L - 1;
-    // At 16 pairs per lane the search kernel (FP32 and FP64 engines) needs
-    // more than 256 VGPRs and spills to AGPRs; that shape stalled on the GPU
-    // and is not used until the cause is understood.
-    const int C = choose_cpl(Wp, 4, o->cpl, 12);
-    if (C < 0) return fail(o->cpl > 0 ? NNDTW_EINVAL : NNDTW_EUNSUP,
-                           "no DTW engine shape for W=%d (cpl=%d)", rs->W, o->cpl);
+    // Only shapes up to SEARCH_MAX_CPL pairs per lane are compiled for the
+    // search: it takes windows with min(W, L-1) + 1 <= 63 * SEARCH_MAX_CPL.
+    const int C = choose_cpl(Wp, 4, o->cpl, SEARCH_MAX_CPL);
+    if (C < 0 && o->cpl <= 0)
+        return fail(NNDTW_EUNSUP, "window W=%d too wide for the search (min(W, L-1) + 1 <= %d)", rs->W,
+                    63 * SEARCH_MAX_CPL);
+    if (C < 0) return fail(NNDTW_EINVAL, "no search engine shape with cpl=%d for W=%d", o->cpl, rs->W);
     EngineGeom g = make_geom(L, rs->W, C, prefetch_global(C), window_global(C));
     const EngineGeom gd = make_geom(L, rs->W, C, recheck_prefetch(C), recheck_window(C));
     const int P = g.P;
+    // at least one pair of series per wave, hence a round of at least one
+    // candidate (the search divides positions by R)
+    if (P < 1) return fail(NNDTW_EUNSUP, "no DTW engine shape for W=%d with %d pairs per lane", rs->W, C);
     const int NW = o->waves > 0 ? o->waves : SEARCH_DEFAULT_WAVES;
     // Default round: two candidates per group, so that groups whose
     // candidate is abandoned early take another one within the round.
@@ -634,6 +654,19 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     int r = mark(0);
     if (r) return r;
     r = launch_cascade_bounds(rs, Qy, nQ, o->V, ed2, lbk, lbeb, lbe, st);
+    if (r) return r;
+    // comparison cascades: their bound replaces b1 or b3 (see stage_of)
+    switch (o->cascade) {
+    case NNDTW_CASCADE_KIM: r = launch_compare_bounds(0, Qy, nQ, rs->B, rs->U, rs->Lo, n, L, rs->W, o->V, nullptr,
+                                                      NNDTW_CROSS, lbk, st); break;
+    case NNDTW_CASCADE_IMPROVED: r = launch_compare_bounds(1, Qy, nQ, rs->B, rs->U, rs->Lo, n, L, rs->W, o->V,
+                                                           nullptr, NNDTW_CROSS, lbe, st); break;
+    case NNDTW_CASCADE_NEW: r = launch_compare_bounds(2, Qy, nQ, rs->B, rs->U, rs->Lo, n, L, rs->W, o->V, nullptr,
+                                                      NNDTW_CROSS, lbk, st); break;
+    case NNDTW_CASCADE_ENH_SYM: r = launch_compare_bounds(3, Qy, nQ, rs->B, rs->U, rs->Lo, n, L, rs->W, o->V,
+                                                          nullptr, NNDTW_CROSS, lbe, st); break;
+    default: break;
+    }
     if (r) return r;
     if ((r = mark(1))) return r;
     if ((r = launch_cells_prefix(L, plan.Wp, prefix, st))) return r;

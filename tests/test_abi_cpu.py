@@ -91,6 +91,25 @@ def test_pairwise_validation():
     assert _err(lib.nndtw_dtw_w_f64(FAKE, 3, FAKE, 4, 64, 2, NULL, 0, ctypes.c_void_p(0x100004), NULL),
                 "out is not 8-byte aligned") == nd.EINVAL
     assert lib.nndtw_dtw_w(NULL, 0, NULL, 5, 64, 2, NULL, 0, NULL, NULL) == 0      # empty
+    # 1501 window diagonal pairs exceed 63 lanes x 16 pairs: no engine shape
+    assert _err(lib.nndtw_dtw_w(FAKE, 3, FAKE, 4, 2048, 1500, NULL, 0, FAKE, NULL), "too wide") == nd.EUNSUP
+
+
+def test_comparison_bounds_validation():
+    lib = nd.lib()
+    assert _err(lib.nndtw_lb_kim(FAKE, 3, FAKE, 4, 1, 0, FAKE, NULL), "L=1") == nd.EINVAL
+    assert _err(lib.nndtw_lb_kim(FAKE, 3, NULL, 4, 64, 0, FAKE, NULL), "B is NULL") == nd.EINVAL
+    assert lib.nndtw_lb_kim(NULL, 0, NULL, 4, 64, 0, NULL, NULL) == 0                  # empty
+    assert _err(lib.nndtw_lb_improved(FAKE, 3, FAKE, NULL, FAKE, 4, 64, 3, NULL, 0, FAKE, NULL),
+                "U is NULL") == nd.EINVAL
+    assert _err(lib.nndtw_lb_improved(FAKE, 3, FAKE, FAKE, FAKE, 4, 64, -1, NULL, 0, FAKE, NULL),
+                "W=-1") == nd.EINVAL
+    assert _err(lib.nndtw_lb_new(FAKE, 3, FAKE, 4, 64, 3, nd.ZIP, FAKE, NULL), "nA == nB") == nd.EINVAL
+    assert _err(lib.nndtw_lb_new(FAKE, 3, FAKE, 3, 4096, 3, nd.ZIP, FAKE, NULL), "exceeds") == nd.EUNSUP
+    assert _err(lib.nndtw_lb_enhanced_sym(FAKE, 3, FAKE, FAKE, FAKE, 4, 64, 3, 0, 0, FAKE, NULL),
+                "V=0") == nd.EINVAL
+    assert _err(lib.nndtw_lb_enhanced_sym(FAKE, 3, FAKE, FAKE, FAKE, 4, 64, 3, 2, 0, ctypes.c_void_p(0x100004),
+                                          NULL), "out is not 8-byte aligned") == nd.EINVAL
 
 
 def test_refset_and_search_validation():
@@ -174,6 +193,9 @@ def test_batch_validation_and_workspace_size():
     ev.events = FAKE
     assert _err(lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(ev), ctypes.byref(nbytes)),
                 "events must be NULL") == nd.EINVAL
+    cmp = nd._opts(5, "improved", 0, 0.0, True, 0)
+    assert _err(lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(cmp), ctypes.byref(nbytes)),
+                "paper's cascades only") == nd.EUNSUP
     assert _err(lib.nndtw_search_batch(None, FAKE, NULL), "plan is NULL") == nd.EINVAL
     assert _err(lib.nndtw_search_batch(ctypes.byref(plan), FAKE, NULL), "not made by") == nd.EINVAL
 
@@ -182,3 +204,44 @@ def test_python_binding_rejects_cpu_tensors():
     import torch
     with pytest.raises(TypeError):
         nd.envelopes(torch.zeros(3, 8), 2)
+
+
+def test_search_plan_has_a_shape_for_every_window():
+    """For every window the host plan is a shape whose groups fit a wave
+    (at least one pair of series per wave, so a round of at least one
+    candidate), or EUNSUP beyond 63 lanes x 9 pairs.  (A plan with zero
+    groups per wave once gave a round size of 0, which the kernel divides by.)"""
+    lib = nd.lib()
+    for L in (2, 64, 300, 512, 2048):
+        d = nd._Refset()
+        d.magic, d.L, d.n = nd.REFSET_MAGIC, L, 100
+        d.padl, d.ppitch = 4096, 16384                      # margins wide enough for any shape
+        for W in sorted(set(range(0, min(L, 600) + 1)) | {L - 1, L, 2 * L}):
+            d.W = W
+            Wp = min(W, L - 1)
+            opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
+            st = lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts))
+            if Wp + 1 > 63 * 9:
+                assert _err(st, "too wide for the search") == nd.EUNSUP
+                continue
+            assert st == 0, (L, W, nd.last_error())
+            C = opts.cpl
+            G = -(-(Wp + 1) // C)
+            assert C in (1, 2, 3, 4, 6, 8, 9) and G <= 63, (L, W, C, G)
+            assert opts.R == 2 * (63 // G) * opts.waves >= 1, (L, W, opts.R)
+    d.W = 251
+    opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 2)              # 126 lanes per group: no fit
+    assert _err(lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)), "cpl=2") == nd.EINVAL
+
+
+def test_search_kernels_fit_the_register_file():
+    """Every search kernel shape compiles without spilling to scratch memory
+    (the resource report the build writes from the compiler's remarks)."""
+    from paper_1808_09617_amd import build as hipbuild
+    if not os.path.exists(hipbuild.RESOURCES):
+        hipbuild.build()
+    rows = [l.split() for l in open(hipbuild.RESOURCES) if l.strip() and not l.startswith("#")]
+    search = [r for r in rows if "search_kernel" in r[0]]
+    assert len(search) >= 2 * 4 + 2 * 4                     # 4 shapes x 2, single-set and batched
+    for name, v, a, scratch in search:
+        assert int(scratch) == 0 and int(a) == 0 and int(v) <= 256, (name, v, a, scratch)

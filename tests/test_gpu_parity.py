@@ -276,11 +276,7 @@ def test_search_waves_per_query(waves):
     check_search(refs, series(5, 64, seed=32), 12, 2, "keogh_enh", 0, True, 1, waves=waves)
 
 
-@pytest.mark.parametrize("W", [5, 51, 128,
-                               pytest.param(256, marks=pytest.mark.skip(reason="large-window search stalled on the "
-                                            "GPU (16 pairs per lane); path switched off, cause not yet shown")),
-                               pytest.param(511, marks=pytest.mark.skip(reason="large-window search not yet run on "
-                                            "the GPU after the W=256 stall"))])
+@pytest.mark.parametrize("W", [5, 51, 128, 256, 511])
 def test_search_mix512_sampled(W):
     wl = synth.workload("nndtw-mix512", n_refs=5000, n_queries=500)
     sel = np.arange(0, 500, 125)          # sampled queries of the full workload
@@ -407,7 +403,7 @@ def test_batch_full_workload_sampled():
 
 
 # ------------------------------------------------------------------ DTW backward
-@pytest.mark.parametrize("L,W", [(2, 1), (17, 0), (17, 4), (64, 6), (64, 63), (256, 26), (300, 100)])
+@pytest.mark.parametrize("L,W", [(2, 1), (17, 0), (17, 4), (64, 6), (64, 63), (256, 26), (300, 100), (600, 300)])
 def test_dtw_backward_f64_matches_oracle(L, W):
     """FP64 forward with codes: distances bit-exact; the gradient with respect
     to the queries equal to the oracle's up to the order of its sums."""
@@ -556,3 +552,89 @@ def test_serving_results_equal_alone():
         _, _, _, R = nd.search(rss[r.set_id], r.query[None], V=5)
         oi, od, oc = oracle.search(refs, q, W, 5, "keogh_enh", R, True)
         assert r.result[0] == oi[0] and r.result[1] == od[0] and r.result[2][:5] == oc[0, :5].tolist()
+
+
+# ------------------------------------------------------------ comparison bounds
+# LB_Kim, LB_Improved, LB_New and the symmetric LB_Enhanced: FP64 sums in
+# ascending point order (one lane per sum), so bit-exact against the oracle.
+CMP_CASES = [(2, 0), (2, 1), (3, 1), (5, 2), (17, 4), (64, 6), (64, 63), (97, 13), (256, 26), (300, 100),
+             (512, 128), (512, 511), (1000, 37), (2048, 205), (2048, 2047)]
+
+
+@pytest.mark.parametrize("L,W", CMP_CASES)
+def test_comparison_bounds_bit_exact(L, W):
+    nA, nB = (4, 5) if L >= 1000 else (7, 9)
+    A = series(nA, L, seed=3 * L + W)
+    B = series(nB, L, seed=3 * L + W + 1, kind="sin5")
+    say("compare", L, W)
+    dA, dB = dev(A), dev(B)
+    U, Lo = nd.envelopes(dB, W)
+    assert np.array_equal(host(nd.lb_kim(dA, dB)), oracle.lb_kim(A, B))
+    assert np.array_equal(host(nd.lb_new(dA, dB, W)), oracle.lb_new(A, B, W))
+    imp = oracle.lb_improved(A, B, W)
+    assert np.array_equal(host(nd.lb_improved(dA, dB, U, Lo, W)), imp)
+    for V in (1, 5):
+        assert np.array_equal(host(nd.lb_enhanced_sym(dA, dB, U, Lo, W, V)), oracle.lb_enhanced_sym(A, B, W, V))
+    # second-pass skip: +inf exactly where LB_Keogh(A, B) exceeds the cutoff
+    ou, ol = oracle.envelopes(B, W)
+    k = oracle.lb_keogh(A, ou, ol)
+    cut = np.median(k, axis=1)
+    got = host(nd.lb_improved(dA, dB, U, Lo, W, cutoff=torch.from_numpy(cut).to(DEV)))
+    want = np.where(k > cut[:, None], np.inf, imp)
+    assert np.array_equal(got, want)
+    # zip pairing
+    Z = B[:nA]
+    dZ = dev(Z)
+    Uz, Lz = nd.envelopes(dZ, W)
+    assert np.array_equal(host(nd.lb_kim(dA, dZ, zip_=True)), oracle.lb_kim(A, Z, zip_=True))
+    assert np.array_equal(host(nd.lb_new(dA, dZ, W, zip_=True)), oracle.lb_new(A, Z, W, zip_=True))
+    assert np.array_equal(host(nd.lb_improved(dA, dZ, Uz, Lz, W, zip_=True)), oracle.lb_improved(A, Z, W, zip_=True))
+    assert np.array_equal(host(nd.lb_enhanced_sym(dA, dZ, Uz, Lz, W, 3, zip_=True)),
+                          oracle.lb_enhanced_sym(A, Z, W, 3, zip_=True))
+
+
+def test_comparison_bounds_special_inputs():
+    """Constant series (every point is an extreme: LB_Kim keeps only the
+    corners), exact copies (all bounds 0) and extremes at the series' ends."""
+    L = 40
+    base = series(6, L, seed=4242)
+    A = np.concatenate([np.zeros((1, L), np.float32), np.full((1, L), 3.0, np.float32), base])
+    B = np.concatenate([np.full((1, L), -2.0, np.float32), base[:1], base])
+    B[-1, 0] = B[-1].max() + 1.0                 # maximum at the first point
+    B[-2, -1] = B[-2].min() - 1.0                # minimum at the last point
+    A = np.ascontiguousarray(A)
+    B = np.ascontiguousarray(B)
+    for W in (0, 3, 39):
+        say("compare special", W)
+        dA, dB = dev(A), dev(B)
+        U, Lo = nd.envelopes(dB, W)
+        assert np.array_equal(host(nd.lb_kim(dA, dB)), oracle.lb_kim(A, B))
+        assert np.array_equal(host(nd.lb_new(dA, dB, W)), oracle.lb_new(A, B, W))
+        assert np.array_equal(host(nd.lb_improved(dA, dB, U, Lo, W)), oracle.lb_improved(A, B, W))
+        assert np.array_equal(host(nd.lb_enhanced_sym(dA, dB, U, Lo, W, 2)), oracle.lb_enhanced_sym(A, B, W, 2))
+        same = host(nd.lb_new(dev(base), dev(base), W, zip_=True))
+        assert np.all(same == 0.0)
+
+
+def test_comparison_bounds_tightness_pairs_zip():
+    """The benchmarked tightness pairs (sin5, L=256, W=26), sampled."""
+    a, b = synth.tightness_pairs(2000)
+    say("compare tightness pairs", a.shape)
+    da, db = dev(a), dev(b)
+    U, Lo = nd.envelopes(db, 26)
+    assert np.array_equal(host(nd.lb_kim(da, db, zip_=True)), oracle.lb_kim(a, b, zip_=True))
+    assert np.array_equal(host(nd.lb_new(da, db, 26, zip_=True)), oracle.lb_new(a, b, 26, zip_=True))
+    assert np.array_equal(host(nd.lb_improved(da, db, U, Lo, 26, zip_=True)), oracle.lb_improved(a, b, 26, zip_=True))
+    assert np.array_equal(host(nd.lb_enhanced_sym(da, db, U, Lo, 26, 5, zip_=True)),
+                          oracle.lb_enhanced_sym(a, b, 26, 5, zip_=True))
+
+
+@pytest.mark.parametrize("cascade", ["kim", "improved", "new", "enh_sym"])
+def test_search_comparison_cascades(cascade):
+    wl = synth.workload("nndtw-small")
+    for R in (0, 1, 7):
+        check_search(wl.refs, wl.queries, 6, 2, cascade, R)
+    sub = synth.workload("nndtw-sin256", n_refs=1000, n_queries=24)
+    check_search(sub.refs, sub.queries, 26, 5, cascade, 0, True, 0, brute=False)
+    mix = synth.workload("nndtw-mix512", n_refs=600, n_queries=6)
+    check_search(mix.refs, mix.queries, 51, 5, cascade, 0, True, 0, brute=False)

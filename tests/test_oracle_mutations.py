@@ -24,7 +24,8 @@ MUTATIONS = [
     ("enh: keogh middle starts one late", "for (int i = nb; i < L - nb; ++i) res += keogh_term", "for (int i = nb + 1; i < L - nb; ++i) res += keogh_term"),
     ("eq7: left/right switch point", "else if (i >= L - nb)  s += band_min", "else if (i > L - nb)  s += band_min"),
     ("band set: left band misses a mirrored link", "rows[n] = j; cols[n] = i; ++n;\n        }\n    } else {", "}\n    } else {"),
-    ("search: prune on >=", "if (oracle_lb_keogh(A, Uk, Lk, L) > thr)", "if (oracle_lb_keogh(A, Uk, Lk, L) >= thr)"),
+    ("search: prune on >=", "CASCADE_KEOGH_ENH) {\n                    if (oracle_lb_keogh(A, Uk, Lk, L) > thr)",
+     "CASCADE_KEOGH_ENH) {\n                    if (oracle_lb_keogh(A, Uk, Lk, L) >= thr)"),
     ("search: ties to the highest index", "return d < bd || (d == bd && k < bk);", "return d < bd || (d == bd && k > bk);"),
     ("search: order ties by reversed index", "return (a->idx > b->idx) - (a->idx < b->idx);", "return (a->idx < b->idx) - (a->idx > b->idx);"),
     ("search: no slack", "double thr = dmin(bsf, ub) * (1.0 + slack);", "double thr = dmin(bsf, ub);"),
