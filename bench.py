@@ -277,6 +277,110 @@ def batch_bench(nd, synth, torch, dev, reps=3, tuned=None):
     return out
 
 
+def _median_ms(torch, fn, reps):
+    times = []
+    out = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = fn()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return sorted(times)[len(times) // 2], out
+
+
+def window_sweep(nd, synth, torch, dev, reps=3):
+    """The window sweep: 5000 mixed references (random walks and class
+    sinusoids) x 500 queries, L=512, W = round(f L) for f in {0.01, 0.1,
+    0.25, 0.5, 1.0} (W = 5, 51, 128, 256, 511), V in {1, 5}, cascade
+    LB_Keogh -> LB_Enhanced^V.  Per (W, V): the reference-set build, the
+    search and their sum (end to end), pruning per stage, DTW cells/s."""
+    wl = synth.workload("nndtw-mix512")
+    refs = torch.from_numpy(wl.refs).to(dev)
+    qs = torch.from_numpy(wl.queries).to(dev)
+    N, Q = wl.refs.shape[0], wl.queries.shape[0]
+    rows = []
+    for W in wl.windows:
+        rs = nd.RefSet(refs, W)
+        t_build, _ = _median_ms(torch, lambda: rs.rebuild(refs), reps)
+        for V in wl.vs:
+            sr = nd.Searcher(rs, Q, V=V, cascade="keogh_enh")
+            sr(qs)
+            t_search, (_, _, c) = _median_ms(torch, lambda: sr(qs), reps)
+            c = c.cpu().numpy()
+            pairs = N * Q
+            rows.append({"W": W, "V": V, "cpl": sr.cpl, "R": sr.R, "build_ms": t_build, "search_ms": t_search,
+                         "end_to_end_ms": t_build + t_search, "queries_per_s": Q / ((t_build + t_search) / 1e3),
+                         "pruning_rate": 1.0 - int(c[:, 4].sum()) / pairs,
+                         "pruned": {"keogh": int(c[:, 1].sum()) / pairs, "enh_bands": int(c[:, 2].sum()) / pairs,
+                                    "enh": int(c[:, 3].sum()) / pairs},
+                         "dtw_cells_per_s": int(c[:, 6].sum()) / (t_search / 1e3)})
+            del sr
+        del rs
+    torch.cuda.empty_cache()
+    return {"workload": "nndtw-mix512", "N": N, "Q": Q, "L": wl.L, "rows": rows}
+
+
+COMPARE_CASCADES = (("kim", "kim"), ("keogh", "keogh"), ("improved", "improved"), ("new", "new"),
+                    ("enhanced5", "enh"), ("keogh_enhanced5", "keogh_enh"), ("enhanced5_sym", "enh_sym"))
+
+
+def compare_bounds(nd, synth, torch, dev, a, b, W=26):
+    """Synthetic analogues of the paper's comparisons (UCR is not available):
+    tightness LB/DTW of every bound on the independent class-sinusoid pairs
+    (L=256, W=26), and the NN-DTW search with each bound alone (plus the
+    cascade and the symmetric variant) on the benchmarked 1000 x 1000 set and
+    across the windows of the window sweep (V=5).  Search time includes the
+    bound pass, the ordering and the DTWs."""
+    A, B = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    U, Lo = nd.envelopes(B, W)
+    d = nd.dtw_w(A, B, W, zip_=True).double()
+    keep = d > 0
+    bounds = {"kim": nd.lb_kim(A, B, zip_=True), "keogh": nd.lb_keogh(A, U, Lo, zip_=True),
+              "improved": nd.lb_improved(A, B, U, Lo, W, zip_=True), "new": nd.lb_new(A, B, W, zip_=True),
+              "enhanced5_sym": nd.lb_enhanced_sym(A, B, U, Lo, W, 5, zip_=True)}
+    for v in (1, 2, 5):
+        bounds[f"enhanced{v}"] = nd.lb_enhanced(A, B, U, Lo, W, v, zip_=True)
+    tight = {k: float((x[keep] / d[keep]).mean()) for k, x in bounds.items()}
+    ms = {}
+    for k, x in bounds.items():
+        if k.startswith("enhanced") and k != "enhanced5":
+            continue
+        fn = {"kim": lambda: nd.lb_kim(A, B, zip_=True), "keogh": lambda: nd.lb_keogh(A, U, Lo, zip_=True),
+              "improved": lambda: nd.lb_improved(A, B, U, Lo, W, zip_=True),
+              "new": lambda: nd.lb_new(A, B, W, zip_=True),
+              "enhanced5": lambda: nd.lb_enhanced(A, B, U, Lo, W, 5, zip_=True),
+              "enhanced5_sym": lambda: nd.lb_enhanced_sym(A, B, U, Lo, W, 5, zip_=True)}[k]
+        fn()
+        ms[k], _ = _median_ms(torch, fn, 3)
+    del A, B, U, Lo, d, bounds
+
+    def search_rows(refs, qs, W, reps):
+        rs = nd.RefSet(refs, W)
+        out = {}
+        for name, cas in COMPARE_CASCADES:
+            sr = nd.Searcher(rs, qs.shape[0], V=5, cascade=cas)
+            sr(qs)
+            t, (_, _, c) = _median_ms(torch, lambda: sr(qs), reps)
+            c = c.cpu().numpy()
+            pairs = refs.shape[0] * qs.shape[0]
+            out[name] = {"search_ms": t, "queries_per_s": qs.shape[0] / (t / 1e3),
+                         "pruning_rate": 1.0 - int(c[:, 4].sum()) / pairs}
+            del sr
+        del rs
+        return out
+
+    wl = synth.workload("nndtw-sin256")
+    c2 = search_rows(torch.from_numpy(wl.refs).to(dev), torch.from_numpy(wl.queries).to(dev), W, 3)
+    mx = synth.workload("nndtw-mix512")
+    refs, qs = torch.from_numpy(mx.refs).to(dev), torch.from_numpy(mx.queries).to(dev)
+    c3 = {str(w): search_rows(refs, qs, w, 1) for w in mx.windows}
+    torch.cuda.empty_cache()
+    return {"tightness_pairs": int(keep.sum()), "W": W, "tightness": tight, "pairwise_ms_250k": ms,
+            "search_nndtw_sin256": c2, "search_nndtw_mix512_by_W": c3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,6 +395,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the per-query arm and tightness")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batching workload (defaults and autotuned), one JSON line each")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only the window sweep and the comparison bounds, one JSON line")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, one plain device copy of this many MiB (memory-counter calibration)")
     args = ap.parse_args()
@@ -309,6 +415,13 @@ def main():
         dev = torch.device("cuda:0")
         for tuned in (None, "auto"):
             print(json.dumps(batch_bench(nd, synth, torch, dev, tuned=tuned)), flush=True)
+        return
+
+    if args.sweep_only:
+        dev = torch.device("cuda:0")
+        a, b = synth.tightness_pairs(250_000)
+        print(json.dumps({"window_sweep": window_sweep(nd, synth, torch, dev),
+                          "compare_bounds": compare_bounds(nd, synth, torch, dev, a, b)}), flush=True)
         return
 
     wl = synth.workload("nndtw-sin256")
@@ -415,6 +528,10 @@ def main():
         for v in (1, 2, 5):
             tight[f"enhanced{v}"] = float((nd.lb_enhanced(A, B, U, Lo, W, v, zip_=True)[keep] / d[keep]).mean())
         res["tightness"] = tight
+        res["window_sweep"] = window_sweep(nd, synth, torch, dev)
+        log("window sweep done")
+        res["compare_bounds"] = compare_bounds(nd, synth, torch, dev, a, b, W)
+        log("comparison bounds done")
         res["hbm_streaming"] = hbm_streaming(nd, synth, torch, dev)
         res["backward"] = backward_bench(nd, synth, torch, dev, cpu=not args.no_cpu)
         res["serving"] = serving_bench(nd, synth, torch, dev)
