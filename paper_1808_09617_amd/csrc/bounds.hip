@@ -9,7 +9,8 @@
 //    middle points.
 //
 // Two kernels: a generic one over (A, B) pairs in row-major layout (one
-// thread per pair), and the fused pass of the search over a reference set,
+// thread per pair, rows staged through LDS in coalesced chunks), and the
+// fused pass of the search over a reference set,
 // where lanes index references and read the point-major copies (coalesced),
 // each thread carrying TQ queries so every reference value loaded from memory
 // is reused TQ times.  The query values are staged in LDS as doubles.
@@ -19,33 +20,67 @@ namespace nndtw {
 
 enum { PB_ED2 = 0, PB_KEOGH = 1, PB_ENH = 2 };
 
-__global__ void __launch_bounds__(256)
+// Generic pairs: a workgroup of PB_THREADS threads takes PB_THREADS
+// consecutive pairs, one per thread.  Rows are read in chunks of PB_CH
+// points: the workgroup loads the chunk of every pair's rows with
+// consecutive threads on consecutive points (64-byte row segments) into LDS,
+// then each thread adds its pair's terms from LDS in ascending point order,
+// as a sequential evaluation would.
+constexpr int PB_THREADS = 256;
+constexpr int PB_CH = 16;
+constexpr int PB_PITCH = PB_CH + 1;      // odd pitch: a thread's row reads hit distinct banks
+
+__global__ void __launch_bounds__(PB_THREADS)
 pair_bounds_kernel(int what, const float *__restrict__ A, int64_t nA, const float *__restrict__ B,
                    const float *__restrict__ U, const float *__restrict__ Lo, int64_t nB, int L, int W,
                    int nb, const double *__restrict__ cutoff, int pairing, double *__restrict__ out)
 {
+    __shared__ float ta[PB_THREADS * PB_PITCH], t1[PB_THREADS * PB_PITCH], t2[PB_THREADS * PB_PITCH];
     const int64_t np = pairing ? nA : nA * nB;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t ia = pairing ? p : p / nB, ib = pairing ? p : p % nB;
+    const int t = threadIdx.x;
+    for (int64_t p0 = (int64_t)blockIdx.x * PB_THREADS; p0 < np; p0 += (int64_t)gridDim.x * PB_THREADS) {
+        const int64_t p = p0 + t;
+        const bool live = p < np;
+        const int64_t ia = live ? (pairing ? p : p / nB) : 0, ib = live ? (pairing ? p : p % nB) : 0;
         const float *a = A + ia * L;
+        // middle points of LB_Enhanced (its bands part is computed first)
+        int lo = 0, hi = L;
         double s = 0.0;
-        if (what == PB_ED2) {
-            const float *b = B + ib * L;
-            for (int i = 0; i < L; ++i) s += sqd(a[i], b[i]);
-        } else if (what == PB_KEOGH) {
-            const float *u = U + ib * L, *l = Lo + ib * L;
-            for (int i = 0; i < L; ++i) s += keogh_term(a[i], u[i], l[i]);
-        } else {
-            const float *b = B + ib * L, *u = U + ib * L, *l = Lo + ib * L;
-            s = enh_bands([&](int i) { return a[i]; }, [&](int j) { return b[j]; }, L, W, nb);
-            if (cutoff && s > cutoff[ia]) {
-                s = __builtin_inf();
-            } else {
-                for (int i = nb; i < L - nb; ++i) s += keogh_term(a[i], u[i], l[i]);
+        bool skip = false;
+        if (what == PB_ENH) {
+            lo = nb;
+            hi = L - nb;
+            if (live) {
+                const float *b = B + ib * L;
+                s = enh_bands([&](int i) { return a[i]; }, [&](int j) { return b[j]; }, L, W, nb);
+                skip = cutoff && s > cutoff[ia];
             }
         }
-        out[p] = s;
+        // the second and third arrays: B (squared ED) or the envelopes U, Lo
+        const float *X1 = what == PB_ED2 ? B : U, *X2 = Lo;
+        for (int c0 = 0; c0 < L; c0 += PB_CH) {
+            const int cn = (L - c0) < PB_CH ? (L - c0) : PB_CH;
+            __syncthreads();
+            for (int e = t; e < PB_THREADS * PB_CH; e += PB_THREADS) {
+                const int r = e / PB_CH, x = e % PB_CH;
+                const int64_t q = p0 + r;
+                if (q < np && x < cn) {
+                    const int64_t qa = pairing ? q : q / nB, qb = pairing ? q : q % nB;
+                    ta[r * PB_PITCH + x] = A[qa * L + c0 + x];
+                    t1[r * PB_PITCH + x] = X1[qb * L + c0 + x];
+                    if (what != PB_ED2) t2[r * PB_PITCH + x] = X2[qb * L + c0 + x];
+                }
+            }
+            __syncthreads();
+            if (!live) continue;
+            const float *ra = ta + t * PB_PITCH, *r1 = t1 + t * PB_PITCH, *r2 = t2 + t * PB_PITCH;
+            for (int x = 0; x < cn; ++x) {
+                const int i = c0 + x;
+                if (i < lo || i >= hi) continue;
+                s += what == PB_ED2 ? sqd(ra[x], r1[x]) : keogh_term(ra[x], r1[x], r2[x]);
+            }
+        }
+        if (live) out[p] = skip ? __builtin_inf() : s;
     }
 }
 
@@ -56,8 +91,8 @@ int launch_pair_bounds(int what, const float *A, int64_t nA, const float *B, con
     const int64_t np = pairing ? nA : nA * nB;
     if (np == 0) return NNDTW_OK;
     const int nb = V < L / 2 ? V : L / 2;
-    const int64_t blocks = ceil_div(np, 256) < 65536 ? ceil_div(np, 256) : 65536;
-    hipLaunchKernelGGL(pair_bounds_kernel, dim3((unsigned)blocks), dim3(256), 0, st, what, A, nA, B, U,
+    const int64_t blocks = ceil_div(np, PB_THREADS) < 65536 ? ceil_div(np, PB_THREADS) : 65536;
+    hipLaunchKernelGGL(pair_bounds_kernel, dim3((unsigned)blocks), dim3(PB_THREADS), 0, st, what, A, nA, B, U,
                        Lo, nB, L, W, nb, cutoff, pairing, out);
     NNDTW_LAUNCH_CHECK("bounds kernel launch");
     return NNDTW_OK;

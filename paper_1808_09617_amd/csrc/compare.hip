@@ -117,10 +117,20 @@ __device__ void window_envelope(const float *x, int L, int w, float *U, float *L
     }
 }
 
-// In-order sum of t[lo .. hi) onto s (one lane).
+// In-order sum of t[lo .. hi) onto s (one lane).  The LDS loads of a block
+// of 16 terms are issued before its adds, so the load latency is paid once
+// per block instead of once per term; the additions keep their order.
 __device__ __forceinline__ double ordered_sum(double s, const double *t, int lo, int hi)
 {
-    for (int i = lo; i < hi; ++i) s += t[i];
+    int i = lo;
+    for (; i + 16 <= hi; i += 16) {
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = t[i + k];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += v[k];
+    }
+    for (; i < hi; ++i) s += t[i];
     return s;
 }
 
