@@ -102,7 +102,7 @@ int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, 
         std::memset(&b, 0, sizeof(b));
         SearchArgs &a = b.a;
         a.geo = make_geom(L, rs->W, sp.C, prefetch_global(sp.C), window_global(sp.C));
-        a.geoD = make_geom(L, rs->W, sp.C, recheck_prefetch(sp.C), recheck_window(sp.C));
+        a.geoD = recheck_geom(L, rs->W, sp.C);
         a.PD = sp.PD;
         a.SLOTS = sp.SLOTS;
         a.B = rs->B;

@@ -113,6 +113,12 @@ __host__ __device__ constexpr int window_global(int C) { return C == 3 ? 15 : C 
 // and must not raise the kernel's register count above the FP32 engine's).
 __host__ __device__ constexpr int recheck_prefetch(int C) { return prefetch_lds(C); }
 __host__ __device__ constexpr int recheck_window(int C) { return C + recheck_prefetch(C); }
+// Diagonal pairs per lane of the FP64 recheck: one when all of the window's
+// pairs fit in one wave, else the FP32 engine's C.  A recheck runs while the
+// query's other groups wait, so its latency (super-steps x instructions per
+// super-step) is on the query's critical path, and one pair per lane has the
+// shortest super-step.
+__host__ __device__ constexpr int recheck_cpl(int Wp, int C) { return Wp + 1 <= 63 ? 1 : C; }
 
 // Engine geometry shared by the DTW kernels (see dtw_engine.hpp).
 struct EngineGeom {
@@ -169,6 +175,21 @@ struct BatchHdr {
 // Choose the diagonal-pairs-per-lane C for a window (cmax bounds latency).
 int choose_cpl(int Wp, int cmax, int prefer, int chard = 16);
 EngineGeom make_geom(int L, int W, int C, int D, int M);
+// Geometry of the search's FP64 recheck for an FP32 engine of C pairs per lane.
+inline EngineGeom recheck_geom(int L, int W, int C)
+{
+    const int Wp = W < L - 1 ? W : L - 1;
+    const int CD = recheck_cpl(Wp, C);
+    return make_geom(L, W, CD, recheck_prefetch(CD), recheck_window(CD));
+}
+// Elements of the query row the search stages for both engines: the
+// recheck's rows start C - CD elements after the FP32 engine's (its left
+// padding is CD instead of C elements).
+__host__ __device__ inline int staged_len(const EngineGeom &g, const EngineGeom &gd)
+{
+    const int ld = gd.LEN + g.C - gd.C;
+    return g.LEN > ld ? g.LEN : ld;
+}
 bool cpl_supported(int C);
 
 }  // namespace nndtw

@@ -327,7 +327,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     const EngineGeom &geo = a.geo, &geoD = a.geoD;
     const int PD = a.PD, SLOTS = a.SLOTS;
     // the query row serves both engines: stage the longer of their rows
-    const int LENA = geo.LEN > geoD.LEN ? geo.LEN : geoD.LEN;
+    const int LENA = staged_len(geo, geoD);
     constexpr int DG = prefetch_global(C), MG = window_global(C), DD = recheck_prefetch(C), MD = recheck_window(C);
     float *aF = reinterpret_cast<float *>(smem);
     double *resD = reinterpret_cast<double *>(aF + ((LENA + 1) & ~1));
@@ -424,10 +424,19 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                 __syncthreads();
                 if (tid == 0) *next_task = 0;
                 __syncthreads();
-                engine_run<double, C, DD, MD, EXACT>(
-                    geoD, nd, next_task, [&](int) { return (const float *)aF; },
-                    [&](int i) { return Bp + (int64_t)rq[b0 + i] * a.ppitch; }, [&](int) { return thr; },
-                    TaskOut<double>{resD, trunD});
+                if (C > 1 && geoD.C == 1) {
+                    // one pair per lane: rows start C - 1 elements later
+                    constexpr int D1 = recheck_prefetch(1), M1 = recheck_window(1);
+                    engine_run<double, 1, D1, M1, true>(
+                        geoD, nd, next_task, [&](int) { return (const float *)aF + (C - 1); },
+                        [&](int i) { return Bp + (C - 1) + (int64_t)rq[b0 + i] * a.ppitch; },
+                        [&](int) { return thr; }, TaskOut<double>{resD, trunD});
+                } else {
+                    engine_run<double, C, DD, MD, EXACT>(
+                        geoD, nd, next_task, [&](int) { return (const float *)aF; },
+                        [&](int i) { return Bp + (int64_t)rq[b0 + i] * a.ppitch; }, [&](int) { return thr; },
+                        TaskOut<double>{resD, trunD});
+                }
                 __syncthreads();
                 for (int i = 0; i < nd; ++i) {
                     const double d = resD[i];
@@ -576,7 +585,7 @@ int launch_batch_search(int C, bool exact, const BatchSet *sets, const int64_t *
 
 size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD)
 {
-    const int LENA = g.LEN > gd.LEN ? g.LEN : gd.LEN;
+    const int LENA = staged_len(g, gd);
     return (size_t)((LENA + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 8 + QCAP * 4 + 64 * 4 + 16;
 }
 
@@ -592,7 +601,7 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
                     63 * SEARCH_MAX_CPL);
     if (C < 0) return fail(NNDTW_EINVAL, "no search engine shape with cpl=%d for W=%d", o->cpl, rs->W);
     EngineGeom g = make_geom(L, rs->W, C, prefetch_global(C), window_global(C));
-    const EngineGeom gd = make_geom(L, rs->W, C, recheck_prefetch(C), recheck_window(C));
+    const EngineGeom gd = recheck_geom(L, rs->W, C);
     const int P = g.P;
     // at least one pair of series per wave, hence a round of at least one
     // candidate (the search divides positions by R)
@@ -610,7 +619,7 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the search", L);
     // the engines read padded rows [base0 - PADL, base0 - PADL + LEN) of Bp
     const int64_t boff = rs->padl + g.base0 - C;
-    const int LENA = g.LEN > gd.LEN ? g.LEN : gd.LEN;
+    const int LENA = staged_len(g, gd);
     if (g.base0 != gd.base0 || boff < 0 || boff + LENA > rs->ppitch)
         return fail(NNDTW_EUNSUP, "reference set margins too narrow for the DTW engine shape");
     plan->Wp = Wp;
@@ -676,7 +685,7 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
 
     SearchArgs a;
     a.geo = make_geom(L, rs->W, plan.C, prefetch_global(plan.C), window_global(plan.C));
-    a.geoD = make_geom(L, rs->W, plan.C, recheck_prefetch(plan.C), recheck_window(plan.C));
+    a.geoD = recheck_geom(L, rs->W, plan.C);
     a.PD = plan.PD;
     a.SLOTS = plan.SLOTS;
     a.B = rs->B;
