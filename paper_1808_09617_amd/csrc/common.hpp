@@ -126,6 +126,7 @@ struct EngineGeom {
     int D;      // prefetch distance (super-steps)
     int M;      // window registers (super-steps per unrolled block)
     int T;      // super-steps (multiple of M)
+    int t0;     // first super-step a task executes (multiple of M, before the matrix)
     int base0;  // series index of the first super-step's base
     int LEN;    // elements per staged series in LDS (with padding)
 };

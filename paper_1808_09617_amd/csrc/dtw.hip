@@ -72,6 +72,11 @@ EngineGeom make_geom(int L, int W, int C, int D, int M)
     const int T0 = L + (g.Wp + 2) / 2;
     const int epad = (M - T0 % M) % M;
     g.T = T0 + epad;
+    // The first (W'+2)/2 super-steps lie wholly before the matrix, where a
+    // cell costs 0 with both indices in the padding and +inf with one: a task
+    // starts at the last block boundary among them with that state loaded
+    // directly (see engine_run).
+    g.t0 = ((g.Wp + 2) / 2) / M * M;
     g.base0 = -g.Wp - 1;
     g.LEN = g.T + g.Wp + 2 * C + D + 2;
     return g;

@@ -24,10 +24,13 @@
 // Boundaries without branches: the staged series are padded with a huge
 // value PAD on both sides.  A cell with both indices in the padding costs
 // (PAD - PAD)^2 = 0, a cell with exactly one index in the padding costs
-// (PAD - x)^2 = +inf (overflow).  Starting the sweep far enough before the
+// (PAD - x)^2 = +inf (overflow).  A sweep started far enough before the
 // matrix with every register at 0 therefore reproduces D(0,0) = delta(A_1,B_1)
 // exactly (the virtual predecessor is 0, the others +inf), and cells past the
-// matrix never feed D(L-1, L-1).
+// matrix never feed D(L-1, L-1).  The state that such a sweep reaches before
+// the matrix is known in closed form (0 where both indices are in the
+// padding, +inf elsewhere), so a task loads it directly at super-step t0, the
+// last block boundary before the matrix, and skips the steps before.
 //
 // Series values: the a-value of a bottom cell of pair m equals the a-value of
 // the top cell of pair m-1 and the b-value is shared by both cells of a pair,
@@ -202,7 +205,7 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
 {
     static_assert(M >= C + D, "window smaller than the live values");
     const int lane = threadIdx.x & (WAVE - 1);
-    const int G = geo.G, Wp = geo.Wp, T_ = geo.T;
+    const int G = geo.G, Wp = geo.Wp, T_ = geo.T, t0 = geo.t0;
     const int gi = lane >= 1 ? (lane - 1) / G : 0;
     const int gl = lane >= 1 ? (lane - 1) - gi * G : 0;
     const bool in_group = lane >= 1 && gi < geo.P;
@@ -232,6 +235,19 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
     for (int m = 0; m < M; ++m) { Aw[m] = (T)0; Bw[m] = (T)0; }
     if (force_last) X1[C - 1] = INF;
 
+    // State of this lane's cells before super-step t0 (all of it before the
+    // matrix), bit m for pair glc+m: pair p's bottom cell there is
+    // (i, j) = (t0+p-W'-2, t0-p-2) and its top cell (i+1, j); a cell inside
+    // the window is 0 with both indices in the padding (so is its path from
+    // the start), +inf with one index in it; outside the window +inf.
+    unsigned z0 = 0u, z1 = 0u;
+#pragma unroll
+    for (int m = 0; m < C; ++m) {
+        const int p = glc + m;
+        const int ib = t0 + p - Wp - 2, jb = t0 - p - 2;
+        z0 |= (p <= Wp && ib < 0 && jb < 0) ? (1u << m) : 0u;
+        z1 |= (p < Wp && ib + 1 < 0 && jb < 0) ? (1u << m) : 0u;
+    }
     int task = -1, tl = 0;
     bool dead = true, exhausted = false;
     static_assert(!Codes::on || M % 8 == 0, "codes need blocks of whole words");
@@ -274,23 +290,23 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
                 task = base + rank;
                 thr = thr_of(task);
                 dead = false;
+                tl = t0;
                 aP = arow(task) + Stage<C>::PADL + glc;
                 bP = brow(task) + Stage<C>::PADL + Wp - glc;
                 if constexpr (Codes::on) cb = codes_of(task) + glc;
 #pragma unroll
                 for (int m = 0; m < C; ++m) {
-                    const int p = glc + m;           // global pair index
-                    X0[m] = (!EXACT && p > Wp) ? INF : (T)0;
-                    X1[m] = (!EXACT && p >= Wp) ? INF : (T)0;
+                    X0[m] = ((z0 >> m) & 1u) ? (T)0 : INF;
+                    X1[m] = ((z1 >> m) & 1u) ? (T)0 : INF;
                 }
                 if (EXACT && force_last) X1[C - 1] = INF;
                 // a-slot m at super-step t is aP[t + m] in Aw[(t + m) % M];
                 // b-slot m is bP[t - m] in Bw[(t - m) mod M]: preload what
-                // super-steps 0..D-1 read.
+                // super-steps t0..t0+D-1 read (t0 is a multiple of M).
 #pragma unroll
-                for (int r = 0; r < C + D; ++r) Aw[r % M] = (T)aP[r];
+                for (int r = 0; r < C + D; ++r) Aw[r % M] = (T)aP[t0 + r];
 #pragma unroll
-                for (int r = 1 - C; r <= D - 1; ++r) Bw[((r % M) + M) % M] = (T)bP[r];
+                for (int r = 1 - C; r <= D - 1; ++r) Bw[((r % M) + M) % M] = (T)bP[t0 + r];
             }
         }
         if (__ballot(task >= 0) == 0ull) break;
