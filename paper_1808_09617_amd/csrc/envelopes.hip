@@ -6,12 +6,26 @@
 // LDS, the running max/min over every aligned block of p = 2^floor(log2(W'+1))
 // elements is built by doubling (log2 p passes), and each output takes the
 // max/min of at most four such blocks covering its window (max and min are
-// exact, so the result equals a direct scan).
+// exact, so the result equals a direct scan).  A wave touches only its own
+// row, so it synchronises with itself only: each pass is done in place in
+// ascending order, a group of chunks at a time, all reads of a group before
+// its writes (a later position is never overwritten before it is read).
 #include "common.hpp"
 
 namespace nndtw {
 
 constexpr int ENV_WAVES = 4;  // series per workgroup
+constexpr int ENV_GROUP = 8;  // 64-element chunks read before they are written
+
+// LDS accesses of one wave before this point complete before those after it
+// (LDS executes a wave's instructions in order; this stops the compiler from
+// moving them across).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ void __launch_bounds__(WAVE *ENV_WAVES)
 envelopes_kernel(const float *__restrict__ B, int64_t n, int L, int Wp, int p,
@@ -20,28 +34,39 @@ envelopes_kernel(const float *__restrict__ B, int64_t n, int L, int Wp, int p,
     extern __shared__ float lds[];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int64_t s = (int64_t)blockIdx.x * ENV_WAVES + w;
+    if (s >= n) return;                      // waves never wait for each other
     float *mx = lds + (size_t)w * 2 * L;
     float *mn = mx + L;
-    const bool live = s < n;
-    const float *b = B + (live ? s : 0) * (int64_t)L;
-    if (live)
-        for (int i = lane; i < L; i += WAVE) { float v = b[i]; mx[i] = v; mn[i] = v; }
-    __syncthreads();
-    // mx[i] <- max over [i, min(i+h, L-1)] ... doubling up to width p
+    const float *b = B + s * (int64_t)L;
+    for (int i = lane; i < L; i += WAVE) { float v = b[i]; mx[i] = v; mn[i] = v; }
+    wave_lds_sync();
+    // mx[i] <- max over [i, min(i + 2h - 1, L - 1)] for h = 1, 2, ... < p
     for (int h = 1; h < p; h <<= 1) {
-        for (int i0 = 0; i0 < L; i0 += WAVE) {
-            int i = i0 + lane;
-            float a1 = 0.f, a2 = 0.f, c1 = 0.f, c2 = 0.f;
-            if (live && i < L) {
-                int j = min(i + h, L - 1);
-                a1 = mx[i]; a2 = mx[j]; c1 = mn[i]; c2 = mn[j];
+        for (int g0 = 0; g0 < L; g0 += WAVE * ENV_GROUP) {
+            float a[ENV_GROUP], c[ENV_GROUP];
+#pragma unroll
+            for (int k = 0; k < ENV_GROUP; ++k) {
+                const int i = g0 + k * WAVE + lane;
+                const int j = min(i + h, L - 1);
+                a[k] = 0.f;
+                c[k] = 0.f;
+                if (i < L) {
+                    a[k] = fmaxf(mx[i], mx[j]);
+                    c[k] = fminf(mn[i], mn[j]);
+                }
             }
-            __syncthreads();
-            if (live && i < L) { mx[i] = fmaxf(a1, a2); mn[i] = fminf(c1, c2); }
-            __syncthreads();
+            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < ENV_GROUP; ++k) {
+                const int i = g0 + k * WAVE + lane;
+                if (i < L) {
+                    mx[i] = a[k];
+                    mn[i] = c[k];
+                }
+            }
+            wave_lds_sync();
         }
     }
-    if (!live) return;
     float *u = U + s * (int64_t)L, *l = Lo + s * (int64_t)L;
     for (int i = lane; i < L; i += WAVE) {
         int lo = max(0, i - Wp), hi = min(L - 1, i + Wp);

@@ -285,6 +285,16 @@ def test_search_mix512_sampled(W):
         check_search(refs, wl.queries[sel], W, V, "keogh_enh", 0, True, 0, brute=False)
 
 
+@pytest.mark.parametrize("L,W", [(2048, 205), (2048, 566), (1200, 566), (560, 559)])
+def test_search_long_series_and_widest_windows(L, W):
+    """Maximum length and the widest windows the search compiles (9 pairs per
+    lane, min(W, L-1) + 1 = 567), against the oracle at the same R."""
+    refs = series(60, L, seed=L + W, kind="rw")
+    queries = series(3, L, seed=L + W + 1, kind="rw")
+    for V in (1, 5):
+        check_search(refs, queries, W, V, "keogh_enh", 0, True, 0, brute=False)
+
+
 def test_search_full_sin256_properties():
     """Full-size workload in the benchmarked launch shape: every query's
     result is checked on a sample against the oracle and on all queries
