@@ -63,20 +63,19 @@ EngineGeom make_geom(int L, int W, int C, int D, int M)
     g.P = 63 / g.G;
     g.D = D;
     g.M = M;
-    // The sweep starts at the first anti-diagonal pair outside the matrix
-    // and runs T0 super-steps to (L-1, L-1), plus up to M-1 super-steps that
-    // round T up to whole blocks.  Those run past the end: both series are
-    // padded there with the same value, so every later cell of diagonal 0
-    // keeps DTW_W exactly (a pad pair costs 0, a pad against a value costs
-    // +inf); a DTW that is abandoned never reaches them.
+    // The sweep is numbered from the first anti-diagonal pair outside the
+    // matrix and reaches (L-1, L-1) after T0 super-steps.  Its first
+    // (W'+2)/2 super-steps lie wholly before the matrix, where a cell costs 0
+    // with both indices in the padding and +inf with one: a task starts at
+    // t0 = (W'+2)/2 with that state loaded directly (see engine_run) and runs
+    // whole blocks of M super-steps, so T = t0 + ceil((T0 - t0) / M) * M.
+    // The super-steps after T0 run past the end: both series are padded there
+    // with the same value, so every later cell of diagonal 0 keeps DTW_W
+    // exactly (a pad pair costs 0, a pad against a value costs +inf); a DTW
+    // that is abandoned never reaches them.
     const int T0 = L + (g.Wp + 2) / 2;
-    const int epad = (M - T0 % M) % M;
-    g.T = T0 + epad;
-    // The first (W'+2)/2 super-steps lie wholly before the matrix, where a
-    // cell costs 0 with both indices in the padding and +inf with one: a task
-    // starts at the last block boundary among them with that state loaded
-    // directly (see engine_run).
-    g.t0 = ((g.Wp + 2) / 2) / M * M;
+    g.t0 = (g.Wp + 2) / 2;
+    g.T = g.t0 + (int)ceil_div(T0 - g.t0, M) * M;
     g.base0 = -g.Wp - 1;
     g.LEN = g.T + g.Wp + 2 * C + D + 2;
     return g;

@@ -29,8 +29,9 @@
 // exactly (the virtual predecessor is 0, the others +inf), and cells past the
 // matrix never feed D(L-1, L-1).  The state that such a sweep reaches before
 // the matrix is known in closed form (0 where both indices are in the
-// padding, +inf elsewhere), so a task loads it directly at super-step t0, the
-// last block boundary before the matrix, and skips the steps before.
+// padding, +inf elsewhere), so a task loads it directly at super-step t0,
+// just before the matrix, and skips the steps before; blocks of M super-steps
+// (and the register rotation of the windows) count from t0.
 //
 // Series values: the a-value of a bottom cell of pair m equals the a-value of
 // the top cell of pair m-1 and the b-value is shared by both cells of a pair,
@@ -300,9 +301,9 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
                     X1[m] = ((z1 >> m) & 1u) ? (T)0 : INF;
                 }
                 if (EXACT && force_last) X1[C - 1] = INF;
-                // a-slot m at super-step t is aP[t + m] in Aw[(t + m) % M];
-                // b-slot m is bP[t - m] in Bw[(t - m) mod M]: preload what
-                // super-steps t0..t0+D-1 read (t0 is a multiple of M).
+                // a-slot m at super-step t is aP[t + m] in Aw[(t - t0 + m) % M];
+                // b-slot m is bP[t - m] in Bw[(t - t0 - m) mod M]: preload
+                // what super-steps t0..t0+D-1 read.
 #pragma unroll
                 for (int r = 0; r < C + D; ++r) Aw[r % M] = (T)aP[t0 + r];
 #pragma unroll

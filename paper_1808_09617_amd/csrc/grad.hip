@@ -54,7 +54,10 @@ int codes_geom(int64_t nA, int64_t nB, int L, int W, int pairing, bool f64, Code
     if (C < 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
     cg->g = make_geom(L, W, C, codes_prefetch(f64, C), codes_window(f64, C));
     if (cg->g.P < 1) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
-    cg->g.t0 = 0;        // the code words cover every super-step from the first
+    // the code words cover every super-step from the first, in whole words
+    cg->g.t0 = 0;
+    cg->g.T = (int)ceil_div(cg->g.L + (cg->g.Wp + 2) / 2, cg->g.M) * cg->g.M;
+    cg->g.LEN = cg->g.T + cg->g.Wp + 2 * C + cg->g.D + 2;
     cg->padl = padded_row_margin_left(Wp);
     cg->ppitch = ((int64_t)cg->padl + L + padded_row_margin_right(Wp) + 63) / 64 * 64;
     const int64_t boff = cg->padl + cg->g.base0 - C;
