@@ -322,6 +322,72 @@ def window_sweep(nd, synth, torch, dev, reps=3):
     return {"workload": "nndtw-mix512", "N": N, "Q": Q, "L": wl.L, "rows": rows}
 
 
+def small_latency(nd, synth, torch, dev, calls=1000):
+    """The smallest instance (100 random-walk references x 20 queries, L=64,
+    W=6, V=1): per-call latency of the search over `calls` calls (HIP events
+    around each call; reference set built once), p50 and p99."""
+    wl = synth.workload("nndtw-small")
+    refs = torch.from_numpy(wl.refs).to(dev)
+    qs = torch.from_numpy(wl.queries).to(dev)
+    rs = nd.RefSet(refs, wl.windows[0])
+    sr = nd.Searcher(rs, qs.shape[0], V=wl.vs[0], cascade="keogh_enh")
+    for _ in range(10):
+        sr(qs)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record()
+        sr(qs)
+        e1.record()
+    torch.cuda.synchronize()
+    lat = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    return {"workload": "nndtw-small", "N": wl.refs.shape[0], "Q": wl.queries.shape[0], "L": wl.L,
+            "W": wl.windows[0], "V": wl.vs[0], "calls": calls, "latency_ms": {
+                "p50": lat[calls // 2], "p99": lat[int(math.ceil(0.99 * calls)) - 1], "max": lat[-1]},
+            "queries_per_s_at_p50": wl.queries.shape[0] / (lat[calls // 2] / 1e3)}
+
+
+def arms_2x2(nd, torch, rs, qs, V, nq_per_query=100, reps=3):
+    """{per-query, batched} x {LB_Keogh, LB_Keogh -> LB_Enhanced^V} on the
+    benchmarked set, search only (reference set built): batched = all queries
+    in one call; per-query = one query per call (timed over nq_per_query calls)."""
+    out = {}
+    for cas in ("keogh", "keogh_enh"):
+        sr = nd.Searcher(rs, qs.shape[0], V=V, cascade=cas)
+        sr(qs)
+        t, _ = _median_ms(torch, lambda: sr(qs), reps)
+        one = nd.Searcher(rs, 1, V=V, cascade=cas)
+        one(qs[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(nq_per_query):
+            one(qs[i:i + 1])
+        torch.cuda.synchronize()
+        per = nq_per_query / (time.perf_counter() - t0)
+        out[cas] = {"batched_queries_per_s": qs.shape[0] / (t / 1e3), "per_query_queries_per_s": per}
+    out["factor_batching"] = {c: out[c]["batched_queries_per_s"] / out[c]["per_query_queries_per_s"]
+                              for c in ("keogh", "keogh_enh")}
+    out["factor_enhanced"] = {m: out["keogh_enh"][m] / out["keogh"][m]
+                              for m in ("batched_queries_per_s", "per_query_queries_per_s")}
+    return out
+
+
+def per_v(nd, torch, rs, qs, reps=3):
+    """The benchmarked set at V = 1, 2, 5 (search only): queries/s and pruning per stage."""
+    out = {}
+    N, Q = rs.n, qs.shape[0]
+    for V in (1, 2, 5):
+        sr = nd.Searcher(rs, Q, V=V, cascade="keogh_enh")
+        sr(qs)
+        t, (_, _, c) = _median_ms(torch, lambda: sr(qs), reps)
+        c = c.cpu().numpy()
+        out[str(V)] = {"search_ms": t, "queries_per_s": Q / (t / 1e3),
+                       "pruning_rate": 1.0 - int(c[:, 4].sum()) / (N * Q),
+                       "pruned": {"keogh": int(c[:, 1].sum()) / (N * Q), "enh_bands": int(c[:, 2].sum()) / (N * Q),
+                                  "enh": int(c[:, 3].sum()) / (N * Q)}}
+    return out
+
+
 COMPARE_CASCADES = (("kim", "kim"), ("keogh", "keogh"), ("improved", "improved"), ("new", "new"),
                     ("enhanced5", "enh"), ("keogh_enhanced5", "keogh_enh"), ("enhanced5_sym", "enh_sym"))
 
@@ -543,6 +609,10 @@ def main():
         for v in (1, 2, 5):
             tight[f"enhanced{v}"] = float((nd.lb_enhanced(A, B, U, Lo, W, v, zip_=True)[keep] / d[keep]).mean())
         res["tightness"] = tight
+        res["arms_2x2"] = arms_2x2(nd, torch, rs, qs, V)
+        res["per_v"] = per_v(nd, torch, rs, qs)
+        res["small_latency"] = small_latency(nd, synth, torch, dev)
+        log("arms, V and small-instance latency done")
         res["window_sweep"] = window_sweep(nd, synth, torch, dev)
         log("window sweep done")
         res["compare_bounds"] = compare_bounds(nd, synth, torch, dev, a, b, W)
