@@ -535,14 +535,20 @@ def main():
     step_ev = [hip.events(2) for _ in range(K)]
     stage_ev = [hip.events(5) for _ in range(K)]
     torch.cuda.synchronize()
+    # timed steps: one event pair per step (latency) and nothing in between
     t0 = time.perf_counter()
     for k in range(K):
-        idx, dist, counts = step(step_ev[k], stage_ev[k])
+        idx, dist, counts = step(step_ev[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"timed {K} steps")
     ms_step = (t1 - t0) * 1e3 / K
     lat = sorted(hip.ms(e[0], e[1]) for e in step_ev)
+    # per-stage times (and the search kernel's duration for the roofline) from
+    # as many untimed steps with events between the stages
+    for k in range(K):
+        step(None, stage_ev[k])
+    torch.cuda.synchronize()
     st = {name: [hip.ms(e[i], e[i + 1]) for e in stage_ev] for i, name in
           enumerate(["bounds", "cells_prefix", "order", "search"])}
     st_avg = {k: sum(v) / len(v) for k, v in st.items()}

@@ -263,9 +263,10 @@ typedef struct nndtw_search_opts {
     int32_t init_ub;  /* 1: bound the first round by the first candidate's ED^2      */
     int32_t cpl;      /* engine shape (diagonal pairs per lane); 0 = default; out    */
     void *const *events; /* optional hipEvent_t[5] (caller-created), recorded on the
-                          * stream before the bound pass, after it, after the
-                          * cells table, after the ordering and after the search
-                          * kernel; NULL records nothing                              */
+                          * stream before the bound pass, after it (twice: the
+                          * cells table is filled by the ordering kernel), after
+                          * the ordering and after the search kernel; NULL
+                          * records nothing                                           */
     int32_t waves;    /* waves per query (1..NNDTW_SEARCH_MAX_WAVES); 0 = default; out */
     int32_t reserved32;
     int64_t reserved[2];

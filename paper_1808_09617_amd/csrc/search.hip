@@ -1,12 +1,14 @@
 // Nearest-neighbour lower-bound search (Sections 1 and 4) on one GPU.
 //
-// Enqueued as four kernels on the caller's stream:
+// Enqueued as three kernels on the caller's stream (four with a comparison
+// cascade, whose bound pass follows the fused one):
 //   1. cascade bounds   squared ED, LB_Keogh, LB_Enhanced bands part and full
 //                       bound for every (query, reference)       (bounds.hip)
-//   2. cells prefix     number of window cells on anti-diagonals 0..s
-//   3. order            per query, references sorted by (squared ED, index)
-//                       in LDS, with the bounds gathered in that order
-//   4. search           one wave per query: rounds of R candidates in visiting
+//   2. order            per query, references sorted by (squared ED, index)
+//                       in LDS, with the bounds gathered in that order; the
+//                       first workgroup also fills the cells table (window
+//                       cells on anti-diagonals 0..s, for the cell counts)
+//   3. search           one workgroup per query: rounds of R candidates in visiting
 //                       order are tested against the round's threshold; the
 //                       survivors run through the DTW engine (FP32, abandoned
 //                       above the threshold), groups of the wave computing
@@ -196,14 +198,43 @@ __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *
     }
 }
 
+// The cells table of the search (prefix[s] = window cells on anti-diagonals
+// 0..s) by one wave: each lane counts a contiguous chunk of anti-diagonals,
+// then the chunk totals are scanned across the wave.
+__device__ void cells_prefix_wave(int L, int Wp, uint32_t *__restrict__ prefix, int lane)
+{
+    const int S = 2 * L - 1;
+    const int per = (S + WAVE - 1) / WAVE;
+    const int s0 = lane * per;
+    auto count = [&](int s) {
+        const int km = min(Wp, min(s, 2 * L - 2 - s));
+        return (uint32_t)(km + 1 - ((km + s) & 1));
+    };
+    uint32_t tot = 0;
+    for (int x = 0; x < per && s0 + x < S; ++x) tot += count(s0 + x);
+    uint32_t inc = tot;
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)inc, off);
+        if (lane >= off) inc += v;
+    }
+    uint32_t acc = inc - tot;
+    for (int x = 0; x < per && s0 + x < S; ++x) {
+        acc += count(s0 + x);
+        prefix[s0 + x] = acc;
+    }
+}
+
 template <int E, int NT>
 __global__ void __launch_bounds__(NT)
 order_kernel(int64_t n, const double *__restrict__ ed2, const double *__restrict__ lbk,
              const double *__restrict__ lbeb, const double *__restrict__ lbe, uint32_t *__restrict__ sk,
-             double *__restrict__ slbk, double *__restrict__ slbeb, double *__restrict__ slbe)
+             double *__restrict__ slbk, double *__restrict__ slbeb, double *__restrict__ slbe, int L, int Wp,
+             uint32_t *__restrict__ prefix)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     order_query<E, NT>(n, blockIdx.x, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, smem);
+    // the first workgroup's first wave also fills the search's cells table
+    if (blockIdx.x == 0 && threadIdx.x < WAVE) cells_prefix_wave(L, Wp, prefix, threadIdx.x);
 }
 
 // The ordering of a batch: one workgroup per (set, query) item of the sets
@@ -259,7 +290,8 @@ int launch_cells_prefix(int L, int Wp, uint32_t *prefix, hipStream_t st)
 }
 
 static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *lbk, const double *lbeb,
-                        const double *lbe, uint32_t *sk, double *slbk, double *slbeb, double *slbe, hipStream_t st)
+                        const double *lbe, uint32_t *sk, double *slbk, double *slbeb, double *slbe, int L, int Wp,
+                        uint32_t *prefix, hipStream_t st)
 {
     const int Wd = order_width(n);
     const size_t lds = (size_t)ORDER_THREADS * Wd * 12;
@@ -267,7 +299,7 @@ static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *
 #define NNDTW_ORDER_CASE(WW, EE, NT)                                                                     \
     case WW:                                                                                             \
         hipLaunchKernelGGL((order_kernel<EE, NT>), dim3((unsigned)nQ), dim3(NT), lds, st, n, ed2, lbk, lbeb, \
-                           lbe, sk, slbk, slbeb, slbe);                                                  \
+                           lbe, sk, slbk, slbeb, slbe, L, Wp, prefix);                                   \
         break;
         NNDTW_FOR_EACH_SORT(NNDTW_ORDER_CASE)
 #undef NNDTW_ORDER_CASE
@@ -678,9 +710,9 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     }
     if (r) return r;
     if ((r = mark(1))) return r;
-    if ((r = launch_cells_prefix(L, plan.Wp, prefix, st))) return r;
+    // (the cells table is filled by the ordering kernel: events 1 and 2 mark the same point)
     if ((r = mark(2))) return r;
-    if ((r = launch_order(n, nQ, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, st))) return r;
+    if ((r = launch_order(n, nQ, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, L, plan.Wp, prefix, st))) return r;
     if ((r = mark(3))) return r;
 
     SearchArgs a;

@@ -295,6 +295,21 @@ def test_search_long_series_and_widest_windows(L, W):
         check_search(refs, queries, W, V, "keogh_enh", 0, True, 0, brute=False)
 
 
+@pytest.mark.parametrize("L,W", [(64, 6), (256, 26), (300, 299), (512, 128)])
+def test_search_cell_counts_of_complete_dtws(L, W):
+    """References identical to the query: every distance is 0, the threshold
+    is 0 and no DTW is abandoned (the test is strict), so the cells the search
+    reports (the units of the roofline figure) are N times the window's cell
+    count L(2W'+1) - W'(W'+1)."""
+    q = series(1, L, seed=L + W)
+    refs = np.repeat(q, 37, 0)
+    gi, gd, gc, _ = run_search(refs, q, W, 2)
+    Wp = min(W, L - 1)
+    assert gi[0] == 0 and gd[0] == 0.0
+    assert gc[0, 4] == 37 and gc[0, 5] == 0
+    assert gc[0, 6] == 37 * (L * (2 * Wp + 1) - Wp * (Wp + 1))
+
+
 def test_search_full_sin256_properties():
     """Full-size workload in the benchmarked launch shape: every query's
     result is checked on a sample against the oracle and on all queries
