@@ -59,12 +59,19 @@ class Hip:
 
 
 def source_fingerprint():
+    """Hash of the HIP sources' code (comments and blank space removed), so
+    that only a change of the kernels themselves invalidates the stored
+    counters."""
     import glob
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1808_09617_amd", "csrc", "*"))):
+        text = open(f, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
         h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 
@@ -76,7 +83,7 @@ def profiled_traffic(kernel, workload):
         return None
     fp, val = None, None
     for line in open(path):
-        if line.startswith("# source fingerprint:"):
+        if line.startswith("# source fingerprint"):
             fp = line.split(":", 1)[1].strip()
         if line.startswith("# bytes_per_launch ") and line.split()[2] == kernel:
             val = int(line.split()[3])

@@ -36,9 +36,11 @@
 // Series values: the a-value of a bottom cell of pair m equals the a-value of
 // the top cell of pair m-1 and the b-value is shared by both cells of a pair,
 // so a lane keeps windows of C+1 consecutive a and b values that slide by one
-// element per super-step.  The windows live in registers whose roles rotate
-// with period C+1 (the loop is unrolled by C+1 super-steps), so each
-// super-step costs two LDS reads and no register moves.
+// element per super-step.  The windows live in M >= C + D registers whose
+// roles rotate with period M (the loop is unrolled by M super-steps, a
+// "block"), and the values super-step t+D needs are read at the end of
+// super-step t (from LDS or from global memory), so each super-step costs
+// two reads and no register moves.
 //
 // Early abandon: every warping path crosses every pair of consecutive
 // anti-diagonals and costs only grow along a path, so once all cells of
@@ -104,10 +106,6 @@ template <> __device__ __forceinline__ double inf_of<double>() { return __builti
 
 // Padding left of the first series element inside a staged LDS row (elements).
 template <int C> struct Stage { static constexpr int PADL = C; };
-
-// Window registers of a lane: C+1 values are in use at a super-step and the
-// reads for super-step t+D are issued at the end of super-step t, so the
-// windows hold M = C + D values and rotate with period M.
 
 // Stage series `src` (float[L], global) into LDS row `dst` of geo.LEN
 // elements with PAD outside [0, L).  Whole-wave cooperative.
@@ -195,10 +193,11 @@ __device__ __forceinline__ unsigned argmin_code(double dg, double up, double lf)
 // abandoned once its frontier exceeds thr_of(i).  A group takes the next
 // task as soon as its current one ends (completed or abandoned), at the next
 // block boundary (every M super-steps), so abandoned candidates free their
-// lanes early.  Every task starts at super-step 0 of its own sweep; block
-// boundaries are multiples of M in every group, which keeps the register
-// rotation of the windows the same in all groups.  Whole-wave call with
-// uniform arguments; ntasks >= 1.
+// lanes early.  Every task starts at super-step geo.t0 of its own sweep and
+// runs whole blocks from there, so block boundaries fall on the same
+// super-steps modulo M in every group, which keeps the register rotation of
+// the windows the same in all groups.  Whole-wave call with uniform
+// arguments; ntasks >= 1.
 template <typename T, int C, int D, int M, bool EXACT, typename ARow, typename BRow, typename Thr,
           typename Codes = NoCodes>
 __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, int *next_task, ARow arow, BRow brow,
