@@ -58,36 +58,44 @@ class Hip:
         return float(f.value)
 
 
-def source_fingerprint():
-    """Hash of the HIP sources' code (comments and blank space removed), so
-    that only a change of the kernels themselves invalidates the stored
-    counters."""
-    import glob
+def device_code_fingerprint():
+    """SHA-256 of the device code of the built library (its .hip_fatbin
+    section, read from the ELF section table): it changes exactly when a
+    kernel's code changes, not with comments or host code."""
     import hashlib
-    import re
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1808_09617_amd", "csrc", "*"))):
-        text = open(f, encoding="utf-8").read()
-        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-        text = re.sub(r"//[^\n]*", " ", text)
-        h.update(os.path.basename(f).encode())
-        h.update(" ".join(text.split()).encode())
-    return h.hexdigest()
+    import struct
+    path = os.path.join(ROOT, "paper_1808_09617_amd", "libnndtw.so")
+    if not os.path.exists(path):
+        return None
+    data = open(path, "rb").read()
+    shoff = struct.unpack_from("<Q", data, 0x28)[0]
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", data, 0x3A)
+
+    def section(i):
+        return struct.unpack_from("<IIQQQQIIQQ", data, shoff + i * shentsize)
+
+    names = section(shstrndx)[4]
+    for i in range(shnum):
+        name_off, _, _, _, off, size = section(i)[:6]
+        end = data.index(b"\0", names + name_off)
+        if data[names + name_off:end] == b".hip_fatbin":
+            return hashlib.sha256(data[off:off + size]).hexdigest()
+    return None
 
 
 def profiled_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
-    summary, or None if the HIP sources changed since those counters were taken."""
+    summary, or None if the kernels changed since those counters were taken."""
     path = os.path.join(ROOT, "profiles", f"memory_counters_{workload}.txt")
     if not os.path.exists(path):
         return None
     fp, val = None, None
     for line in open(path):
-        if line.startswith("# source fingerprint"):
+        if line.startswith("# device code fingerprint"):
             fp = line.split(":", 1)[1].strip()
         if line.startswith("# bytes_per_launch ") and line.split()[2] == kernel:
             val = int(line.split()[3])
-    return val if fp == source_fingerprint() else None
+    return val if fp is not None and fp == device_code_fingerprint() else None
 
 
 def cpu_baseline(wl, W, V, target_s):

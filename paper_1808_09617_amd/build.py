@@ -45,8 +45,11 @@ EXTRA = {"bounds.hip": ["-fno-honor-nans"], "compare.hip": ["-fno-honor-nans"]}
 
 def _compile(src: str):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), "-Rpass-analysis=kernel-resource-usage", "-c",
-           src, "-o", obj]
+    # a compilation-unit ID of the file's name (not of its path), so that the
+    # device code does not depend on where the tree is built
+    cuid = "nndtw_" + os.path.splitext(os.path.basename(src))[0]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), f"-cuid={cuid}",
+           "-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")

@@ -107,18 +107,6 @@ template <> __device__ __forceinline__ double inf_of<double>() { return __builti
 // Padding left of the first series element inside a staged LDS row (elements).
 template <int C> struct Stage { static constexpr int PADL = C; };
 
-// Stage series `src` (float[L], global) into LDS row `dst` of geo.LEN
-// elements with PAD outside [0, L).  Whole-wave cooperative.
-template <typename T, int C>
-__device__ __forceinline__ void stage_row(T *dst, const float *__restrict__ src, const EngineGeom &geo, int lane)
-{
-    const int first = geo.base0 - Stage<C>::PADL;
-    for (int e = lane; e < geo.LEN; e += WAVE) {
-        int idx = first + e;
-        dst[e] = (idx >= 0 && idx < geo.L) ? (T)src[idx] : Pad<T>::big();
-    }
-}
-
 // Stage `nrows` series (row r is src + krow(r) * L) into consecutive LDS rows
 // of geo.LEN elements.  Flattened over all rows, each thread keeps U global
 // loads in flight before its LDS stores.  Cooperative over `nthreads`
