@@ -284,11 +284,10 @@ int nndtw_refset_build(const float *B, int64_t n, int32_t L, int32_t W, void *me
     r.Bp = (float *)(m + off[6]);
     r.ppitch = lay.ppitch;
     r.padl = lay.padl;
-    hipError_t e = hipMemcpyAsync(r.B, B, (size_t)n * L * sizeof(float), hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "refset copy");
-    TRY(launch_envelopes(r.B, n, L, W, r.U, r.Lo, st));
+    // one pass over B: envelopes, the row-major copy and the padded rows;
+    // then the point-major copies
+    TRY(launch_envelopes_build(B, n, L, W, r.U, r.Lo, r.B, r.Bp, r.padl, r.ppitch, st));
     TRY(launch_transpose3(r.B, r.U, r.Lo, n, L, pitch, r.Bt, r.Ut, r.Lt, st));
-    TRY(launch_pad_rows(r.B, n, L, r.padl, r.ppitch, r.Bp, st));
     r.magic = NNDTW_REFSET_MAGIC;
     *out = r;
     return NNDTW_OK;

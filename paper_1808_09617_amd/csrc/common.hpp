@@ -37,6 +37,10 @@ inline int padded_row_margin_right(int Wp) { return Wp / 2 + 40; }
 
 // envelopes.hip
 int launch_envelopes(const float *B, int64_t n, int L, int W, float *U, float *Lo, hipStream_t s);
+// The envelopes plus, from the same read of B, its row-major copy Bc and its
+// padded rows Bp (a reference-set build).
+int launch_envelopes_build(const float *B, int64_t n, int L, int W, float *U, float *Lo, float *Bc, float *Bp,
+                           int padl, int64_t ppitch, hipStream_t s);
 int launch_transpose3(const float *B, const float *U, const float *Lo, int64_t n, int L,
                       int64_t pitch, float *Bt, float *Ut, float *Lt, hipStream_t s);
 int launch_pad_rows(const float *B, int64_t n, int L, int padl, int64_t ppitch, float *Bp, hipStream_t s);

@@ -27,9 +27,19 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Optional outputs of a reference-set build, written from the row this
+// kernel reads anyway: the row itself (Bc, row-major) and the row inside its
+// padding (Bp: ppitch elements, the series at padl, 1e30 around it).
+struct RowCopies {
+    float *Bc = nullptr;
+    float *Bp = nullptr;
+    int padl = 0;
+    int64_t ppitch = 0;
+};
+
 __global__ void __launch_bounds__(WAVE *ENV_WAVES)
 envelopes_kernel(const float *__restrict__ B, int64_t n, int L, int Wp, int p,
-                 float *__restrict__ U, float *__restrict__ Lo)
+                 float *__restrict__ U, float *__restrict__ Lo, RowCopies rc)
 {
     extern __shared__ float lds[];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -38,7 +48,19 @@ envelopes_kernel(const float *__restrict__ B, int64_t n, int L, int Wp, int p,
     float *mx = lds + (size_t)w * 2 * L;
     float *mn = mx + L;
     const float *b = B + s * (int64_t)L;
-    for (int i = lane; i < L; i += WAVE) { float v = b[i]; mx[i] = v; mn[i] = v; }
+    for (int i = lane; i < L; i += WAVE) {
+        const float v = b[i];
+        mx[i] = v;
+        mn[i] = v;
+        if (rc.Bc) rc.Bc[s * (int64_t)L + i] = v;
+    }
+    if (rc.Bp) {
+        float *row = rc.Bp + s * rc.ppitch;
+        for (int64_t e = lane; e < rc.ppitch; e += WAVE) {
+            const int64_t j = e - rc.padl;
+            row[e] = (j >= 0 && j < L) ? b[j] : Pad<float>::big();
+        }
+    }
     wave_lds_sync();
     // mx[i] <- max over [i, min(i + 2h - 1, L - 1)] for h = 1, 2, ... < p
     for (int h = 1; h < p; h <<= 1) {
@@ -81,7 +103,8 @@ envelopes_kernel(const float *__restrict__ B, int64_t n, int L, int Wp, int p,
     }
 }
 
-int launch_envelopes(const float *B, int64_t n, int L, int W, float *U, float *Lo, hipStream_t st)
+static int launch_envelopes_rc(const float *B, int64_t n, int L, int W, float *U, float *Lo, RowCopies rc,
+                               hipStream_t st)
 {
     if (n == 0) return NNDTW_OK;
     const int Wp = W < L - 1 ? W : L - 1;
@@ -90,9 +113,25 @@ int launch_envelopes(const float *B, int64_t n, int L, int W, float *U, float *L
     const size_t lds = (size_t)ENV_WAVES * 2 * L * sizeof(float);
     const int64_t blocks = ceil_div(n, ENV_WAVES);
     hipLaunchKernelGGL(envelopes_kernel, dim3((unsigned)blocks), dim3(WAVE * ENV_WAVES), lds, st,
-                       B, n, L, Wp, p, U, Lo);
+                       B, n, L, Wp, p, U, Lo, rc);
     NNDTW_LAUNCH_CHECK("envelopes kernel launch");
     return NNDTW_OK;
+}
+
+int launch_envelopes(const float *B, int64_t n, int L, int W, float *U, float *Lo, hipStream_t st)
+{
+    return launch_envelopes_rc(B, n, L, W, U, Lo, RowCopies{}, st);
+}
+
+int launch_envelopes_build(const float *B, int64_t n, int L, int W, float *U, float *Lo, float *Bc, float *Bp,
+                           int padl, int64_t ppitch, hipStream_t st)
+{
+    RowCopies rc;
+    rc.Bc = Bc;
+    rc.Bp = Bp;
+    rc.padl = padl;
+    rc.ppitch = ppitch;
+    return launch_envelopes_rc(B, n, L, W, U, Lo, rc, st);
 }
 
 // Point-major copies: Xt[i][k] = X[k][i] for B, U and Lo, via 64x64 LDS tiles.
