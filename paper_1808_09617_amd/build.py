@@ -37,10 +37,14 @@ def sources():
 RESOURCES = os.path.join(BUILD, "kernel_resources.txt")
 
 
-# Per-file flags.  The bound kernels take FP64 minima and maxima of loaded
-# values; inputs are finite (a precondition of the C ABI), so the compiler
-# need not quiet NaNs before each of them (a canonicalising max per term).
-EXTRA = {"bounds.hip": ["-fno-honor-nans"], "compare.hip": ["-fno-honor-nans"]}
+# Per-file flags.  The bound kernels and the DTW engines take minima and
+# maxima of loaded or lane-shifted values; inputs are finite (a precondition
+# of the C ABI) and no operation of these kernels makes a NaN from finite
+# values and infinities (no inf - inf, no 0 * inf), so the compiler need not
+# quiet NaNs before each of them (a canonicalising max per term, and per
+# shifted FP64 value on the engine's dependency chain).
+NO_NANS = ["-fno-honor-nans"]
+EXTRA = {f: NO_NANS for f in ("bounds.hip", "compare.hip", "search.hip", "dtw.hip", "batch.hip", "grad.hip")}
 
 
 def _compile(src: str):

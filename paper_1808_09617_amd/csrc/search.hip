@@ -456,6 +456,11 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                 __syncthreads();
                 if (tid == 0) *next_task = 0;
                 __syncthreads();
+                // every wave of the workgroup waits for these few FP64
+                // sweeps: run them at the top wave priority, so that the
+                // waves of other workgroups sharing the SIMD do not stretch
+                // this query's critical path
+                __builtin_amdgcn_s_setprio(3);
                 if (C > 1 && geoD.C == 1) {
                     // one pair per lane: rows start C - 1 elements later
                     constexpr int D1 = recheck_prefetch(1), M1 = recheck_window(1);
@@ -469,6 +474,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                         [&](int i) { return Bp + (int64_t)rq[b0 + i] * a.ppitch; }, [&](int) { return thr; },
                         TaskOut<double>{resD, trunD});
                 }
+                __builtin_amdgcn_s_setprio(0);
                 __syncthreads();
                 for (int i = 0; i < nd; ++i) {
                     const double d = resD[i];
