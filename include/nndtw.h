@@ -229,11 +229,15 @@ typedef struct nndtw_refset {
     int32_t  reserved1;
 } nndtw_refset;
 
+/* Largest number of series in a reference set (row pitch of the
+ * point-major arrays below 2^29 elements). */
+#define NNDTW_REFSET_MAX_N ((int64_t)(1 << 29) - 64)
 /* Device bytes needed for a reference set of n series of length L built
- * for window W. */
+ * for window W.  1 <= n <= NNDTW_REFSET_MAX_N, else EINVAL. */
 int nndtw_refset_bytes(int64_t n, int32_t L, int32_t W, size_t *bytes);
 /* Copy B (device float[n][L]) into mem and build its envelopes and
- * point-major copies for window W.  n >= 1.  EINVAL if bytes is too small. */
+ * point-major copies for window W.  1 <= n <= NNDTW_REFSET_MAX_N.  EINVAL
+ * if bytes is too small. */
 int nndtw_refset_build(const float *B, int64_t n, int32_t L, int32_t W, void *mem,
                        size_t bytes, nndtw_refset *out, void *stream);
 

@@ -248,6 +248,8 @@ int nndtw_refset_bytes(int64_t n, int32_t L, int32_t W, size_t *bytes)
     g_err[0] = 0;
     TRY(check_len_w(L, W));
     REQUIRE(n >= 1, "n=%lld: a reference set needs at least one series", (long long)n);
+    REQUIRE(n <= NNDTW_REFSET_MAX_N, "n=%lld: more than %lld series in a reference set", (long long)n,
+            (long long)NNDTW_REFSET_MAX_N);
     REQUIRE(bytes != nullptr, "bytes is NULL");
     *bytes = refset_layout(n, L, W).total;
     return NNDTW_OK;
@@ -259,6 +261,8 @@ int nndtw_refset_build(const float *B, int64_t n, int32_t L, int32_t W, void *me
     g_err[0] = 0;
     TRY(check_len_w(L, W));
     REQUIRE(n >= 1, "n=%lld: a reference set needs at least one series", (long long)n);
+    REQUIRE(n <= NNDTW_REFSET_MAX_N, "n=%lld: more than %lld series in a reference set", (long long)n,
+            (long long)NNDTW_REFSET_MAX_N);
     TRY(check_ptr(B, 4, "B", true));
     TRY(check_ptr(mem, 256, "mem", true));
     REQUIRE(out != nullptr, "out is NULL");

@@ -100,6 +100,8 @@ int launch_pair_bounds(int what, const float *A, int64_t nA, const float *B, con
 
 // ------------------------------------------------------------------ fused
 constexpr int CB_THREADS = 256;
+// Word 3 of a raw buffer resource on CDNA: 32-bit data format, no swizzle.
+constexpr int BUF_DWORD3 = 0x00020000;
 constexpr int CB_CHUNK = 128;   // points of the query tile staged per pass
 
 // One tile: references rt*CB_THREADS .. +CB_THREADS-1 (one per thread)
@@ -117,6 +119,7 @@ __device__ __forceinline__ void bounds_tile(int64_t rt, int64_t qt, const float 
     const int64_t q0 = qt * TQ;
     const bool live = k < n;
     const int64_t kk = live ? k : 0;
+    const uint32_t kbytes = (uint32_t)kk * 4u;   // k < pitch < 2^29
     const int nq = (int)((nQ - q0) < TQ ? (nQ - q0) : TQ);
 
     double e[TQ], kg[TQ], en[TQ];
@@ -163,13 +166,23 @@ __device__ __forceinline__ void bounds_tile(int64_t rt, int64_t qt, const float 
         // The reference values of point x + PF are loaded while point x is
         // processed (a ring of PF registers per array); loads past the chunk
         // re-read its last point, so every address stays in bounds.
+        // Each point's row is read through a buffer resource built from the
+        // wave-uniform row address (scalar work) and the lane's 32-bit byte
+        // offset, so no per-load vector address arithmetic is needed.  The
+        // resource covers the row (pitch floats); every offset is inside it.
         constexpr int PF = 8;
         float rb[PF], ru[PF], rl[PF];
+        const int row_bytes = (int)(pitch * 4);
+        auto at = [&](const float *rowp) {
+            const __amdgpu_buffer_rsrc_t r =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(rowp), 0, row_bytes, BUF_DWORD3);
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)kbytes, 0, 0));
+        };
         auto fetch = [&](int x, int r) {
-            const int64_t o = (int64_t)(c0 + (x < cn ? x : cn - 1)) * pitch + kk;
-            rb[r] = Bt[o];
-            ru[r] = Ut[o];
-            rl[r] = Lt[o];
+            const int64_t row = (int64_t)(c0 + (x < cn ? x : cn - 1)) * pitch;
+            rb[r] = at(Bt + row);
+            ru[r] = at(Ut + row);
+            rl[r] = at(Lt + row);
         };
         const int cfull = cn - cn % PF;
 #pragma unroll

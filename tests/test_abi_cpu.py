@@ -118,6 +118,10 @@ def test_refset_and_search_validation():
     assert lib.nndtw_refset_bytes(100, 64, 6, ctypes.byref(nbytes)) == 0
     assert nbytes.value >= 7 * 100 * 64 * 4
     assert _err(lib.nndtw_refset_bytes(0, 64, 6, ctypes.byref(nbytes)), "at least one series") == nd.EINVAL
+    max_n = (1 << 29) - 64                       # NNDTW_REFSET_MAX_N
+    assert lib.nndtw_refset_bytes(max_n, 2, 1, ctypes.byref(nbytes)) == 0
+    assert _err(lib.nndtw_refset_bytes(max_n + 1, 2, 1, ctypes.byref(nbytes)), "series in a reference set") \
+        == nd.EINVAL
     desc = nd._Refset()
     assert lib.nndtw_refset_bytes(100, 64, 3, ctypes.byref(nbytes)) == 0
     assert _err(lib.nndtw_refset_build(FAKE, 100, 64, 3, FAKE, nbytes.value - 1, ctypes.byref(desc), NULL),
