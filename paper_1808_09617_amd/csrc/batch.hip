@@ -124,6 +124,7 @@ int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, 
         a.nn_idx = sets[d].nn_idx;
         a.nn_dist = sets[d].nn_dist;
         a.counts = sets[d].counts;
+        a.ncu = device_cu_count();
         b.C = sp.C;
         b.exact = sp.exact;
         b.Bt = rs->Bt;

@@ -91,6 +91,8 @@ int launch_batch_order(int E, const BatchSet *sets, const int64_t *items, int64_
 int launch_batch_search(int C, bool exact, const BatchSet *sets, const int64_t *items, int64_t nitems,
                         unsigned *counter, int waves, int grid, size_t lds, hipStream_t s);
 size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD);
+// Compute units of the current device (0 if it cannot be queried).
+int device_cu_count();
 // batch.hip
 size_t batch_ws_bytes(const nndtw_batch_set *sets, int nsets);
 int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, void *ws, size_t ws_bytes,
@@ -157,6 +159,8 @@ struct SearchArgs {
     int64_t *nn_idx;
     double *nn_dist;
     int64_t *counts;
+    int ncu;           // compute units of the device (> 0: rotate the FP32
+                       // engine's wave priority, see TaskOut)
 };
 
 // One reference set of a batched search: the search arguments plus what the

@@ -383,6 +383,10 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     const float *Bp = a.Bp + (a.padl + geo.base0 - Stage<C>::PADL);
     const double INF = __builtin_inf();
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    // Workgroups dispatched one after another land on successive compute
+    // units, so those sharing a unit are ncu apart: phases from blockIdx / ncu
+    // differ among them.
+    const int rot_phase = a.ncu > 0 ? (int)((blockIdx.x / (unsigned)a.ncu) & 3u) : -1;
 
     {
         EngineGeom ga = geo;
@@ -422,7 +426,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
             engine_run<float, C, DG, MG, EXACT>(
                 geo, nt, next_task, [&](int) { return (const float *)aF; },
                 [&](int i) { return Bp + (int64_t)ring[(h0 + i) % QCAP] * a.ppitch; }, [&](int) { return thrF; },
-                TaskOut<float>{resF, trunF, run_thr, 1.0 + 2.0 * a.eps});
+                TaskOut<float>{resF, trunF, run_thr, 1.0 + 2.0 * a.eps, rot_phase});
             __syncthreads();
             float d32 = __builtin_inff();
             uint32_t kg = 0;
@@ -621,6 +625,19 @@ int launch_batch_search(int C, bool exact, const BatchSet *sets, const int64_t *
     return NNDTW_OK;
 }
 
+int device_cu_count()
+{
+    static int cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cached[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) return 0;
+        cached[dev] = v;
+    }
+    return cached[dev];
+}
+
 size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD)
 {
     const int LENA = staged_len(g, gd);
@@ -745,6 +762,7 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     a.nn_idx = nn_idx;
     a.nn_dist = nn_dist;
     a.counts = counts;
+    a.ncu = device_cu_count();
     const size_t lds = plan.lds_bytes;
     switch (plan.C) {
 #define X(c)                                                                                       \
