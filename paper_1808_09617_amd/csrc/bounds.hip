@@ -112,7 +112,7 @@ __device__ __forceinline__ void bounds_tile(int64_t rt, int64_t qt, const float 
                                             int64_t pitch, int64_t n, const float *__restrict__ Q, int64_t nQ,
                                             int L, int W, int nb, double *__restrict__ ed2,
                                             double *__restrict__ lbk, double *__restrict__ lbeb,
-                                            double *__restrict__ lbe)
+                                            double *__restrict__ lbe, int rot_phase)
 {
     __shared__ double qa[CB_CHUNK][TQ];
     const int64_t k = rt * CB_THREADS + threadIdx.x;
@@ -188,6 +188,7 @@ __device__ __forceinline__ void bounds_tile(int64_t rt, int64_t qt, const float 
 #pragma unroll
         for (int r = 0; r < PF; ++r) fetch(r, r);
         for (int x0 = 0; x0 < cfull; x0 += PF) {
+            if (rot_phase >= 0) rotate_priority(rot_phase);
 #pragma unroll
             for (int r = 0; r < PF; ++r) {
                 const double b = (double)rb[r], u = (double)ru[r], lo = (double)rl[r];
@@ -219,9 +220,10 @@ cascade_bounds_kernel(const float *__restrict__ Bt, const float *__restrict__ Ut
                       const float *__restrict__ Lt, int64_t pitch, int64_t n,
                       const float *__restrict__ Q, int64_t nQ, int L, int W, int nb,
                       double *__restrict__ ed2, double *__restrict__ lbk,
-                      double *__restrict__ lbeb, double *__restrict__ lbe)
+                      double *__restrict__ lbeb, double *__restrict__ lbe, int ncu)
 {
-    bounds_tile<TQ>(blockIdx.x, blockIdx.y, Bt, Ut, Lt, pitch, n, Q, nQ, L, W, nb, ed2, lbk, lbeb, lbe);
+    bounds_tile<TQ>(blockIdx.x, blockIdx.y, Bt, Ut, Lt, pitch, n, Q, nQ, L, W, nb, ed2, lbk, lbeb, lbe,
+                    rotation_phase(ncu));
 }
 
 // The bound pass of a batch: one workgroup per tile of any set; the set is
@@ -243,7 +245,7 @@ batch_bounds_kernel(const BatchSet *__restrict__ sets, int nsets, const int64_t 
     const BatchSet &b = sets[d];
     const int64_t local = tile - tile_start[d];
     bounds_tile<TQ>(local % b.nrt, local / b.nrt, b.Bt, b.Ut, b.Lt, b.pitch, b.a.n, b.a.Q, b.nQ, b.L, b.W,
-                    b.nb, b.ed2w, b.lbk, b.lbeb, b.lbe);
+                    b.nb, b.ed2w, b.lbk, b.lbeb, b.lbe, rotation_phase(b.a.ncu));
 }
 
 constexpr int BATCH_TQ = 4;
@@ -267,7 +269,7 @@ int launch_cascade_bounds(const nndtw_refset *rs, const float *Q, int64_t nQ, in
     const int nb = V < L / 2 ? V : L / 2;
     dim3 grid((unsigned)ceil_div(rs->n, CB_THREADS), (unsigned)ceil_div(nQ, TQ));
     hipLaunchKernelGGL(cascade_bounds_kernel<TQ>, grid, dim3(CB_THREADS), 0, st, rs->Bt, rs->Ut, rs->Lt,
-                       rs->pitch, rs->n, Q, nQ, L, rs->W, nb, ed2, lbk, lbeb, lbe);
+                       rs->pitch, rs->n, Q, nQ, L, rs->W, nb, ed2, lbk, lbeb, lbe, device_cu_count());
     NNDTW_LAUNCH_CHECK("cascade bounds kernel launch");
     return NNDTW_OK;
 }

@@ -24,6 +24,32 @@ template <typename T> struct Pad;
 template <> struct Pad<float> { static __host__ __device__ constexpr float big() { return 1e30f; } };
 template <> struct Pad<double> { static __host__ __device__ constexpr double big() { return 1e200; } };
 
+// Wave-priority rotation for kernels whose workgroups share the SIMDs for
+// their whole run.  The SIMD issues the oldest ready wave first, so of
+// several co-resident workgroups the last dispatched would run mostly in the
+// gaps of the others and end far behind them, alone on an otherwise idle
+// SIMD.  With the rotation each wave's priority cycles through 0..3, one step
+// every 5.12 us of the 100 MHz real-time clock, offset by the workgroup's
+// phase, so co-resident workgroups with different phases take turns at the
+// top.  Workgroups are dispatched to successive compute units, so those that
+// share a unit are ncu apart in dispatch order and rotation_phase gives them
+// different phases; ncu <= 0 turns the rotation off (phase -1).
+__device__ __forceinline__ int rotation_phase(int ncu)
+{
+    if (ncu <= 0) return -1;
+    const unsigned b = blockIdx.z * gridDim.y * gridDim.x + blockIdx.y * gridDim.x + blockIdx.x;
+    return (int)((b / (unsigned)ncu) & 3u);
+}
+
+__device__ __forceinline__ void rotate_priority(int phase)
+{
+    const unsigned pr = ((unsigned)(__builtin_amdgcn_s_memrealtime() >> 9) + (unsigned)phase) & 3u;
+    if (pr == 0) __builtin_amdgcn_s_setprio(0);
+    else if (pr == 1) __builtin_amdgcn_s_setprio(1);
+    else if (pr == 2) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(3);
+}
+
 constexpr int WAVE = 64;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -151,24 +151,10 @@ template <typename T> struct TaskOut {
     // min(its own threshold, that value).
     unsigned *run_thr = nullptr;
     double slack = 1.0;
-    // Optional wave-priority rotation (>= 0: on, the workgroup's phase 0..3).
-    // The SIMD issues the oldest ready wave first, so of several workgroups
-    // sharing the SIMDs the last dispatched would run mostly in the gaps of
-    // the others and end far behind them, alone on an idle SIMD.  With the
-    // rotation each wave's priority cycles through 0..3 every 4 x 5.12 us of
-    // the 100 MHz real-time clock, offset by its phase, so co-resident
-    // workgroups with different phases take turns at the top.
+    // Optional wave-priority rotation (>= 0: on, the workgroup's phase 0..3;
+    // see rotate_priority), checked once per block of M super-steps.
     int rot_phase = -1;
 };
-
-__device__ __forceinline__ void rotate_priority(int phase)
-{
-    const unsigned pr = ((unsigned)(__builtin_amdgcn_s_memrealtime() >> 9) + (unsigned)phase) & 3u;
-    if (pr == 0) __builtin_amdgcn_s_setprio(0);
-    else if (pr == 1) __builtin_amdgcn_s_setprio(1);
-    else if (pr == 2) __builtin_amdgcn_s_setprio(2);
-    else __builtin_amdgcn_s_setprio(3);
-}
 
 // Optional per-cell record of the minimising predecessor (for the argmin
 // warping path): codes(task) is the task's word array [T/8][W'+1]; the

@@ -383,10 +383,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     const float *Bp = a.Bp + (a.padl + geo.base0 - Stage<C>::PADL);
     const double INF = __builtin_inf();
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
-    // Workgroups dispatched one after another land on successive compute
-    // units, so those sharing a unit are ncu apart: phases from blockIdx / ncu
-    // differ among them.
-    const int rot_phase = a.ncu > 0 ? (int)((blockIdx.x / (unsigned)a.ncu) & 3u) : -1;
+    const int rot_phase = rotation_phase(a.ncu);
 
     {
         EngineGeom ga = geo;
