@@ -102,7 +102,10 @@ struct SearchPlan {
     double eps;
     size_t lds_bytes;
 };
-int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan);
+// max_cpl: the largest engine shape the caller has kernels for (0: all of
+// the single-set search; the batched search compiles up to 4 pairs per lane
+// and rejects sets that need more).
+int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan, int max_cpl = 0);
 size_t search_ws_bytes(int64_t nQ, int64_t n, int L);
 int launch_search(const nndtw_refset *rs, const float *Q, int64_t nQ, const nndtw_search_opts *o,
                   const SearchPlan &plan, int64_t *nn_idx, double *nn_dist, int64_t *counts,
@@ -208,7 +211,7 @@ struct BatchHdr {
 };
 
 // Choose the diagonal-pairs-per-lane C for a window (cmax bounds latency).
-int choose_cpl(int Wp, int cmax, int prefer, int chard = 16);
+int choose_cpl(int Wp, int cmax, int prefer, int chard = 16, bool widen_single = false);
 EngineGeom make_geom(int L, int W, int C, int D, int M);
 // Geometry of the search's FP64 recheck for an FP32 engine of C pairs per lane.
 inline EngineGeom recheck_geom(int L, int W, int C)

@@ -31,14 +31,18 @@ static double cpl_score(int Wp, int C)
     return (double)(P * G) / 64.0 * 3.0 / ops;
 }
 
-int choose_cpl(int Wp, int cmax, int prefer, int chard)
+int choose_cpl(int Wp, int cmax, int prefer, int chard, bool widen_single)
 {
     if (prefer > 0)
         return (cpl_supported(prefer) && prefer <= chard && cpl_score(Wp, prefer) > 0) ? prefer : -1;
     int best = -1;
     double bs = -1.0;
     const int cands[] = {1, 2, 3, 4, 6, 8, 9, 12, 16};
-    for (int pass = 0; pass < 2 && best < 0; ++pass) {
+    // Shapes up to cmax pairs per lane first (fewer registers, more waves
+    // per SIMD); the larger ones if none fits, or, with widen_single, if the
+    // best of them leaves one group per wave (most lanes idle).
+    auto single = [&](int C) { return C > 0 && 63 / (int)ceil_div(Wp + 1, C) < 2; };
+    for (int pass = 0; pass < 2 && (best < 0 || (widen_single && single(best))); ++pass) {
         for (int C : cands) {
             if (C > chard || (pass == 0 && C > cmax)) continue;
             double s = cpl_score(Wp, C);

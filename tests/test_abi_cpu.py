@@ -232,7 +232,16 @@ def test_search_plan_has_a_shape_for_every_window():
             C = opts.cpl
             G = -(-(Wp + 1) // C)
             assert C in (1, 2, 3, 4, 6, 8, 9) and G <= 63, (L, W, C, G)
-            assert opts.R == 2 * (63 // G) * opts.waves >= 1, (L, W, opts.R)
+            # default round: two candidates per group, at least 128
+            assert opts.R == max(2 * (63 // G) * opts.waves, 128), (L, W, opts.R)
+    # where the narrow shapes (<= 4 pairs per lane) leave one group per wave
+    # with lanes idle, a wider shape is taken: W=128 at L=512 (129 diagonal
+    # pairs) runs 4 groups of 15 lanes at 9 pairs per lane, not one group of
+    # 43 lanes at 3
+    d.L, d.W = 512, 128
+    opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
+    assert lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)) == 0 and opts.cpl == 9
+    d.L = 2048
     d.W = 251
     opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 2)              # 126 lanes per group: no fit
     assert _err(lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)), "cpl=2") == nd.EINVAL
