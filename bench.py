@@ -465,8 +465,8 @@ def compare_bounds(nd, synth, torch, dev, a, b, W=26):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--V", type=int, default=5)
     ap.add_argument("--R", type=int, default=0)
     ap.add_argument("--cpl", type=int, default=0)
@@ -550,14 +550,19 @@ def main():
     step_ev = [hip.events(2) for _ in range(K)]
     stage_ev = [hip.events(5) for _ in range(K)]
     torch.cuda.synchronize()
-    # timed steps: one event pair per step (latency) and nothing in between
+    # timed steps: nothing but the steps (an event recorded between kernels
+    # costs the stream time of its own)
     t0 = time.perf_counter()
     for k in range(K):
-        idx, dist, counts = step(step_ev[k])
+        idx, dist, counts = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"timed {K} steps")
     ms_step = (t1 - t0) * 1e3 / K
+    # per-step latency from as many untimed steps, one event pair each
+    for k in range(K):
+        step(step_ev[k])
+    torch.cuda.synchronize()
     lat = sorted(hip.ms(e[0], e[1]) for e in step_ev)
     # per-stage times (and the search kernel's duration for the roofline) from
     # as many untimed steps with events between the stages
