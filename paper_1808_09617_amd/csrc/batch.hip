@@ -85,7 +85,7 @@ int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, 
         od.R = sets[d].R;
         od.cpl = sets[d].cpl;
         SearchPlan sp;
-        if (int r = plan_search(rs, &od, &sp, 4)) return r;
+        if (int r = plan_search(rs, &od, &sp, true)) return r;
         if (sp.C > 4)
             return fail(NNDTW_EUNSUP, "set %d: W=%d at L=%d needs %d pairs per lane; the batch supports up to 4", d,
                         rs->W, rs->L, sp.C);

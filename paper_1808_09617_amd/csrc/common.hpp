@@ -102,10 +102,9 @@ struct SearchPlan {
     double eps;
     size_t lds_bytes;
 };
-// max_cpl: the largest engine shape the caller has kernels for (0: all of
-// the single-set search; the batched search compiles up to 4 pairs per lane
-// and rejects sets that need more).
-int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan, int max_cpl = 0);
+// batched: plan one set of a batched search, whose kernels cover 1-4 pairs
+// per lane only (it rejects sets that need more).
+int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan, bool batched = false);
 size_t search_ws_bytes(int64_t nQ, int64_t n, int L);
 int launch_search(const nndtw_refset *rs, const float *Q, int64_t nQ, const nndtw_search_opts *o,
                   const SearchPlan &plan, int64_t *nn_idx, double *nn_dist, int64_t *counts,

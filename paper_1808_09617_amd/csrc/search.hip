@@ -641,16 +641,15 @@ size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, in
     return (size_t)((LENA + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 8 + QCAP * 4 + 64 * 4 + 16;
 }
 
-int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan, int max_cpl)
+int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan, bool batched)
 {
     const int L = rs->L;
     const int Wp = rs->W < L - 1 ? rs->W : L - 1;
     // Only shapes up to SEARCH_MAX_CPL pairs per lane are compiled for the
     // search: it takes windows with min(W, L-1) + 1 <= 63 * SEARCH_MAX_CPL.
-    // A caller with kernels only up to max_cpl keeps the narrow shapes even
-    // where one group fills a wave (it rejects wider ones itself).
-    const bool widen = max_cpl <= 0 || max_cpl >= SEARCH_MAX_CPL;
-    const int C = choose_cpl(Wp, 4, o->cpl, SEARCH_MAX_CPL, widen);
+    // The batched search keeps the narrow shapes even where one group fills
+    // a wave (it has kernels for 1-4 pairs per lane and rejects wider ones).
+    const int C = choose_cpl(Wp, 4, o->cpl, SEARCH_MAX_CPL, !batched);
     if (C < 0 && o->cpl <= 0)
         return fail(NNDTW_EUNSUP, "window W=%d too wide for the search (min(W, L-1) + 1 <= %d)", rs->W,
                     63 * SEARCH_MAX_CPL);
@@ -665,8 +664,8 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     // Default round: two candidates per group, so that groups whose
     // candidate is abandoned early take another one within the round, and
     // at least 128: each round is a serial step of the query (threshold,
-    // DTWs, FP64 recheck), and below that the chain of rounds costs more
-    // than the extra DTWs a larger round starts.
+    // DTWs, FP64 recheck), and below that the chain of rounds cost more
+    // than the extra DTWs a larger round starts on the measured workloads.
     const int64_t R = o->R > 0 ? o->R : (2 * P * NW > 128 ? 2 * P * NW : 128);
     // Candidates per FP32 batch: the round, up to 64 (one bookkeeping lane
     // each); all FP64 rechecks of a batch in one engine call.  Only the

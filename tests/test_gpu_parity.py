@@ -566,16 +566,18 @@ def test_serving_results_equal_alone():
     say("serving", len(reqs), "requests")
     done, summary = serve.Server(rss, n_streams=3, max_batch=64).run(reqs)
     assert summary["batches"] > 1
+    # the batched search's default round and shape per set (the counts are
+    # defined per round size)
+    plan = nd.BatchSearcher([(rs, dev(series(1, rs.L, seed=1))) for rs in rss], V=5)
     for r in done:
         q = r.query[None]
-        i, d, c, R = nd.search(rss[r.set_id], q, V=5)
+        i, d, c, R = nd.search(rss[r.set_id], q, V=5, R=plan.R[r.set_id], cpl=plan.cpl[r.set_id])
         assert r.result[0] == int(host(i)[0]) and r.result[1] == float(host(d)[0])
         assert r.result[2][:5] == host(c)[0, :5].tolist()
     for r in done[::25]:
         refs, W = sets[r.set_id]
         q = host(r.query)[None]
-        _, _, _, R = nd.search(rss[r.set_id], r.query[None], V=5)
-        oi, od, oc = oracle.search(refs, q, W, 5, "keogh_enh", R, True)
+        oi, od, oc = oracle.search(refs, q, W, 5, "keogh_enh", plan.R[r.set_id], True)
         assert r.result[0] == oi[0] and r.result[1] == od[0] and r.result[2][:5] == oc[0, :5].tolist()
 
 
