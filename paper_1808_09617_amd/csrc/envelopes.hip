@@ -134,17 +134,22 @@ int launch_envelopes_build(const float *B, int64_t n, int L, int W, float *U, fl
     return launch_envelopes_rc(B, n, L, W, U, Lo, rc, st);
 }
 
-// Point-major copies: Xt[i][k] = X[k][i] for B, U and Lo, via 64x64 LDS tiles.
+// Point-major copies: Xt[i][k] = X[k][i] for B, U and Lo, via TT x TT LDS
+// tiles (32 x 32: a set of a thousand series of length 256 is 256 tiles,
+// enough workgroups to spread over the compute units).
+constexpr int TT = 32;
+
 __global__ void __launch_bounds__(256)
 transpose3_kernel(const float *__restrict__ B, const float *__restrict__ U, const float *__restrict__ Lo,
                   int64_t n, int L, int64_t pitch, float *__restrict__ Bt, float *__restrict__ Ut,
                   float *__restrict__ Lt)
 {
-    __shared__ float tile[3][64][65];
-    const int64_t k0 = (int64_t)blockIdx.x * 64;
-    const int i0 = blockIdx.y * 64;
-    const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
-    for (int r = ty; r < 64; r += 4) {
+    __shared__ float tile[3][TT][TT + 1];
+    const int64_t k0 = (int64_t)blockIdx.x * TT;
+    const int i0 = blockIdx.y * TT;
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;     // ty in [0, 256 / TT)
+    constexpr int RS = 256 / TT;
+    for (int r = ty; r < TT; r += RS) {
         int64_t k = k0 + r;
         int i = i0 + tx;
         bool ok = k < n && i < L;
@@ -153,7 +158,7 @@ transpose3_kernel(const float *__restrict__ B, const float *__restrict__ U, cons
         tile[2][r][tx] = ok ? Lo[k * L + i] : 0.f;
     }
     __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
+    for (int r = ty; r < TT; r += RS) {
         int i = i0 + r;
         int64_t k = k0 + tx;
         if (i < L && k < pitch) {
@@ -168,7 +173,7 @@ transpose3_kernel(const float *__restrict__ B, const float *__restrict__ U, cons
 int launch_transpose3(const float *B, const float *U, const float *Lo, int64_t n, int L, int64_t pitch,
                       float *Bt, float *Ut, float *Lt, hipStream_t st)
 {
-    dim3 grid((unsigned)ceil_div(pitch, 64), (unsigned)ceil_div(L, 64));
+    dim3 grid((unsigned)ceil_div(pitch, TT), (unsigned)ceil_div(L, TT));
     hipLaunchKernelGGL(transpose3_kernel, grid, dim3(256), 0, st, B, U, Lo, n, L, pitch, Bt, Ut, Lt);
     NNDTW_LAUNCH_CHECK("transpose kernel launch");
     return NNDTW_OK;
