@@ -42,7 +42,7 @@ namespace nndtw {
 #define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(9)
 constexpr int SEARCH_MAX_CPL = 9;
 
-constexpr int QCAP = 128;        // survivor ring (>= 64 + max staged rows)
+constexpr int QCAP = 256;        // survivor ring (>= the largest batch + one chunk of 64)
 constexpr int SEARCH_MAX_WAVES = NNDTW_SEARCH_MAX_WAVES;
 constexpr int SEARCH_DEFAULT_WAVES = 4;
 constexpr int ORDER_THREADS = 256;
@@ -368,7 +368,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     int *trunD = trunF + SLOTS;
     uint32_t *ring = reinterpret_cast<uint32_t *>(trunD + PD);
     uint32_t *rq = ring + QCAP;      // qualifying candidates of a batch
-    int *next_task = reinterpret_cast<int *>(rq + 64);
+    int *next_task = reinterpret_cast<int *>(rq + SLOTS);
     unsigned *run_thr = reinterpret_cast<unsigned *>(next_task + 1);
 
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -425,30 +425,42 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                 [&](int i) { return Bp + (int64_t)ring[(h0 + i) % QCAP] * a.ppitch; }, [&](int) { return thrF; },
                 TaskOut<float>{resF, trunF, run_thr, 1.0 + 2.0 * a.eps, rot_phase});
             __syncthreads();
-            float d32 = __builtin_inff();
-            uint32_t kg = 0;
-            bool done = false;
-            if (lane < nt) {
-                d32 = resF[lane];
-                kg = ring[(h0 + lane) % QCAP];
-                const int tr = trunF[lane];
-                const bool ab = __builtin_isinf(d32);
-                c_ab += ab;
-                int s_last = s_start + 2 * (tr - 1) + 1;
-                if (s_last > 2 * L - 2) s_last = 2 * L - 2;
-                c_cells += s_last >= 0 ? (int64_t)a.prefix[s_last] : 0;
-                done = !ab && (double)d32 <= thr;
+            // the batch's results, 64 tasks per pass: counts and the
+            // smallest completed FP32 result
+            float mn = __builtin_inff();
+            for (int j0 = 0; j0 < nt; j0 += WAVE) {
+                const int j = j0 + lane;
+                if (j < nt) {
+                    const float d32 = resF[j];
+                    const int tr = trunF[j];
+                    const bool ab = __builtin_isinf(d32);
+                    c_ab += ab;
+                    int s_last = s_start + 2 * (tr - 1) + 1;
+                    if (s_last > 2 * L - 2) s_last = 2 * L - 2;
+                    c_cells += s_last >= 0 ? (int64_t)a.prefix[s_last] : 0;
+                    if (!ab && (double)d32 <= thr) mn = __builtin_fminf(mn, d32);
+                }
             }
-            qh += nt;
-            // smallest completed FP32 result of this batch
-            float mn = done ? d32 : __builtin_inff();
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) mn = __builtin_fminf(mn, __shfl_xor(mn, off));
-            const bool qual = done && (double)d32 <= (double)mn * (1.0 + 2.0 * a.eps);
-            const unsigned long long qm = __ballot(qual);
-            const int nq = __popcll(qm);
+            // the completed results that can decide the round, in batch order
+            int nq = 0;
+            for (int j0 = 0; j0 < nt; j0 += WAVE) {
+                const int j = j0 + lane;
+                bool qual = false;
+                uint32_t kg = 0;
+                if (j < nt) {
+                    const float d32 = resF[j];
+                    qual = !__builtin_isinf(d32) && (double)d32 <= thr &&
+                           (double)d32 <= (double)mn * (1.0 + 2.0 * a.eps);
+                    kg = ring[(h0 + j) % QCAP];
+                }
+                const unsigned long long qm = __ballot(qual);
+                if (w0 && qual) rq[nq + __popcll(qm & lt_mask)] = kg;
+                nq += __popcll(qm);
+            }
+            qh += nt;
             __syncthreads();                 // every wave has read the batch results
-            if (w0 && qual) rq[__popcll(qm & lt_mask)] = kg;
             // FP64 recheck: the same float rows, widened exactly at load (the
             // pad 1e30 squares to 1e60 in FP64, still far above any path sum
             // of finite inputs below 1e15, so every min and sum is unchanged)
@@ -638,7 +650,7 @@ int device_cu_count()
 size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD)
 {
     const int LENA = staged_len(g, gd);
-    return (size_t)((LENA + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 8 + QCAP * 4 + 64 * 4 + 16;
+    return (size_t)((LENA + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 12 + QCAP * 4 + 16;
 }
 
 int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan, bool batched)
@@ -667,11 +679,12 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     // DTWs, FP64 recheck), and below that the chain of rounds cost more
     // than the extra DTWs a larger round starts on the measured workloads.
     const int64_t R = o->R > 0 ? o->R : (2 * P * NW > 128 ? 2 * P * NW : 128);
-    // Candidates per FP32 batch: the round, up to 64 (one bookkeeping lane
-    // each); all FP64 rechecks of a batch in one engine call.  Only the
-    // query row and bookkeeping live in LDS.
-    const int SLOTS = 64;
-    const int PD = SLOTS;
+    // Candidates per FP32 batch: the round, up to 128, so that a round of
+    // the default size is one batch (every batch ends waiting for its
+    // longest DTW); up to 64 FP64 rechecks per engine call.  Only the query
+    // row and bookkeeping live in LDS.
+    const int SLOTS = 128;
+    const int PD = 64;
     const size_t lds = search_lds_bytes(g, gd, SLOTS, PD);
     if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the search", L);
     // the engines read padded rows [base0 - PADL, base0 - PADL + LEN) of Bp
