@@ -170,7 +170,7 @@ struct SearchArgs {
     EngineGeom geo;    // FP32 engine (rows streamed from global memory)
     EngineGeom geoD;   // FP64 recheck engine (the same float rows, converted)
     int PD;        // FP64 rechecks per engine call (<= 64)
-    int SLOTS;     // candidates per FP32 batch (<= 128)
+    int SLOTS;     // candidates per FP32 batch (<= 256)
     const float *B;
     const float *Bp;   // padded rows of the reference set
     int64_t ppitch;

@@ -42,7 +42,7 @@ namespace nndtw {
 #define NNDTW_FOR_EACH_CPL(X) X(1) X(2) X(3) X(4) X(6) X(8) X(9)
 constexpr int SEARCH_MAX_CPL = 9;
 
-constexpr int QCAP = 256;        // survivor ring (>= the largest batch + one chunk of 64)
+constexpr int QCAP = 512;        // survivor ring (>= the largest batch + one chunk of 64)
 constexpr int SEARCH_MAX_WAVES = NNDTW_SEARCH_MAX_WAVES;
 constexpr int SEARCH_DEFAULT_WAVES = 4;
 constexpr int ORDER_THREADS = 256;
@@ -675,15 +675,15 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     const int NW = o->waves > 0 ? o->waves : SEARCH_DEFAULT_WAVES;
     // Default round: two candidates per group, so that groups whose
     // candidate is abandoned early take another one within the round, and
-    // at least 128: each round is a serial step of the query (threshold,
+    // at least 256: each round is a serial step of the query (threshold,
     // DTWs, FP64 recheck), and below that the chain of rounds cost more
     // than the extra DTWs a larger round starts on the measured workloads.
-    const int64_t R = o->R > 0 ? o->R : (2 * P * NW > 128 ? 2 * P * NW : 128);
-    // Candidates per FP32 batch: the round, up to 128, so that a round of
+    const int64_t R = o->R > 0 ? o->R : (2 * P * NW > 256 ? 2 * P * NW : 256);
+    // Candidates per FP32 batch: the round, up to 256, so that a round of
     // the default size is one batch (every batch ends waiting for its
     // longest DTW); up to 64 FP64 rechecks per engine call.  Only the query
     // row and bookkeeping live in LDS.
-    const int SLOTS = 128;
+    const int SLOTS = 256;
     const int PD = 64;
     const size_t lds = search_lds_bytes(g, gd, SLOTS, PD);
     if (lds > 160 * 1024) return fail(NNDTW_EUNSUP, "series length %d too long for the search", L);

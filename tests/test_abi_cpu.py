@@ -232,8 +232,8 @@ def test_search_plan_has_a_shape_for_every_window():
             C = opts.cpl
             G = -(-(Wp + 1) // C)
             assert C in (1, 2, 3, 4, 6, 8, 9) and G <= 63, (L, W, C, G)
-            # default round: two candidates per group, at least 128
-            assert opts.R == max(2 * (63 // G) * opts.waves, 128), (L, W, opts.R)
+            # default round: two candidates per group, at least 256
+            assert opts.R == max(2 * (63 // G) * opts.waves, 256), (L, W, opts.R)
     # where the narrow shapes (<= 4 pairs per lane) leave one group per wave
     # with lanes idle, a wider shape is taken: W=128 at L=512 (129 diagonal
     # pairs) runs 4 groups of 15 lanes at 9 pairs per lane, not one group of
