@@ -29,7 +29,7 @@ template <> struct Pad<double> { static __host__ __device__ constexpr double big
 // several co-resident workgroups the last dispatched would run mostly in the
 // gaps of the others and end far behind them, alone on an otherwise idle
 // SIMD.  With the rotation each wave's priority cycles through 0..3, one step
-// every 5.12 us of the 100 MHz real-time clock, offset by the workgroup's
+// every 20.48 us of the 100 MHz real-time clock, offset by the workgroup's
 // phase, so co-resident workgroups with different phases take turns at the
 // top.  Workgroups are dispatched to successive compute units, so those that
 // share a unit are ncu apart in dispatch order and rotation_phase gives them
@@ -43,7 +43,7 @@ __device__ __forceinline__ int rotation_phase(int ncu)
 
 __device__ __forceinline__ void rotate_priority(int phase)
 {
-    const unsigned pr = ((unsigned)(__builtin_amdgcn_s_memrealtime() >> 9) + (unsigned)phase) & 3u;
+    const unsigned pr = ((unsigned)(__builtin_amdgcn_s_memrealtime() >> 11) + (unsigned)phase) & 3u;
     if (pr == 0) __builtin_amdgcn_s_setprio(0);
     else if (pr == 1) __builtin_amdgcn_s_setprio(1);
     else if (pr == 2) __builtin_amdgcn_s_setprio(2);
