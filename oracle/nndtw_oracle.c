@@ -52,11 +52,16 @@ static int eff_window(int L, int W) { return W < L - 1 ? W : L - 1; }
 static int n_bands_of(int L, int V) { return imin(L / 2, V); }
 
 /* Relative slack for every prune/abandon test: twice gamma_{2L+2} of float32,
- * gamma_n = n u / (1 - n u) ~ n u with u = 2^-24 (an FP32 warping-path sum has
- * at most 2L-1 cells, each adding one rounding plus two from the difference). */
+ * gamma_n = n u / (1 - n u) with u = 2^-24.  An FP32 warping-path sum has at
+ * most 2L-1 cells; its first term is rounded once by the difference (twice
+ * after squaring) and once by every fused multiply-add after it, so every
+ * FP32 path cost is within a factor 1 +- gamma_{2L+1} of the exact one, and
+ * twice gamma_{2L+2} exceeds twice gamma_{2L+1} at every length.  (The
+ * approximation 2 (2L+2) u falls just short of 2 gamma_{2L+1} at L = 2048.) */
 double oracle_slack(int L)
 {
-    return 2.0 * (double)(2 * L + 2) * ldexp(1.0, -24);
+    double nu = (double)(2 * L + 2) * ldexp(1.0, -24);
+    return 2.0 * nu / (1.0 - nu);
 }
 
 /* ------------------------------------------------------------------------ */

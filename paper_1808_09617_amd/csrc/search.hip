@@ -20,7 +20,8 @@
 // Why the result and the stage counts do not depend on FP32 rounding: with
 // u = 2^-24 and gamma = (2L+1)u / (1-(2L+1)u), an FP32 cell value is within a
 // factor (1 +- gamma) of the exact one (each term of a path sum is rounded at
-// most 2L+1 times).  Every test uses the slack eps >= 2 gamma:
+// most 2L+1 times).  Every test uses the slack eps >= 2 gamma (the default,
+// also the smallest eps accepted, is twice gamma_{2L+2}):
 //  * a bound prunes only if bound > thr = min(bsf, ub)(1 + eps), so the exact
 //    DTW exceeds bsf and the candidate could not have changed the record;
 //  * an FP32 frontier above thr means an exact value above thr / (1+gamma)
@@ -703,7 +704,15 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     plan->T = g.T;
     plan->LEN = g.LEN;
     plan->R = R;
-    plan->eps = o->eps > 0 ? o->eps : 2.0 * (double)(2 * L + 2) * 0x1p-24;
+    // The slack must cover the FP32 error (see the header): eps >= 2 gamma,
+    // with gamma = gamma_{2L+1} of float32.  The default and the smallest
+    // value accepted is twice gamma_{2L+2} = 2 n u / (1 - n u), n = 2L + 2.
+    const double nu = (double)(2 * L + 2) * 0x1p-24;
+    const double eps_min = 2.0 * nu / (1.0 - nu);
+    if (o->eps > 0 && o->eps < eps_min)
+        return fail(NNDTW_EINVAL, "eps=%g below the FP32 error floor %.9g for L=%d (2 gamma_{2L+2})", o->eps,
+                    eps_min, L);
+    plan->eps = o->eps > 0 ? o->eps : eps_min;
     plan->lds_bytes = lds;
     return NNDTW_OK;
 }

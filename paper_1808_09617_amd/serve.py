@@ -59,6 +59,13 @@ class Server:
         self.V, self.R, self.cpl = V, R, cpl
         # workspace of one query per set, for admission by footprint
         self.per_query = [batch_bytes([rs], [1], V) for rs in self.refsets]
+        # the round size and engine shape every batch uses per set (given, or
+        # the batched search's defaults): a request's result is that of its
+        # query searched alone with these
+        probe = BatchSearcher([(rs, torch.zeros((1, rs.L), dtype=torch.float32, device=rs.device))
+                               for rs in self.refsets], V=V, R=R, cpl=cpl)
+        self.plan_R, self.plan_cpl = list(probe.R), list(probe.cpl)
+        del probe
 
     def _launch(self, reqs, stream):
         """One batched search over `reqs` on `stream`; returns (searcher,
@@ -68,8 +75,8 @@ class Server:
             by_set.setdefault(r.set_id, []).append(r)
         sets = sorted(by_set)
         where = {}
-        R = None if self.R is None else [self.R[s] for s in sets]
-        cpl = None if self.cpl is None else [self.cpl[s] for s in sets]
+        R = [self.plan_R[s] for s in sets]
+        cpl = [self.plan_cpl[s] for s in sets]
         with torch.cuda.stream(stream):
             pairs = []
             for k, s in enumerate(sets):

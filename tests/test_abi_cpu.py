@@ -258,3 +258,28 @@ def test_search_kernels_fit_the_register_file():
     assert len(search) >= 2 * 4 + 2 * 4                     # 4 shapes x 2, single-set and batched
     for name, v, a, scratch in search:
         assert int(scratch) == 0 and int(a) == 0 and int(v) <= 256, (name, v, a, scratch)
+
+
+def test_search_eps_floor():
+    """The slack must cover the FP32 error of a path sum: eps <= 0 selects the
+    floor 2 g / (1 - g), g = (2L + 2) 2^-24, and 0 < eps < floor is rejected
+    (a smaller slack could let FP32 rounding drop the nearest neighbour or a
+    lower-index tie).  The floor equals the oracle's slack."""
+    import oracle
+    lib = nd.lib()
+    for L in (2, 64, 256, 512, 2048):
+        d = nd._Refset()
+        d.magic, d.L, d.n, d.W = nd.REFSET_MAGIC, L, 100, max(1, L // 10)
+        d.padl, d.ppitch = 4096, 16384
+        floor = oracle.slack(L)
+        g = (2 * L + 2) * 2.0 ** -24
+        assert floor == 2.0 * g / (1.0 - g)
+        # twice gamma_{2L+1}, the FP32 error bound of a path sum, is covered
+        n1 = (2 * L + 1) * 2.0 ** -24
+        assert floor >= 2.0 * n1 / (1.0 - n1)
+        for eps in (floor * (1 - 1e-9), floor / 2, 1e-12):
+            opts = nd._opts(5, "keogh_enh", 0, eps, True, 0)
+            assert _err(lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)), "FP32 error floor") == nd.EINVAL
+        for eps in (0.0, -1.0, floor, 2 * floor, 0.5):
+            opts = nd._opts(5, "keogh_enh", 0, eps, True, 0)
+            assert lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)) == 0, (L, eps, nd.last_error())
