@@ -263,7 +263,11 @@ typedef struct nndtw_search_opts {
     int32_t V;        /* LB_Enhanced tightness parameter (>= 1)                      */
     int32_t cascade;  /* NNDTW_CASCADE_*                                              */
     int64_t R;        /* round size; 0 = library default; on return: the value used  */
-    double  eps;      /* relative slack; <= 0 selects 2 * (2L + 2) * 2^-24           */
+    double  eps;      /* relative slack; <= 0 selects the floor 2 g / (1 - g) with
+                       * g = (2L + 2) * 2^-24 (twice gamma_{2L+2} of float32, which
+                       * covers the FP32 error of a path sum); 0 < eps < floor is
+                       * EINVAL (a smaller slack could let FP32 rounding drop the
+                       * nearest neighbour or a lower-index tie)                    */
     int32_t init_ub;  /* 1: bound the first round by the first candidate's ED^2      */
     int32_t cpl;      /* engine shape (diagonal pairs per lane); 0 = default; out    */
     void *const *events; /* optional hipEvent_t[5] (caller-created), recorded on the
