@@ -299,6 +299,25 @@ int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ,
                  nndtw_search_opts *opts, int64_t *nn_idx, double *nn_dist,
                  int64_t *counts, void *ws, size_t ws_bytes, void *stream);
 
+/* nndtw_search without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a fixed device array of
+ * NNDTW_SEARCH_SCRATCH_BYTES inside the library, one per GPU, held from the
+ * device's first use until the process ends; the call allocates nothing and
+ * otherwise behaves exactly as nndtw_search (same validation, kernels and
+ * results).  EUNSUP when the workspace nndtw_search_workspace_bytes reports
+ * exceeds NNDTW_SEARCH_SCRATCH_BYTES (60 bytes per (query, reference) pair:
+ * up to about 1.1 million pairs, e.g. 1000 queries x 1000 references; split
+ * larger query sets into several calls).  Every call on one GPU uses that
+ * GPU's single array: calls that overlap on the same GPU (other streams or
+ * threads) race and corrupt each other's results; serialise them. */
+#define NNDTW_SEARCH_SCRATCH_BYTES ((size_t)64 << 20)
+/* Devices (ordinals 0 .. NNDTW_MAX_DEVICES-1) nndtw_search_noalloc serves. */
+#define NNDTW_MAX_DEVICES 64
+int nndtw_search_noalloc(const nndtw_refset *refset, const float *Q, int64_t nQ,
+                         nndtw_search_opts *opts, int64_t *nn_idx, double *nn_dist,
+                         int64_t *counts, void *stream);
+
 /* The fused bound pass the search runs first, exposed on its own: for every
  * query q and reference k of the set, ed2 = squared Euclidean distance,
  * lbk = LB_Keogh, lbe_bands = Algorithm 1 bands part, lbe = LB_Enhanced^V

@@ -27,6 +27,7 @@ COUNT_NAMES = ("n", "pruned_keogh", "pruned_enh_bands", "pruned_enh", "dtw_start
 MAX_L = 2048
 SEARCH_MAX_N = 8192
 SEARCH_MAX_WAVES = 8
+SEARCH_SCRATCH_BYTES = 64 << 20
 REFSET_MAGIC = 0x4E444157
 
 
@@ -91,6 +92,8 @@ SIGNATURES = {
     "nndtw_search": (ctypes.c_int, [ctypes.POINTER(_Refset), _P, _I64, ctypes.POINTER(_SearchOpts), _P, _P,
                                     _P, _P, _SZ, _P]),
     "nndtw_search_plan": (ctypes.c_int, [ctypes.POINTER(_Refset), ctypes.POINTER(_SearchOpts)]),
+    "nndtw_search_noalloc": (ctypes.c_int, [ctypes.POINTER(_Refset), _P, _I64, ctypes.POINTER(_SearchOpts), _P, _P,
+                                            _P, _P]),
     "nndtw_cascade_bounds": (ctypes.c_int, [ctypes.POINTER(_Refset), _P, _I64, _I32, _P, _P, _P, _P, _P]),
     "nndtw_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(_BatchSet), _I32, ctypes.POINTER(_SearchOpts),
                                                    ctypes.POINTER(_SZ)]),
@@ -446,6 +449,19 @@ def search(refset: RefSet, Q: torch.Tensor, V: int = 5, cascade: str = "keogh_en
     s = Searcher(refset, Q.shape[0], V, cascade, R, eps, init_ub, cpl, waves)
     idx, dist, counts = s(Q)
     return idx.clone(), dist.clone(), counts.clone(), s.R
+
+
+def search_noalloc(refset: RefSet, Q: torch.Tensor, idx: torch.Tensor, dist: torch.Tensor, counts=None,
+                   V: int = 5, cascade: str = "keogh_enh", R: int = 0, eps: float = 0.0, init_ub: bool = True,
+                   cpl: int = 0, waves: int = 0):
+    """nndtw_search_noalloc: the search into caller-provided outputs (idx int64
+    [nQ], dist float64 [nQ], counts int64 [nQ][8] or None) with the library's
+    fixed device workspace; returns the R used."""
+    Q = _series(Q, "Q")
+    opts = _opts(V, cascade, R, eps, init_ub, cpl, waves)
+    _check(lib().nndtw_search_noalloc(ctypes.byref(refset.desc), _ptr(Q), Q.shape[0], ctypes.byref(opts), _ptr(idx),
+                                      _ptr(dist), _ptr(counts), _stream()))
+    return int(opts.R)
 
 
 def cascade_bounds(refset: RefSet, Q: torch.Tensor, V: int):

@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "common.hpp"
 
 namespace nndtw {
@@ -370,6 +372,66 @@ int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ, nndtw_s
     opts->cpl = plan.C;
     opts->waves = plan.NW;
     return launch_search(refset, Q, nQ, opts, plan, nn_idx, nn_dist, counts, ws, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Search without a workspace argument: the workspace of nndtw_search lives in
+// a fixed device array of this file, which every GPU the library runs on
+// holds until the process ends.  In host code `scratch` is only a stand-in
+// for the device address: kernels are given the address that
+// hipGetSymbolAddress returns for the current device, taken once per device.
+static __device__ __align__(256) unsigned char scratch[NNDTW_SEARCH_SCRATCH_BYTES];
+
+namespace nndtw {
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NNDTW_MAX_DEVICES];
+
+// Device address of `scratch` on the current device (looked up on the
+// device's first call).
+static int scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= NNDTW_MAX_DEVICES)
+        return fail(NNDTW_EUNSUP, "device %d: the scratch array is tracked for %d devices", dev, NNDTW_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (ptr == nullptr || ((uintptr_t)ptr & 255u) != 0)
+            return fail(NNDTW_EHIP, "scratch array at an unexpected address %p", ptr);
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return NNDTW_OK;
+}
+}  // namespace nndtw
+
+extern "C" {
+
+int nndtw_search_noalloc(const nndtw_refset *refset, const float *Q, int64_t nQ, nndtw_search_opts *opts,
+                         int64_t *nn_idx, double *nn_dist, int64_t *counts, void *stream)
+{
+    g_err[0] = 0;
+    TRY(check_refset(refset));
+    TRY(check_opts(opts));
+    REQUIRE(nQ >= 0, "nQ=%lld must be >= 0", (long long)nQ);
+    const size_t need = search_ws_bytes(nQ, refset->n, refset->L);
+    if (nQ > 0 && need > (size_t)NNDTW_SEARCH_SCRATCH_BYTES)
+        return fail(NNDTW_EUNSUP,
+                    "search of %lld queries against %lld references needs %zu workspace bytes, above the %zu of "
+                    "the fixed scratch array (NNDTW_SEARCH_SCRATCH_BYTES): split the queries or use nndtw_search",
+                    (long long)nQ, (long long)refset->n, need, (size_t)NNDTW_SEARCH_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if (nQ > 0) TRY(scratch_address(&ws));
+    // nndtw_search validates everything else and enqueues the same kernels;
+    // nothing in the workspace needs clearing (every array is written before
+    // it is read within the call)
+    return nndtw_search(refset, Q, nQ, opts, nn_idx, nn_dist, counts, ws, NNDTW_SEARCH_SCRATCH_BYTES, stream);
 }
 
 int nndtw_cascade_bounds(const nndtw_refset *refset, const float *Q, int64_t nQ, int32_t V, double *ed2,
