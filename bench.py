@@ -3,10 +3,13 @@
 
 A step is one pass of the whole path over one batch: build the reference set
 (copy, envelopes, point-major copies), then the search (fused bound pass,
-visiting order, round-based pruned search with DTW_W).  The workload is the
-1000 x 1000, L=256, W=26 (0.1 L) class-sinusoid configuration with the
-paper's recommended V=5 and the LB_Keogh -> LB_Enhanced cascade.  Inputs are
-resident in HBM before timing starts.
+visiting order, round-based pruned search with DTW_W).  The headline workload
+is the largest plain NN-DTW configuration: 5000 references x 500 queries,
+L=512, random walks mixed with class sinusoids, window W=51 (0.1 L, the
+paper's recommended fraction) with V=5 and the LB_Keogh -> LB_Enhanced
+cascade.  Inputs are resident in HBM before timing starts.  The 1000 x 1000,
+L=256 class-sinusoid configuration, the whole window sweep, batching,
+serving, the backward pass and the comparison bounds are reported beside it.
 
 Prints ONE JSON line (see the design doc for every field).
 """
@@ -98,21 +101,46 @@ def profiled_traffic(kernel, workload):
     return val if fp is not None and fp == device_code_fingerprint() else None
 
 
-def cpu_baseline(wl, W, V, target_s):
-    import numpy as np
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, W, V, target_s, unit_scale=1.0):
+    """The oracle's paper-mode search (R = 1, the paper's sequential loop) on
+    the host's cores: all threads over a prefix of the queries sized to about
+    target_s seconds, then one thread over a smaller prefix."""
     import oracle
     threads = oracle.max_threads()
-    n = 8
+    nq_all = wl.queries.shape[0]
+    n = min(nq_all, max(4, threads))
     t = time.perf_counter()
     oracle.search(wl.refs, wl.queries[:n], W, V, "keogh_enh", 1, True)
     dt = time.perf_counter() - t
-    want = int(min(wl.queries.shape[0], max(n, n * target_s / max(dt, 1e-3))))
+    want = int(min(nq_all, max(n, n * target_s / max(dt, 1e-3))))
     t = time.perf_counter()
     oracle.search(wl.refs, wl.queries[:want], W, V, "keogh_enh", 1, True)
     dt = time.perf_counter() - t
+    # single thread, on a prefix of about target_s / 4 seconds
+    one = int(min(want, max(1, want * (target_s / 4.0) / max(dt * threads, 1e-3))))
+    oracle.set_threads(1)
+    try:
+        t = time.perf_counter()
+        oracle.search(wl.refs, wl.queries[:one], W, V, "keogh_enh", 1, True)
+        dt1 = time.perf_counter() - t
+    finally:
+        oracle.set_threads(threads)
     return {"value": want / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {want} of {wl.queries.shape[0]} queries, full reference set, paper-mode "
-                      f"sequential search (R=1), LB_Keogh->LB_Enhanced^{V}, FP64, {dt:.1f} s wall"}
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread": {"value": one / dt1, "unit": "queries/s", "queries": one, "wall_s": dt1},
+            "sample": f"first {want} of {nq_all} queries of {wl.name}, full reference set ({wl.refs.shape[0]}), "
+                      f"W={W}, paper-mode sequential search (R=1), LB_Keogh->LB_Enhanced^{V}, FP64, "
+                      f"{dt:.1f} s wall on {threads} threads; single thread: first {one} queries, {dt1:.1f} s"}
 
 
 def hbm_streaming(nd, synth, torch, dev):
@@ -462,6 +490,117 @@ def compare_bounds(nd, synth, torch, dev, a, b, W=26):
             "search_nndtw_sin256": c2, "search_nndtw_mix512_by_W": c3}
 
 
+def profiled_kernel_us(kernel, workload):
+    """Average duration (us) of `kernel` in the committed rocprofv3 kernel-trace
+    summary of `workload`, if it was taken from the current device code."""
+    path = os.path.join(ROOT, "profiles", f"kernel_stats_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    fp, val = None, None
+    for line in open(path):
+        if line.startswith("# device code fingerprint"):
+            fp = line.split(":", 1)[1].strip()
+        parts = line.split()
+        if not line.startswith("#") and len(parts) >= 6 and kernel in line:
+            try:
+                val = float(parts[-4])
+            except ValueError:
+                pass
+    return val if fp is not None and fp == device_code_fingerprint() else None
+
+
+def search_step_bench(nd, torch, hip, dev, wl, W, V, args, headline):
+    """Time steps (reference-set build + full search) of one workload: K timed
+    steps that enqueue nothing else, then K untimed steps with an event pair
+    each (latency) and K with events between the stages (stage times, and the
+    search kernel's average duration for the roofline)."""
+    N, Q, L = wl.refs.shape[0], wl.queries.shape[0], wl.L
+    refs = torch.from_numpy(wl.refs).to(dev)
+    qs = torch.from_numpy(wl.queries).to(dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rs = nd.RefSet(refs, W)
+    srch = nd.Searcher(rs, Q, V=V, cascade="keogh_enh", R=args.R, init_ub=True, cpl=args.cpl, waves=args.waves)
+
+    def step(ev=None, stage_ev=None):
+        if ev is not None:
+            hip.record(ev[0], stream)
+        rs.rebuild(refs)
+        srch.set_events(stage_ev)
+        out = srch(qs)
+        if ev is not None:
+            hip.record(ev[1], stream)
+        return out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    K = args.steps
+    step_ev = [hip.events(2) for _ in range(K)]
+    stage_ev = [hip.events(5) for _ in range(K)]
+    torch.cuda.synchronize()
+    # timed steps: nothing but the steps (an event recorded between kernels
+    # costs the stream time of its own)
+    t0 = time.perf_counter()
+    for k in range(K):
+        idx, dist, counts = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / K
+    for k in range(K):
+        step(step_ev[k])
+    torch.cuda.synchronize()
+    lat = sorted(hip.ms(e[0], e[1]) for e in step_ev)
+    for k in range(K):
+        step(None, stage_ev[k])
+    torch.cuda.synchronize()
+    st = {name: [hip.ms(e[i], e[i + 1]) for e in stage_ev] for i, name in
+          enumerate(["bounds", "cells_prefix", "order", "search"])}
+    st_avg = {k: sum(v) / len(v) for k, v in st.items()}
+
+    c = counts.cpu().numpy()
+    cells = int(c[:, 6].sum())
+    started = int(c[:, 4].sum())
+    pairs = N * Q
+    # roofline of the dominant kernel: the search kernel, ALU-bound (3 useful
+    # VALU lane operations per band cell it evaluates)
+    cells_ops = 3.0 * cells
+    t_search = st_avg["search"] / 1e3
+    ach = cells_ops / t_search
+    prof_us = profiled_kernel_us("search_kernel", wl.name)
+    roof = {"kernel": "search_kernel", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "Tops/s", "frac": ach / VALU_PEAK_OPS,
+            "traffic": profiled_traffic("search_kernel", wl.name),
+            "kernel_avg_us_events": t_search * 1e6, "cells_per_launch": cells,
+            "kernel_avg_us_rocprof": prof_us,
+            "frac_rocprof": (cells_ops / (prof_us / 1e6) / VALU_PEAK_OPS) if prof_us else None}
+    bytes_bounds = 12.0 * N * L * math.ceil(Q / 4) + 32.0 * Q * N
+    res = {
+        "metric": METRIC, "value": Q / (ms_step / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "N": N, "Q": Q, "L": L, "W": W, "V": V, "cascade": "keogh_enh",
+                   "R": srch.R, "cpl": srch.cpl, "waves_per_query": srch.waves, "init_ub": True},
+        "roofline": roof,
+        "dtw_cells_per_s": cells / (ms_step / 1e3),
+        "search_kernel_cells_per_s": cells / t_search,
+        "valu_frac_dtw": cells_ops / t_search / VALU_PEAK_OPS,
+        "pruning_rate": 1.0 - started / pairs,
+        "pruned": {"keogh": int(c[:, 1].sum()) / pairs, "enh_bands": int(c[:, 2].sum()) / pairs,
+                   "enh": int(c[:, 3].sum()) / pairs},
+        "dtw_started": started, "dtw_abandoned": int(c[:, 5].sum()), "fp64_rechecks": int(c[:, 7].sum()),
+        "latency_ms": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
+                       "max": lat[-1]},
+        "stage_ms": st_avg,
+        "bounds_kernel_gbps_algorithmic": bytes_bounds / (st_avg["bounds"] / 1e3) / 1e9,
+    }
+    if not headline:
+        for k in ("metric", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline", "data"):
+            res.pop(k)
+    res["_refset"], res["_queries"] = rs, qs
+    del srch
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -520,111 +659,42 @@ def main():
                           "compare_bounds": compare_bounds(nd, synth, torch, dev, a, b)}), flush=True)
         return
 
-    wl = synth.workload("nndtw-sin256")
-    W, V = wl.windows[0], args.V
-    N, Q, L = wl.refs.shape[0], wl.queries.shape[0], wl.L
     dev = torch.device("cuda:0")
-    refs = torch.from_numpy(wl.refs).to(dev)
-    qs = torch.from_numpy(wl.queries).to(dev)
     hip = Hip()
-    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-
-    rs = nd.RefSet(refs, W)
-    srch = nd.Searcher(rs, Q, V=V, cascade="keogh_enh", R=args.R, init_ub=True, cpl=args.cpl, waves=args.waves)
-    log(f"workload nndtw-sin256 N={N} Q={Q} L={L} W={W} V={V}")
-
-    def step(ev=None, stage_ev=None):
-        if ev is not None:
-            hip.record(ev[0], stream)
-        rs.rebuild(refs)
-        srch.set_events(stage_ev)
-        out = srch(qs)
-        if ev is not None:
-            hip.record(ev[1], stream)
-        return out
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    K = args.steps
-    step_ev = [hip.events(2) for _ in range(K)]
-    stage_ev = [hip.events(5) for _ in range(K)]
-    torch.cuda.synchronize()
-    # timed steps: nothing but the steps (an event recorded between kernels
-    # costs the stream time of its own)
-    t0 = time.perf_counter()
-    for k in range(K):
-        idx, dist, counts = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    log(f"timed {K} steps")
-    ms_step = (t1 - t0) * 1e3 / K
-    # per-step latency from as many untimed steps, one event pair each
-    for k in range(K):
-        step(step_ev[k])
-    torch.cuda.synchronize()
-    lat = sorted(hip.ms(e[0], e[1]) for e in step_ev)
-    # per-stage times (and the search kernel's duration for the roofline) from
-    # as many untimed steps with events between the stages
-    for k in range(K):
-        step(None, stage_ev[k])
-    torch.cuda.synchronize()
-    st = {name: [hip.ms(e[i], e[i + 1]) for e in stage_ev] for i, name in
-          enumerate(["bounds", "cells_prefix", "order", "search"])}
-    st_avg = {k: sum(v) / len(v) for k, v in st.items()}
-
-    c = counts.cpu().numpy()
-    cells = int(c[:, 6].sum())
-    started = int(c[:, 4].sum())
-    pairs = N * Q
-    # roofline of the dominant kernel
-    cells_ops = 3.0 * cells                              # sub, min3, fma per cell
-    bounds_ops = 9.0 * Q * N * L                         # FP64 per (query, reference, point)
-    if st_avg["search"] >= st_avg["bounds"]:
-        t = st_avg["search"] / 1e3
-        ach = cells_ops / t
-        roof = {"kernel": "search_kernel", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                "unit": "Tops/s", "frac": ach / VALU_PEAK_OPS,
-                "traffic": profiled_traffic("search_kernel", "nndtw-sin256")}
-    else:
-        t = st_avg["bounds"] / 1e3
-        ach = bounds_ops / t
-        roof = {"kernel": "cascade_bounds_kernel", "bound": "alu", "achieved": ach / 1e12,
-                "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s", "frac": ach / VALU_PEAK_OPS,
-                "traffic": profiled_traffic("cascade_bounds_kernel", "nndtw-sin256")}
-    bytes_bounds = 12.0 * N * L * math.ceil(Q / 4) + 32.0 * Q * N
-    res = {
-        "metric": METRIC, "value": Q / (ms_step / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": K,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "nndtw-sin256", "N": N, "Q": Q, "L": L, "W": W, "V": V, "cascade": "keogh_enh",
-                   "R": srch.R, "cpl": srch.cpl, "waves_per_query": srch.waves, "init_ub": True},
-        "roofline": roof,
-        "dtw_cells_per_s": cells / (ms_step / 1e3),
-        "search_kernel_cells_per_s": cells / (st_avg["search"] / 1e3),
-        "valu_frac_dtw": cells_ops / (st_avg["search"] / 1e3) / VALU_PEAK_OPS,
-        "pruning_rate": 1.0 - started / pairs,
-        "pruned": {"keogh": int(c[:, 1].sum()) / pairs, "enh_bands": int(c[:, 2].sum()) / pairs,
-                   "enh": int(c[:, 3].sum()) / pairs},
-        "dtw_started": started, "dtw_abandoned": int(c[:, 5].sum()), "fp64_rechecks": int(c[:, 7].sum()),
-        "latency_ms": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
-                       "max": lat[-1]},
-        "stage_ms": st_avg,
-        "bounds_kernel_gbps_algorithmic": bytes_bounds / (st_avg["bounds"] / 1e3) / 1e9,
-    }
+    wl = synth.workload("nndtw-mix512")
+    W_head = int(math.floor(0.1 * wl.L + 0.5))           # W = round-half-up(0.1 L) = 51
+    log(f"workload nndtw-mix512 W={W_head} V={args.V}")
+    res = search_step_bench(nd, torch, hip, dev, wl, W_head, args.V, args, headline=True)
+    log(f"timed {args.steps} steps")
 
     if not args.no_extras:
-        # arm B: plain per-query LB_Keogh -> DTW, one query per launch sequence
+        V = args.V
+        # the headline set searched one query per launch sequence (arm B:
+        # plain per-query LB_Keogh -> DTW, no ED upper bound)
+        rs, qs = res.pop("_refset"), res.pop("_queries")
         nq = 100
-        one = [nd.Searcher(rs, 1, V=V, cascade="keogh", R=0, init_ub=False)]
+        one = nd.Searcher(rs, 1, V=V, cascade="keogh", R=0, init_ub=False)
+        one(qs[:1])
         torch.cuda.synchronize()
         t = time.perf_counter()
         for i in range(nq):
-            one[0](qs[i:i + 1])
+            one(qs[i:i + 1])
         torch.cuda.synchronize()
         per_q = nq / (time.perf_counter() - t)
         res["per_query_keogh_qps"] = per_q
         res["speedup_vs_per_query_keogh"] = res["value"] / per_q
+        res["arms_2x2"] = arms_2x2(nd, torch, rs, qs, V)
+        del rs, qs, one
+        torch.cuda.empty_cache()
+        # the 1000 x 1000, L=256 class-sinusoid workload, measured as the headline
+        c2 = synth.workload("nndtw-sin256")
+        W = c2.windows[0]
+        sub = search_step_bench(nd, torch, hip, dev, c2, W, V, args, headline=False)
+        rs, qs = sub.pop("_refset"), sub.pop("_queries")
+        sub["arms_2x2"] = arms_2x2(nd, torch, rs, qs, V)
+        sub["per_v"] = per_v(nd, torch, rs, qs)
+        res["nndtw_sin256"] = sub
+        del rs, qs
         # LB tightness on independent class-sinusoid pairs (LB / DTW, un-rooted)
         a, b = synth.tightness_pairs(250_000)
         A, B = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
@@ -635,8 +705,6 @@ def main():
         for v in (1, 2, 5):
             tight[f"enhanced{v}"] = float((nd.lb_enhanced(A, B, U, Lo, W, v, zip_=True)[keep] / d[keep]).mean())
         res["tightness"] = tight
-        res["arms_2x2"] = arms_2x2(nd, torch, rs, qs, V)
-        res["per_v"] = per_v(nd, torch, rs, qs)
         res["small_latency"] = small_latency(nd, synth, torch, dev)
         log("arms, V and small-instance latency done")
         res["window_sweep"] = window_sweep(nd, synth, torch, dev)
@@ -658,8 +726,10 @@ def main():
         torch.cuda.synchronize()
         res["calib_copy_bytes"] = src.numel() * 4
 
+    res.pop("_refset", None)
+    res.pop("_queries", None)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(wl, W, V, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(wl, W_head, args.V, args.cpu_seconds)
         log("cpu baseline done")
     print(json.dumps(res), flush=True)
 

@@ -52,9 +52,9 @@ extern "C" {
 #define NNDTW_ZIP   1
 
 #define NNDTW_MAX_L 2048
-/* Largest reference-set size nndtw_search accepts (its visiting order is
- * sorted in on-chip memory). */
-#define NNDTW_SEARCH_MAX_N 8192
+/* Largest reference set of one set of the batched search (its visiting
+ * order is sorted on chip).  nndtw_search takes any reference set. */
+#define NNDTW_BATCH_MAX_N 8192
 /* Largest number of waves (workgroup of 64-lane waves) one query may use. */
 #define NNDTW_SEARCH_MAX_WAVES 8
 
@@ -275,9 +275,13 @@ typedef struct nndtw_search_opts {
                           * cells table is filled by the ordering kernel), after
                           * the ordering and after the search kernel; NULL
                           * records nothing                                           */
-    int32_t waves;    /* waves per query (1..NNDTW_SEARCH_MAX_WAVES); 0 = default; out */
+    int32_t waves;    /* waves per query (1..NNDTW_SEARCH_MAX_WAVES); 0 = default (8
+                       * when the query count is at most twice the device's compute
+                       * units, else 4); out                                          */
     int32_t reserved32;
-    int64_t reserved[2];
+    int64_t nq_hint;  /* nndtw_search_plan only: the query count to plan for (0 =
+                       * many); nndtw_search plans for its own nQ                    */
+    int64_t reserved;
 } nndtw_search_opts;
 
 /* Workspace bytes nndtw_search needs for nQ queries against refset. */
@@ -293,8 +297,10 @@ int nndtw_search_plan(const nndtw_refset *refset, nndtw_search_opts *opts);
 
 /* Q: device float[nQ][L] (L of the reference set); outputs: nn_idx int64[nQ],
  * nn_dist double[nQ], counts int64[nQ][NNDTW_NCOUNTS] (NULL allowed).
- * ws: device workspace of at least nndtw_search_workspace_bytes() bytes.
- * EUNSUP if refset->n > NNDTW_SEARCH_MAX_N. */
+ * ws: device workspace of at least nndtw_search_workspace_bytes() bytes
+ * (60 bytes per (query, reference) pair plus a table of 8L bytes).  Any
+ * reference-set size: above 8192 references the visiting order is sorted in
+ * chunks of 8192 that are then merged in the workspace. */
 int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ,
                  nndtw_search_opts *opts, int64_t *nn_idx, double *nn_dist,
                  int64_t *counts, void *ws, size_t ws_bytes, void *stream);

@@ -189,34 +189,31 @@ double oracle_lb_enhanced_eq7(const float *A, const float *B, const float *U,
     return s;
 }
 
-/* Algorithm 1, bands part: delta at the two corners, then for band index
- * i = 2..n_bands the left-band minimum and the mirrored right-band minimum,
- * accumulated as res <- (res + min_L) + min_R.                             */
+/* Bands part of LB_Enhanced^V_W (Equation 7): the band minima at both ends
+ * of the series, from the explicit band sets above.  Band index k = 1 is the
+ * single link (1, 1) on the left and (L, L) on the right; for k = 2..n_bands
+ * the left band L^W_k and the right band R^W_{L-k+1} (the mirror image of
+ * L^W_k at (L, L)).  Summation order (a convention shared with the GPU path,
+ * the order Algorithm 1 accumulates in): the two corner links first, then
+ * per band index the left minimum and then the right one.                  */
 double oracle_lb_enhanced_bands(const float *A, const float *B, int L, int W, int V)
 {
-    int w = eff_window(L, W);
     int nb = n_bands_of(L, V);
-    double res = delta(A[0], B[0]) + delta(A[L - 1], B[L - 1]);
-    for (int i = 1; i < nb; ++i) {                 /* paper: i = 2 .. n_bands */
-        int r = L - 1 - i;                         /* paper: L - i + 1        */
-        double mL = delta(A[i], B[i]);
-        double mR = delta(A[r], B[r]);
-        for (int j = imax(0, i - w); j < i; ++j) { /* paper: max(1,i-W)..i-1 */
-            int rj = L - 1 - j;                    /* paper: L - j + 1        */
-            mL = dmin(mL, delta(A[i], B[j]));
-            mL = dmin(mL, delta(A[j], B[i]));
-            mR = dmin(mR, delta(A[r], B[rj]));
-            mR = dmin(mR, delta(A[rj], B[r]));
-        }
-        res = res + mL + mR;
+    double res = band_min(A, B, L, W, 0, 0) + band_min(A, B, L, W, 1, L - 1);
+    for (int k = 1; k < nb; ++k) {
+        double left = band_min(A, B, L, W, 0, k);
+        double right = band_min(A, B, L, W, 1, L - 1 - k);
+        res = res + left + right;
     }
     return res;
 }
 
-/* Algorithm 1 in full: the bands part, then, unless it already exceeds the
- * current nearest-neighbour distance D (then +inf), the Keogh terms for
- * i = n_bands+1 .. L-n_bands added in ascending order.  The early exit uses
- * a strict comparison (a bound equal to D cannot exclude a tie).           */
+/* LB_Enhanced^V_W with the early exit of the paper's search: the bands part;
+ * if it already exceeds the current nearest-neighbour distance D the bound is
+ * +inf (strict comparison: a bound equal to D cannot exclude a tie),
+ * otherwise the LB_Keogh terms of the middle points n_bands+1 .. L-n_bands
+ * (1-based) are added in ascending order.  With D = +inf this is Equation 7
+ * summed in the order above.                                               */
 double oracle_lb_enhanced_alg1(const float *A, const float *B, const float *U,
                                const float *Lo, int L, int W, int V, double D)
 {

@@ -25,7 +25,7 @@ CASCADES = {"none": 0, "keogh": 1, "keogh_enh": 2, "enh": 3,
 COUNT_NAMES = ("n", "pruned_keogh", "pruned_enh_bands", "pruned_enh", "dtw_started",
                "dtw_abandoned", "cells", "fp64_rechecks")
 MAX_L = 2048
-SEARCH_MAX_N = 8192
+BATCH_MAX_N = 8192
 SEARCH_MAX_WAVES = 8
 SEARCH_SCRATCH_BYTES = 64 << 20
 REFSET_MAGIC = 0x4E444157
@@ -50,7 +50,7 @@ class _SearchOpts(ctypes.Structure):
     _fields_ = [("V", ctypes.c_int32), ("cascade", ctypes.c_int32), ("R", ctypes.c_int64),
                 ("eps", ctypes.c_double), ("init_ub", ctypes.c_int32), ("cpl", ctypes.c_int32),
                 ("events", ctypes.c_void_p), ("waves", ctypes.c_int32), ("reserved32", ctypes.c_int32),
-                ("reserved", ctypes.c_int64 * 2)]
+                ("nq_hint", ctypes.c_int64), ("reserved", ctypes.c_int64)]
 
 
 class _BatchSet(ctypes.Structure):

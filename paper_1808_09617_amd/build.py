@@ -44,7 +44,8 @@ RESOURCES = os.path.join(BUILD, "kernel_resources.txt")
 # quiet NaNs before each of them (a canonicalising max per term, and per
 # shifted FP64 value on the engine's dependency chain).
 NO_NANS = ["-fno-honor-nans"]
-EXTRA = {f: NO_NANS for f in ("bounds.hip", "compare.hip", "search.hip", "dtw.hip", "batch.hip", "grad.hip")}
+EXTRA = {f: NO_NANS for f in ("bounds.hip", "compare.hip", "search.hip", "dtw.hip", "batch.hip", "grad.hip",
+                               "envelopes.hip")}
 
 
 def _compile(src: str):

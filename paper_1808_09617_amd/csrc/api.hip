@@ -318,6 +318,7 @@ static int check_opts(const nndtw_search_opts *o)
     REQUIRE(o->cpl >= 0, "cpl=%d must be >= 0", o->cpl);
     REQUIRE(o->waves >= 0 && o->waves <= NNDTW_SEARCH_MAX_WAVES, "waves=%d must be in 0..%d", o->waves,
             NNDTW_SEARCH_MAX_WAVES);
+    REQUIRE(o->nq_hint >= 0, "nq_hint=%lld must be >= 0", (long long)o->nq_hint);
     return NNDTW_OK;
 }
 
@@ -353,9 +354,6 @@ int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ, nndtw_s
     TRY(check_refset(refset));
     TRY(check_opts(opts));
     REQUIRE(nQ >= 0, "nQ=%lld must be >= 0", (long long)nQ);
-    if (refset->n > NNDTW_SEARCH_MAX_N)
-        return fail(NNDTW_EUNSUP, "reference set of %lld series exceeds NNDTW_SEARCH_MAX_N=%d",
-                    (long long)refset->n, NNDTW_SEARCH_MAX_N);
     const bool any = nQ > 0;
     TRY(check_ptr(Q, 4, "Q", any));
     TRY(check_ptr(nn_idx, 8, "nn_idx", any));
@@ -367,7 +365,9 @@ int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ, nndtw_s
     if (opts->cascade > NNDTW_CASCADE_ENH && compare_lds_bytes(refset->L, refset->W) > 160 * 1024)
         return fail(NNDTW_EUNSUP, "series length %d too long for the comparison bounds", refset->L);
     SearchPlan plan;
-    TRY(plan_search(refset, opts, &plan));
+    nndtw_search_opts po = *opts;
+    po.nq_hint = nQ;
+    TRY(plan_search(refset, &po, &plan));
     opts->R = plan.R;
     opts->cpl = plan.C;
     opts->waves = plan.NW;
@@ -521,9 +521,9 @@ static int check_batch(const nndtw_batch_set *sets, int32_t nsets, const nndtw_s
         REQUIRE(s.nQ >= 0, "set %d: nQ=%lld must be >= 0", d, (long long)s.nQ);
         REQUIRE(s.nQ <= 0xFFFFFFFFLL, "set %d: too many queries", d);
         REQUIRE(s.R >= 0 && s.cpl >= 0, "set %d: R and cpl must be >= 0", d);
-        if (s.refset->n > NNDTW_SEARCH_MAX_N)
-            return fail(NNDTW_EUNSUP, "set %d: reference set of %lld series exceeds NNDTW_SEARCH_MAX_N=%d", d,
-                        (long long)s.refset->n, NNDTW_SEARCH_MAX_N);
+        if (s.refset->n > NNDTW_BATCH_MAX_N)
+            return fail(NNDTW_EUNSUP, "set %d: reference set of %lld series exceeds NNDTW_BATCH_MAX_N=%d", d,
+                        (long long)s.refset->n, NNDTW_BATCH_MAX_N);
         if (!ptrs) continue;
         const bool any = s.nQ > 0;
         if (int r = check_ptr(s.Q, 4, "Q", any)) return set_error(r, d);

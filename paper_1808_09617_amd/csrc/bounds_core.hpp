@@ -21,24 +21,39 @@ __device__ __forceinline__ double keogh_term(double a, double u, double lo)
     return t * t;
 }
 
-// Bands part of Algorithm 1 (corners and band indices 2..nb, 1-based).
+// Smallest point cost over one band of links around the corner cell (c, c):
+// the corner link itself and the pairs (c, x), (x, c) for x0 <= x <= x1
+// (0-based).  The left band L^W_k (Section 3) has c = k and x ranging over
+// the W positions before it; the right band, its mirror image at (L, L), has
+// x ranging over the W positions after c.  min is exact, so the result does
+// not depend on the order the links are visited in.
+template <typename FA, typename FB>
+__device__ __forceinline__ double band_min(FA av, FB bv, int c, int x0, int x1)
+{
+    const float ac = av(c), bc = bv(c);
+    double m = sqd(ac, bc);
+    for (int x = x0; x <= x1; ++x) {
+        m = __builtin_fmin(m, sqd(ac, bv(x)));
+        m = __builtin_fmin(m, sqd(av(x), bc));
+    }
+    return m;
+}
+
+// Bands part of LB_Enhanced^V (Equation 7) for nb = min(floor(L/2), V) band
+// indices at each end: the single corner links (0, 0) and (L-1, L-1), then
+// per band index k = 1..nb-1 the left band around (k, k) and the right band
+// around (L-1-k, L-1-k), summed as res <- (res + left) + right (the
+// accumulation order of the paper's algorithm, which the oracle follows too).
 // av(i) / bv(j) fetch A_i and B_j (0-based).
 template <typename FA, typename FB>
 __device__ __forceinline__ double enh_bands(FA av, FB bv, int L, int W, int nb)
 {
     double res = sqd(av(0), bv(0)) + sqd(av(L - 1), bv(L - 1));
-    for (int i = 1; i < nb; ++i) {
-        const int r = L - 1 - i;
-        const float ai = av(i), bi = bv(i), ar = av(r), br = bv(r);
-        double mL = sqd(ai, bi), mR = sqd(ar, br);
-        for (int j = max(0, i - W); j < i; ++j) {
-            const int rj = L - 1 - j;
-            mL = __builtin_fmin(mL, sqd(ai, bv(j)));
-            mL = __builtin_fmin(mL, sqd(av(j), bi));
-            mR = __builtin_fmin(mR, sqd(ar, bv(rj)));
-            mR = __builtin_fmin(mR, sqd(av(rj), br));
-        }
-        res = res + mL + mR;
+    for (int k = 1; k < nb; ++k) {
+        const double left = band_min(av, bv, k, max(0, k - W), k - 1);
+        const int p = L - 1 - k;
+        const double right = band_min(av, bv, p, p + 1, min(L - 1, p + W));
+        res = res + left + right;
     }
     return res;
 }

@@ -33,6 +33,8 @@
 // The bounds are FP64 sums in the same order as a sequential evaluation, and
 // the recomputed distances are bit-identical to a sequential FP64 evaluation
 // of the recurrence, so every decision is taken on the same values.
+#include <algorithm>
+
 #include "dtw_engine.hpp"
 
 namespace nndtw {
@@ -123,26 +125,15 @@ __device__ __forceinline__ void keep(double &k, uint32_t &x, double ko, uint32_t
     x = take ? xo : x;
 }
 
+// Bitonic sort of the (key, index) pairs held in registers: thread t of NT
+// holds positions t*E .. t*E+E-1 before and after.  Whole-workgroup call.
 template <int E, int NT>
-__device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *__restrict__ ed2,
-                                            const double *__restrict__ lbk, const double *__restrict__ lbeb,
-                                            const double *__restrict__ lbe, uint32_t *__restrict__ sk,
-                                            double *__restrict__ slbk, double *__restrict__ slbeb,
-                                            double *__restrict__ slbe, unsigned char *smem)
+__device__ __forceinline__ void sort_pairs(double (&k)[E], uint32_t (&x)[E], unsigned char *smem)
 {
     constexpr int npow = NT * E;
     double *key = reinterpret_cast<double *>(smem);
     uint32_t *idx = reinterpret_cast<uint32_t *>(key + npow);
     const int t = threadIdx.x;
-    const double *e2 = ed2 + q * n;
-    double k[E];
-    uint32_t x[E];
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int e = t * E + r;
-        k[r] = e < n ? e2[e] : __builtin_inf();
-        x[r] = e < n ? (uint32_t)e : 0xFFFFFFFFu;
-    }
     for (int size = 2; size <= npow; size <<= 1) {
         int stride = size >> 1;
         for (; stride >= WAVE * E; stride >>= 1) {        // across waves
@@ -186,6 +177,31 @@ __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *
             }
         }
     }
+}
+
+// Visiting order of one query of a set of n <= NT * E references, sorted on
+// chip, with the bounds gathered in that order.
+template <int E, int NT>
+__device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *__restrict__ ed2,
+                                            const double *__restrict__ lbk, const double *__restrict__ lbeb,
+                                            const double *__restrict__ lbe, uint32_t *__restrict__ sk,
+                                            double *__restrict__ slbk, double *__restrict__ slbeb,
+                                            double *__restrict__ slbe, unsigned char *smem)
+{
+    constexpr int npow = NT * E;
+    double *key = reinterpret_cast<double *>(smem);
+    uint32_t *idx = reinterpret_cast<uint32_t *>(key + npow);
+    const int t = threadIdx.x;
+    const double *e2 = ed2 + q * n;
+    double k[E];
+    uint32_t x[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int e = t * E + r;
+        k[r] = e < n ? e2[e] : __builtin_inf();
+        x[r] = e < n ? (uint32_t)e : 0xFFFFFFFFu;
+    }
+    sort_pairs<E, NT>(k, x, smem);
 #pragma unroll
     for (int r = 0; r < E; ++r) idx[t * E + r] = x[r];
     __syncthreads();
@@ -196,6 +212,89 @@ __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *
         slbk[o] = lbk[q * n + kk];
         slbeb[o] = lbeb[q * n + kk];
         slbe[o] = lbe[q * n + kk];
+    }
+}
+
+// ------------------------------------------------------- large reference sets
+// Above the on-chip size (8192 references) the visiting order is sorted in
+// chunks of 8192 on chip, then the sorted runs are merged pairwise in global
+// memory: an element's place in the merged run is its place in its own run
+// plus the number of elements of the other run that precede it, found by
+// binary search (the (key, index) pairs are all distinct, so the order is
+// total and every element lands on a distinct place).  Then the bounds are
+// gathered in the final order.
+constexpr int CHUNK_E = 8, CHUNK_NT = 1024, CHUNK = CHUNK_E * CHUNK_NT;
+
+__global__ void __launch_bounds__(CHUNK_NT)
+chunk_sort_kernel(int64_t n, int64_t nchunks, const double *__restrict__ ed2, double *__restrict__ kout,
+                  uint32_t *__restrict__ xout)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t q = blockIdx.x / nchunks, c = blockIdx.x % nchunks;
+    const int64_t c0 = c * CHUNK;
+    const int64_t len = (n - c0) < CHUNK ? (n - c0) : CHUNK;
+    const int t = threadIdx.x;
+    double k[CHUNK_E];
+    uint32_t x[CHUNK_E];
+#pragma unroll
+    for (int r = 0; r < CHUNK_E; ++r) {
+        const int e = t * CHUNK_E + r;
+        k[r] = e < len ? ed2[q * n + c0 + e] : __builtin_inf();
+        x[r] = e < len ? (uint32_t)(c0 + e) : 0xFFFFFFFFu;
+    }
+    sort_pairs<CHUNK_E, CHUNK_NT>(k, x, smem);
+#pragma unroll
+    for (int r = 0; r < CHUNK_E; ++r) {
+        const int e = t * CHUNK_E + r;
+        if (e < len) {
+            kout[q * n + c0 + e] = k[r];
+            xout[q * n + c0 + e] = x[r];
+        }
+    }
+}
+
+// One merge pass over runs of w sorted elements per query: runs 2j and 2j+1
+// become one sorted run of up to 2w.  One thread per element.
+__global__ void __launch_bounds__(256)
+merge_pass_kernel(int64_t nQ, int64_t n, int64_t w, const double *__restrict__ kin, const uint32_t *__restrict__ xin,
+                  double *__restrict__ kout, uint32_t *__restrict__ xout)
+{
+    const int64_t total = nQ * n;
+    for (int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x; id < total; id += (int64_t)gridDim.x * 256) {
+        const int64_t q = id / n, g = id - q * n;
+        const int64_t run = g / w, rs = run * w, ps = (run & ~(int64_t)1) * w;
+        const bool first = (run & 1) == 0;
+        const int64_t os = first ? ps + w : ps;                       // the other run
+        const int64_t oe = first ? (ps + 2 * w < n ? ps + 2 * w : n) : ps + w;
+        const double km = kin[id];
+        const uint32_t xm = xin[id];
+        int64_t lo = 0, hi = oe > os ? oe - os : 0;                   // count of the other run before (km, xm)
+        const double *ko = kin + q * n + os;
+        const uint32_t *xo = xin + q * n + os;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (key_gt(km, xm, ko[mid], xo[mid])) lo = mid + 1;
+            else hi = mid;
+        }
+        const int64_t out = q * n + ps + (g - rs) + lo;
+        kout[out] = km;
+        xout[out] = xm;
+    }
+}
+
+// The bounds in visiting order, from the sorted indices.
+__global__ void __launch_bounds__(256)
+gather_bounds_kernel(int64_t nQ, int64_t n, const uint32_t *__restrict__ sk, const double *__restrict__ lbk,
+                     const double *__restrict__ lbeb, const double *__restrict__ lbe, double *__restrict__ slbk,
+                     double *__restrict__ slbeb, double *__restrict__ slbe)
+{
+    const int64_t total = nQ * n;
+    for (int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x; id < total; id += (int64_t)gridDim.x * 256) {
+        const int64_t q = id / n;
+        const int64_t src = q * n + sk[id];
+        slbk[id] = lbk[src];
+        slbeb[id] = lbeb[src];
+        slbe[id] = lbe[src];
     }
 }
 
@@ -290,10 +389,44 @@ int launch_cells_prefix(int L, int Wp, uint32_t *prefix, hipStream_t st)
     return NNDTW_OK;
 }
 
+// Visiting order of more than CHUNK references: sorted chunks, merge passes
+// and the gather.  The key and index runs ping-pong between (slbk, sk) and
+// (slbeb, slbe viewed as uint32): both are rewritten by the gather at the
+// end, which reads the final indices from sk (so the chunks are sorted into
+// the buffer that the last merge pass leaves in sk).
+static int launch_order_large(int64_t n, int64_t nQ, const double *ed2, const double *lbk, const double *lbeb,
+                              const double *lbe, uint32_t *sk, double *slbk, double *slbeb, double *slbe, int L,
+                              int Wp, uint32_t *prefix, hipStream_t st)
+{
+    const int64_t nchunks = ceil_div(n, CHUNK);
+    int passes = 0;
+    while (((int64_t)CHUNK << passes) < n) ++passes;
+    double *kb[2] = {slbk, slbeb};
+    uint32_t *xb[2] = {sk, reinterpret_cast<uint32_t *>(slbe)};
+    int cur = passes & 1;                                    // after `passes` swaps the runs are in buffer 0
+    if (nchunks * nQ > 0x7FFFFFFFLL) return fail(NNDTW_EUNSUP, "visiting-order sort: too many chunks");
+    const size_t lds = (size_t)CHUNK * 12;
+    hipLaunchKernelGGL(chunk_sort_kernel, dim3((unsigned)(nchunks * nQ)), dim3(CHUNK_NT), lds, st, n, nchunks, ed2,
+                       kb[cur], xb[cur]);
+    NNDTW_LAUNCH_CHECK("chunk sort kernel launch");
+    const int64_t blocks = std::min<int64_t>(ceil_div(nQ * n, 256), 256 * 64);
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(merge_pass_kernel, dim3((unsigned)blocks), dim3(256), 0, st, nQ, n, (int64_t)CHUNK << p,
+                           kb[cur], xb[cur], kb[cur ^ 1], xb[cur ^ 1]);
+        NNDTW_LAUNCH_CHECK("merge pass kernel launch");
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(gather_bounds_kernel, dim3((unsigned)blocks), dim3(256), 0, st, nQ, n, sk, lbk, lbeb, lbe,
+                       slbk, slbeb, slbe);
+    NNDTW_LAUNCH_CHECK("gather kernel launch");
+    return launch_cells_prefix(L, Wp, prefix, st);
+}
+
 static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *lbk, const double *lbeb,
                         const double *lbe, uint32_t *sk, double *slbk, double *slbeb, double *slbe, int L, int Wp,
                         uint32_t *prefix, hipStream_t st)
 {
+    if (n > CHUNK) return launch_order_large(n, nQ, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, L, Wp, prefix, st);
     const int Wd = order_width(n);
     const size_t lds = (size_t)ORDER_THREADS * Wd * 12;
     switch (Wd) {
@@ -673,7 +806,15 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     // at least one pair of series per wave, hence a round of at least one
     // candidate (the search divides positions by R)
     if (P < 1) return fail(NNDTW_EUNSUP, "no DTW engine shape for W=%d with %d pairs per lane", rs->W, C);
-    const int NW = o->waves > 0 ? o->waves : SEARCH_DEFAULT_WAVES;
+    // Waves per query: a query's rounds are a chain of dependent steps, so the
+    // kernel lasts as long as its most expensive query (on the 5000 x 500,
+    // L=512 workload one query does 3.7 times the mean work).  When the
+    // queries do not fill the device at 4 waves each, each gets 8.
+    int NW = o->waves;
+    if (NW <= 0) {
+        const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
+        NW = (!batched && o->nq_hint > 0 && o->nq_hint <= 2 * (int64_t)cu) ? 8 : SEARCH_DEFAULT_WAVES;
+    }
     // Default round: two candidates per group, so that groups whose
     // candidate is abandoned early take another one within the round, and
     // at least 256: each round is a serial step of the query (threshold,

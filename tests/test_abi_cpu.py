@@ -35,7 +35,7 @@ def test_header_constants_match_binding():
     text = open(HEADER).read()
     defs = dict(re.findall(r"#define\s+(NNDTW_\w+)\s+(\S+)", text))
     assert int(defs["NNDTW_MAX_L"]) == nd.MAX_L
-    assert int(defs["NNDTW_SEARCH_MAX_N"]) == nd.SEARCH_MAX_N
+    assert int(defs["NNDTW_BATCH_MAX_N"]) == nd.BATCH_MAX_N
     assert int(defs["NNDTW_SEARCH_MAX_WAVES"]) == nd.SEARCH_MAX_WAVES
     for name, v in nd.CASCADES.items():
         assert int(defs["NNDTW_CASCADE_" + name.upper()]) == v
@@ -56,7 +56,8 @@ def test_struct_layouts():
     assert nd._Refset.B.offset == 32
     assert ctypes.sizeof(nd._SearchOpts) == 64
     assert nd._SearchOpts.eps.offset == 16 and nd._SearchOpts.events.offset == 32
-    assert nd._SearchOpts.waves.offset == 40 and nd._SearchOpts.reserved.offset == 48
+    assert nd._SearchOpts.waves.offset == 40 and nd._SearchOpts.nq_hint.offset == 48
+    assert nd._SearchOpts.reserved.offset == 56
 
 
 def _err(status, fragment):
@@ -142,10 +143,6 @@ def test_refset_and_search_validation():
                                  nbytes.value, NULL), "R=-1") == nd.EINVAL
     assert _err(lib.nndtw_search(ctypes.byref(desc), FAKE, 10, ctypes.byref(opts), FAKE, FAKE, NULL, FAKE,
                                  nbytes.value - 1, NULL), "workspace too small") == nd.EINVAL
-    big = nd._Refset()
-    big.magic, big.L, big.n, big.W = nd.REFSET_MAGIC, 64, nd.SEARCH_MAX_N + 1, 6
-    assert _err(lib.nndtw_search(ctypes.byref(big), FAKE, 10, ctypes.byref(opts), FAKE, FAKE, NULL, FAKE,
-                                 1 << 40, NULL), "NNDTW_SEARCH_MAX_N") == nd.EUNSUP
     assert _err(lib.nndtw_cascade_bounds(ctypes.byref(desc), NULL, 10, 2, NULL, NULL, NULL, NULL, NULL),
                 "Q is NULL") == nd.EINVAL
 
@@ -283,3 +280,21 @@ def test_search_eps_floor():
         for eps in (0.0, -1.0, floor, 2 * floor, 0.5):
             opts = nd._opts(5, "keogh_enh", 0, eps, True, 0)
             assert lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)) == 0, (L, eps, nd.last_error())
+
+
+def test_search_plan_waves_default_follows_query_count():
+    """Default waves per query: 8 when the queries would not fill the device
+    at 4 waves each (at most twice the compute units; 256 when the device
+    cannot be queried), else 4; an explicit value is kept."""
+    lib = nd.lib()
+    d = nd._Refset()
+    d.magic, d.L, d.n, d.W = nd.REFSET_MAGIC, 512, 5000, 51
+    d.padl, d.ppitch = 4096, 16384
+    for hint, want in ((0, 4), (1, 8), (500, 8), (512, 8), (513, 4), (100000, 4)):
+        opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
+        opts.nq_hint = hint
+        assert lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)) == 0
+        assert opts.waves == want, (hint, opts.waves)
+    opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, 2)
+    opts.nq_hint = 10
+    assert lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)) == 0 and opts.waves == 2

@@ -48,7 +48,7 @@ def series(n, L, seed, kind="rw"):
 
 
 # ------------------------------------------------------------------ a1
-@pytest.mark.parametrize("L", [2, 3, 17, 64, 256, 511, 2048])
+@pytest.mark.parametrize("L", [2, 3, 17, 64, 129, 256, 511, 1000, 1024, 2048])
 def test_envelopes_bit_exact(L):
     B = series(37, L, seed=L)
     for W in sorted({0, 1, 2, 5, L // 10, L // 3, L - 2, L - 1, L, 4 * L}):
@@ -278,6 +278,24 @@ def test_search_reference_counts(n):
     refs = series(n, 24, seed=900 + n % 97, kind="sin5")
     queries = series(5, 24, seed=901, kind="sin5")
     check_search(refs, queries, 3, 2, "keogh_enh", 0, True, 0, brute=n <= 2049)
+
+
+@pytest.mark.parametrize("n", [8193, 16384, 16385, 40000])
+def test_search_large_reference_sets(n):
+    """Reference sets above the on-chip sort (8192): the visiting order is
+    sorted in chunks and merged; sizes around one, two and five chunks."""
+    refs = series(n, 24, seed=700 + n % 89, kind="sin5")
+    queries = series(6, 24, seed=701, kind="sin5")
+    for R in (0, 1000):
+        check_search(refs, queries, 3, 2, "keogh_enh", R, True, 0, brute=False)
+
+
+def test_search_hbm512_sampled():
+    """The 200,000 x 512 reference set (W=51, V=5) searched end to end: four
+    queries against the oracle at the same R."""
+    hb = synth.workload("nndtw-hbm512")
+    qs = np.ascontiguousarray(hb.queries[:4])
+    check_search(hb.refs, qs, 51, 5, "keogh_enh", 0, True, 0, brute=False)
 
 
 @pytest.mark.parametrize("waves", [1, 2, 3, 5, 8])

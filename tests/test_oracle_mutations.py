@@ -17,9 +17,13 @@ MUTATIONS = [
     ("envelope window one short", "hi = imin(L - 1, i + w);\n            float u", "hi = imin(L - 1, i + w - (w > 0));\n            float u"),
     ("dtw: diagonal predecessor dropped", "double m = dmin(dmin(prev[j - 1], cur[j - 1]), prev[j]);", "double m = dmin(cur[j - 1], prev[j]);"),
     ("dtw: band one too wide", "int lo = imax(1, i - w), hi = imin(L, i + w);", "int lo = imax(1, i - w - 1), hi = imin(L, i + w);"),
-    ("enh: transposed link in left band", "mL = dmin(mL, delta(A[j], B[i]));", "mL = dmin(mL, delta(A[j], B[j]));"),
-    ("enh: right band mirrored index off by one", "int rj = L - 1 - j;                    /* paper", "int rj = L - 2 - j;                    /* paper"),
-    ("enh: right corner dropped", "double res = delta(A[0], B[0]) + delta(A[L - 1], B[L - 1]);", "double res = delta(A[0], B[0]);"),
+    ("band set: transposed link in the right band", "rows[n] = q; cols[n] = i; ++n;", "rows[n] = q; cols[n] = q; ++n;"),
+    ("enh: right band at the wrong position", "double right = band_min(A, B, L, W, 1, L - 1 - k);",
+     "double right = band_min(A, B, L, W, 1, L - 2 - k);"),
+    ("enh: right corner dropped", "double res = band_min(A, B, L, W, 0, 0) + band_min(A, B, L, W, 1, L - 1);",
+     "double res = band_min(A, B, L, W, 0, 0);"),
+    ("enh: right band of the left position", "double right = band_min(A, B, L, W, 1, L - 1 - k);",
+     "double right = band_min(A, B, L, W, 0, L - 1 - k);"),
     ("enh: n_bands not clamped", "static int n_bands_of(int L, int V) { return imin(L / 2, V); }", "static int n_bands_of(int L, int V) { return V; }"),
     ("enh: keogh middle starts one late", "for (int i = nb; i < L - nb; ++i) res += keogh_term", "for (int i = nb + 1; i < L - nb; ++i) res += keogh_term"),
     ("eq7: left/right switch point", "else if (i >= L - nb)  s += band_min", "else if (i > L - nb)  s += band_min"),
