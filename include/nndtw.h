@@ -55,8 +55,11 @@ extern "C" {
 /* Largest reference set of one set of the batched search (its visiting
  * order is sorted on chip).  nndtw_search takes any reference set. */
 #define NNDTW_BATCH_MAX_N 8192
-/* Largest number of waves (workgroup of 64-lane waves) one query may use. */
-#define NNDTW_SEARCH_MAX_WAVES 8
+/* Largest number of waves (workgroup of 64-lane waves) one query may use.
+ * Above 8 waves only engine shapes that fit 128 registers per lane qualify
+ * (windows of up to 63 diagonal pairs with up to 6 pairs per lane);
+ * nndtw_search_plan / nndtw_search return EUNSUP for the others. */
+#define NNDTW_SEARCH_MAX_WAVES 16
 
 /* Lower-bound cascades for nndtw_search. */
 #define NNDTW_CASCADE_NONE      0  /* DTW_W of every candidate (with abandon)        */

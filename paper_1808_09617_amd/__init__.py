@@ -26,7 +26,7 @@ COUNT_NAMES = ("n", "pruned_keogh", "pruned_enh_bands", "pruned_enh", "dtw_start
                "dtw_abandoned", "cells", "fp64_rechecks")
 MAX_L = 2048
 BATCH_MAX_N = 8192
-SEARCH_MAX_WAVES = 8
+SEARCH_MAX_WAVES = 16
 SEARCH_SCRATCH_BYTES = 64 << 20
 REFSET_MAGIC = 0x4E444157
 

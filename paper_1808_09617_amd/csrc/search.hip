@@ -46,7 +46,8 @@ namespace nndtw {
 constexpr int SEARCH_MAX_CPL = 9;
 
 constexpr int QCAP = 512;        // survivor ring (>= the largest batch + one chunk of 64)
-constexpr int SEARCH_MAX_WAVES = NNDTW_SEARCH_MAX_WAVES;
+constexpr int SEARCH_MAX_WAVES = 8;        // workgroup size of the search kernels (waves)
+constexpr int SEARCH_WIDE_WAVES = NNDTW_SEARCH_MAX_WAVES;   // ... of the wide ones
 constexpr int SEARCH_DEFAULT_WAVES = 4;
 constexpr int ORDER_THREADS = 256;
 
@@ -487,7 +488,10 @@ __device__ __forceinline__ int stage_of(int cascade, double b1, double b2, doubl
 // on identical values (the scan, the thresholds, the record); only wave 0
 // writes shared LDS state and counts.  Staging and DTW tasks are spread over
 // all waves (tasks dealt from an LDS counter).
-template <int C, bool EXACT>
+// RK: which FP64 recheck engine the code holds: 1 one diagonal pair per lane
+// (windows of up to 63 pairs), 2 the FP32 engine's C pairs per lane, 0 both
+// (chosen at run time).  A kernel holding one of them needs fewer registers.
+template <int C, bool EXACT, int RK = 0>
 __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t q, unsigned char *smem)
 {
     const EngineGeom &geo = a.geo, &geoD = a.geoD;
@@ -608,7 +612,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                 // waves of other workgroups sharing the SIMD do not stretch
                 // this query's critical path
                 __builtin_amdgcn_s_setprio(3);
-                if (C > 1 && geoD.C == 1) {
+                if (RK == 1 || (RK == 0 && C > 1 && geoD.C == 1)) {
                     // one pair per lane: rows start C - 1 elements later
                     constexpr int D1 = recheck_prefetch(1), M1 = recheck_window(1);
                     engine_run<double, 1, D1, M1, true>(
@@ -710,12 +714,33 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     }
 }
 
-template <int C, bool EXACT>
-__global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES) search_kernel(SearchArgs a)
+// Kernels whose registers allow it (no scratch spill) are held to 128 VGPRs,
+// so that two workgroups of 8 waves (a query each) share a compute unit:
+// 512 queries run at once instead of 256, and a query with much more work
+// than the others does not start late.  With the one-pair FP64 recheck
+// (windows of up to 63 pairs) that holds up to 6 pairs per lane.
+template <int C, bool EXACT, int RK>
+__global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES)
+    __attribute__((amdgpu_waves_per_eu((C <= 3 || (RK == 1 && C <= 6)) ? 4 : 1)))
+search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    search_query<C, EXACT>(a, blockIdx.x, smem);
+    search_query<C, EXACT, RK>(a, blockIdx.x, smem);
 }
+
+// Up to 16 waves per query for the shapes with the one-pair FP64 recheck
+// and at most 6 pairs per lane (128 VGPRs): an expensive query's rounds run
+// on twice the groups of lanes.
+template <int C, bool EXACT>
+__global__ void __launch_bounds__(WAVE * SEARCH_WIDE_WAVES) __attribute__((amdgpu_waves_per_eu(4)))
+search_kernel_wide(SearchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    search_query<C, EXACT, C == 1 ? 2 : 1>(a, blockIdx.x, smem);
+}
+
+// Whether a plan may use more than SEARCH_MAX_WAVES waves (search_kernel_wide).
+static bool wide_ok(int C, int Wp) { return C <= 6 && recheck_cpl(Wp, C) == 1; }
 
 // The search of a batch: persistent workgroups take (set, query) items of
 // one engine shape (C, EXACT) from that shape's counter in the batch header,
@@ -810,17 +835,28 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     // kernel lasts as long as its most expensive query (on the 5000 x 500,
     // L=512 workload one query does 3.7 times the mean work).  When the
     // queries do not fill the device at 4 waves each, each gets 8.
+    // When the queries do not fill the device at 4 waves each, each gets 8,
+    // or 16 where the shape fits 128 VGPRs (5000 x 500, L=512, W=51: search
+    // kernel 5.1 ms at 4 waves, 3.3 ms at 8, 2.5 ms at 16).
     int NW = o->waves;
     if (NW <= 0) {
         const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
-        NW = (!batched && o->nq_hint > 0 && o->nq_hint <= 2 * (int64_t)cu) ? 8 : SEARCH_DEFAULT_WAVES;
+        const bool few = !batched && o->nq_hint > 0 && o->nq_hint <= 2 * (int64_t)cu;
+        NW = few ? (wide_ok(C, Wp) ? SEARCH_WIDE_WAVES : 8) : SEARCH_DEFAULT_WAVES;
     }
+    if (NW > SEARCH_MAX_WAVES && (batched || !wide_ok(C, Wp)))
+        return fail(NNDTW_EUNSUP, "waves=%d: more than %d waves per query need a window of at most 63 diagonal "
+                                  "pairs and at most 6 pairs per lane (W=%d, %d pairs per lane)%s",
+                    NW, SEARCH_MAX_WAVES, rs->W, C, batched ? "; the batched search takes at most 8" : "");
     // Default round: two candidates per group, so that groups whose
     // candidate is abandoned early take another one within the round, and
     // at least 256: each round is a serial step of the query (threshold,
     // DTWs, FP64 recheck), and below that the chain of rounds cost more
     // than the extra DTWs a larger round starts on the measured workloads.
-    const int64_t R = o->R > 0 ? o->R : (2 * P * NW > 256 ? 2 * P * NW : 256);
+    // (With more than 8 waves a round of 512 measured faster: 3.40 -> 3.29 ms
+    // for the search on the workload above.)
+    int64_t R = o->R > 0 ? o->R : (2 * P * NW > 256 ? 2 * P * NW : 256);
+    if (o->R <= 0 && NW > SEARCH_MAX_WAVES && R < 512) R = 512;
     // Candidates per FP32 batch: the round, up to 256, so that a round of
     // the default size is one batch (every batch ends waiting for its
     // longest DTW); up to 64 FP64 rechecks per engine call.  Only the query
@@ -929,13 +965,38 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     a.counts = counts;
     a.ncu = device_cu_count();
     const size_t lds = plan.lds_bytes;
-    switch (plan.C) {
-#define X(c)                                                                                       \
-    case c:                                                                                        \
-        if (plan.exact)                                                                            \
-            hipLaunchKernelGGL((search_kernel<c, true>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a); \
-        else                                                                                       \
-            hipLaunchKernelGGL((search_kernel<c, false>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a); \
+    if (plan.NW > SEARCH_MAX_WAVES) {
+        switch (plan.C * 2 + (plan.exact ? 1 : 0)) {
+#define X(c)                                                                                                    \
+    case c * 2:                                                                                                 \
+        hipLaunchKernelGGL((search_kernel_wide<c, false>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a); \
+        break;                                                                                                  \
+    case c * 2 + 1:                                                                                             \
+        hipLaunchKernelGGL((search_kernel_wide<c, true>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);  \
+        break;
+            X(1) X(2) X(3) X(4) X(6)
+#undef X
+        default:
+            return fail(NNDTW_EUNSUP, "no wide search kernel for %d pairs per lane", plan.C);
+        }
+        NNDTW_LAUNCH_CHECK("search kernel launch");
+        return mark(4);
+    }
+    // the FP64 recheck engine the kernel holds (see search_query)
+    const bool rk1 = plan.C > 1 && a.geoD.C == 1;
+    switch (plan.C * 4 + (plan.exact ? 2 : 0) + (rk1 ? 1 : 0)) {
+#define X(c)                                                                                                       \
+    case c * 4 + 0:                                                                                                \
+        hipLaunchKernelGGL((search_kernel<c, false, 2>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);   \
+        break;                                                                                                     \
+    case c * 4 + 1:                                                                                                \
+        hipLaunchKernelGGL((search_kernel<c, false, 1>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);   \
+        break;                                                                                                     \
+    case c * 4 + 2:                                                                                                \
+        hipLaunchKernelGGL((search_kernel<c, true, 2>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);    \
+        break;                                                                                                     \
+    case c * 4 + 3:                                                                                                \
+        hipLaunchKernelGGL((search_kernel<c, true, 1>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);    \
         break;
         NNDTW_FOR_EACH_CPL(X)
 #undef X

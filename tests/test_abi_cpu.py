@@ -283,18 +283,28 @@ def test_search_eps_floor():
 
 
 def test_search_plan_waves_default_follows_query_count():
-    """Default waves per query: 8 when the queries would not fill the device
-    at 4 waves each (at most twice the compute units; 256 when the device
-    cannot be queried), else 4; an explicit value is kept."""
+    """Default waves per query: when the queries would not fill the device at
+    4 waves each (at most twice the compute units; 256 when the device cannot
+    be queried) 16 for shapes that fit 128 VGPRs (at most 63 diagonal pairs,
+    at most 6 pairs per lane), else 8; with more queries 4.  More than 8 waves
+    take a default round of at least 512.  An explicit value is kept, and
+    more than 8 waves for a shape that does not fit is EUNSUP."""
     lib = nd.lib()
     d = nd._Refset()
     d.magic, d.L, d.n, d.W = nd.REFSET_MAGIC, 512, 5000, 51
     d.padl, d.ppitch = 4096, 16384
-    for hint, want in ((0, 4), (1, 8), (500, 8), (512, 8), (513, 4), (100000, 4)):
+    for hint, want in ((0, 4), (1, 16), (500, 16), (512, 16), (513, 4), (100000, 4)):
         opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
         opts.nq_hint = hint
         assert lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)) == 0
         assert opts.waves == want, (hint, opts.waves)
+        assert opts.R == (512 if want == 16 else 256), (hint, opts.R)
+    d.W = 128                                   # 129 diagonal pairs: the 8-wave kernels
+    opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
+    opts.nq_hint = 500
+    assert lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)) == 0 and opts.waves == 8
+    opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, 12)
+    assert _err(lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)), "more than 8 waves") == nd.EUNSUP
     opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, 2)
     opts.nq_hint = 10
     assert lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)) == 0 and opts.waves == 2

@@ -298,7 +298,7 @@ def test_search_hbm512_sampled():
     check_search(hb.refs, qs, 51, 5, "keogh_enh", 0, True, 0, brute=False)
 
 
-@pytest.mark.parametrize("waves", [1, 2, 3, 5, 8])
+@pytest.mark.parametrize("waves", [1, 2, 3, 5, 8, 12, 16])
 def test_search_waves_per_query(waves):
     """Every workgroup size gives the oracle's result and counts (the waves of
     a query share its DTW tasks)."""
