@@ -43,6 +43,22 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+SAN_LIB = os.path.join(HERE, "_nndtw_oracle_san.so")
+
+
+def build_sanitized() -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc, every undefined-behaviour report fatal), for the CPU test that runs
+    the pins against it.  Loading it needs the ASan runtime preloaded."""
+    tmp = SAN_LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-o", tmp, SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 _lib = None
 
 

@@ -16,7 +16,9 @@ import os
 import torch
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libnndtw.so")
+# NNDTW_LIB selects another build of the same library (the host-sanitized
+# build of the CPU sanitizer test); the default is the in-tree build.
+LIB_PATH = os.environ.get("NNDTW_LIB") or os.path.join(PKG, "libnndtw.so")
 
 OK, EINVAL, EHIP, EUNSUP = 0, -1, -2, -3
 CROSS, ZIP = 0, 1

@@ -105,6 +105,37 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_sanitized(out: str) -> str:
+    """A build of the library whose host code (argument validation, planning,
+    launch sequencing: api.hip and the host halves of the launchers) is
+    instrumented with AddressSanitizer and UndefinedBehaviorSanitizer; the
+    device code is the same.  For the CPU sanitizer test, which loads it with
+    clang's ASan runtime preloaded."""
+    san = os.path.join(BUILD, "san")
+    os.makedirs(san, exist_ok=True)
+    flags = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+    def comp(src):
+        obj = os.path.join(san, os.path.basename(src) + ".o")
+        cuid = "nndtw_" + os.path.splitext(os.path.basename(src))[0]
+        cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), f"-cuid={cuid}", *flags, "-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+        return obj
+
+    srcs = sources()
+    jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
+    with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        objs = list(ex.map(comp, srcs))
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *flags, "-o", out, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
