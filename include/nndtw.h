@@ -352,7 +352,7 @@ int nndtw_cascade_bounds(const nndtw_refset *refset, const float *Q, int64_t nQ,
  * cross, nA zip): four bits per (anti-diagonal pair, window diagonal pair)
  * of each series pair and padded copies of A and B (codes: 256-byte
  * aligned device memory).  EUNSUP for
- * min(W, L-1) + 1 > 756. */
+ * min(W, L-1) + 1 > 756; the FP64 calls take min(W, L-1) + 1 <= 567. */
 int nndtw_dtw_codes_bytes(int64_t nA, int64_t nB, int32_t L, int32_t W, int32_t pairing,
                           size_t *bytes);
 
@@ -364,9 +364,13 @@ int nndtw_dtw_w_codes(const float *A, int64_t nA, const float *B, int64_t nB, in
 
 /* Backward: gA[a][i] = sum over the pairs (a, b) of gout[pair] * dDTW/dA_a[i]
  * (cross: gout [nA][nB]; zip: gout [nA]), from the codes of the forward call
- * with the same A, B, L, W, pairing and f64.  gA: device [nA][L].  With
- * cross pairing the sum over references runs in an unspecified order (the
- * last bits of FP32 results may vary between runs). */
+ * with the same A, B, L, W, pairing and f64.  gA: device [nA][L].  Each
+ * path's terms are summed per row i along the path, then the per-reference
+ * row sums in ascending reference order, so results are the same from run
+ * to run.  With cross pairing the backward writes the per-pair
+ * row sums into the part of the codes buffer after the codes (L values per
+ * series pair; the codes themselves are only read): backward calls on one
+ * buffer must not overlap. */
 int nndtw_dtw_w_backward(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L,
                          int32_t W, int32_t pairing, int32_t f64, const void *gout,
                          const uint8_t *codes, size_t codes_bytes, void *gA, void *stream);

@@ -13,10 +13,13 @@
 //      words of 8 super-steps (one store per 8 super-steps and slot);
 //   2. backtrack: from (L-1, L-1) the recorded predecessors lead back to
 //      (0, 0); every cell adds gout * 2 (A_i - B_j) to the query's gradient.
-//      Cross pairing: one workgroup per query, its threads walk the paths of
-//      different references and add into an LDS row with atomics (the order
-//      of the additions, hence the last bits of an FP32 sum, varies from run
-//      to run); zip pairing: one thread per pair.
+//      One thread per pair sums its path's terms per row i (a path visits
+//      the rows in order).  Cross pairing: the row sums are stored per pair
+//      and a second kernel adds them per (query, i) in ascending reference
+//      order, so the sums always run in the same order and the result is the
+//      same from run to run.  Zip pairing: the row sums are the gradient.
+#include <algorithm>
+
 #include "dtw_engine.hpp"
 
 namespace nndtw {
@@ -33,7 +36,7 @@ struct CodesGeom {
     int padl;
     int64_t ppitch;      // floats per padded row
     int64_t pitch;       // code words per series pair
-    size_t offA, offB, offC, total;
+    size_t offA, offB, offC, offP, total;
 };
 
 // Prefetch distance and block length (a multiple of 8): FP32 fills a block
@@ -50,7 +53,10 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 int codes_geom(int64_t nA, int64_t nB, int L, int W, int pairing, bool f64, CodesGeom *cg)
 {
     const int Wp = W < L - 1 ? W : L - 1;
-    const int C = choose_cpl(Wp, 4, 0, 12);
+    // FP64 cells need twice the registers: up to 9 pairs per lane (windows of
+    // up to 567 diagonal pairs) fit without spilling to scratch memory, FP32
+    // up to 12 (756)
+    const int C = choose_cpl(Wp, 4, 0, f64 ? 9 : 12);
     if (C < 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
     cg->g = make_geom(L, W, C, codes_prefetch(f64, C), codes_window(f64, C));
     if (cg->g.P < 1) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
@@ -69,6 +75,8 @@ int codes_geom(int64_t nA, int64_t nB, int L, int W, int pairing, bool f64, Code
     cg->offA = o; o = al256(o + (size_t)nA * cg->ppitch * 4);
     cg->offB = o; o = al256(o + (size_t)nB * cg->ppitch * 4);
     cg->offC = o; o = al256(o + (size_t)np * cg->pitch * 4);
+    // cross backward: every pair's path sums per row, [nA][nB][L]
+    cg->offP = o; o = al256(o + (pairing ? 0 : (size_t)np * L * (f64 ? 8 : 4)));
     cg->total = o;
     return NNDTW_OK;
 }
@@ -121,7 +129,8 @@ dtw_codes_kernel(EngineGeom geo, int K, int64_t np, int64_t nB, int pairing, con
 }
 
 // Walk back one pair's path, calling add(i, j) for every cell from (L-1,L-1)
-// to (0,0).  The bounds tests only guard memory against corrupt codes.
+// to (0,0) (i never increases).  The bounds tests only guard memory against
+// corrupt codes.
 template <typename Add>
 __device__ __forceinline__ void walk_path(const EngineGeom &geo, const uint32_t *__restrict__ codes, Add add)
 {
@@ -159,7 +168,7 @@ template <typename T>
 __global__ void __launch_bounds__(BT_THREADS)
 dtw_backtrack_kernel(EngineGeom geo, const float *__restrict__ A, int64_t nA, const float *__restrict__ B,
                      int64_t nB, int pairing, const T *__restrict__ gout, const uint32_t *__restrict__ codes,
-                     int64_t cpitch, T *__restrict__ gA)
+                     int64_t cpitch, T *__restrict__ gA, T *__restrict__ rowsums)
 {
     const int L = geo.L;
     if (pairing) {
@@ -172,27 +181,52 @@ dtw_backtrack_kernel(EngineGeom geo, const float *__restrict__ A, int64_t nA, co
         walk_path(geo, codes + k * cpitch, [&](int i, int j) { g[i] += w * ((T)2 * ((T)a[i] - (T)b[j])); });
         return;
     }
-    extern __shared__ __align__(16) unsigned char smem[];
-    T *acc = reinterpret_cast<T *>(smem);
-    const int64_t q = blockIdx.x;
-    const float *a = A + q * L;
-    for (int i = threadIdx.x; i < L; i += BT_THREADS) acc[i] = (T)0;
-    __syncthreads();
-    for (int64_t r = threadIdx.x; r < nB; r += BT_THREADS) {
-        const float *b = B + r * L;
-        const T w = gout[q * nB + r];
-        walk_path(geo, codes + (q * nB + r) * cpitch,
-                  [&](int i, int j) { atomicAdd(&acc[i], w * ((T)2 * ((T)a[i] - (T)b[j]))); });
+    // cross pairing: one thread per (query, reference) pair sums its path's
+    // terms per row i (a path visits the rows in order) and stores the row
+    // sums rs[q][r][i]; the combine kernel adds them in reference order
+    // (stored as rs[q][i][r]: the threads of a wave, walking neighbouring
+    // references' paths at about the same row, store to neighbouring words)
+    const int64_t p = (int64_t)blockIdx.x * BT_THREADS + threadIdx.x;
+    if (p >= nA * nB) return;
+    const int64_t q = p / nB, r = p - q * nB;
+    const float *a = A + q * L, *b = B + r * L;
+    const T w = gout[p];
+    T *col = rowsums + q * L * nB + r;
+    int cur = L - 1;
+    T sum = (T)0;
+    walk_path(geo, codes + p * cpitch, [&](int i, int j) {
+        if (i != cur) {
+            col[(int64_t)cur * nB] = sum;
+            cur = i;
+            sum = (T)0;
+        }
+        sum += w * ((T)2 * ((T)a[i] - (T)b[j]));
+    });
+    col[(int64_t)cur * nB] = sum;
+}
+
+// gA[q][i] = the pairs' row sums rs[q][i][r] added in ascending reference order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+dtw_backward_combine_kernel(int64_t nA, int64_t nB, int L, const T *__restrict__ rowsums, T *__restrict__ gA)
+{
+    const int64_t total = nA * L;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const T *src = rowsums + e * nB;       // rs[q][i][0 .. nB-1]
+        T s = (T)0;
+        for (int64_t r = 0; r < nB; ++r) s += src[r];
+        gA[e] = s;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < L; i += BT_THREADS) gA[q * L + i] = acc[i];
 }
 
 size_t dtw_codes_bytes(int64_t nA, int64_t nB, int L, int W, int pairing)
 {
-    // the larger of the two precisions' layouts (they differ in T only)
+    // the larger of the two precisions' layouts (they differ in T only); a
+    // window wider than the FP64 kernels take is sized for FP32 (the FP64
+    // calls return EUNSUP for it)
     CodesGeom cg, cd;
-    if (codes_geom(nA, nB, L, W, pairing, false, &cg) || codes_geom(nA, nB, L, W, pairing, true, &cd)) return 0;
+    if (codes_geom(nA, nB, L, W, pairing, false, &cg)) return 0;
+    if (codes_geom(nA, nB, L, W, pairing, true, &cd)) return cg.total;
     return cg.total > cd.total ? cg.total : cd.total;
 }
 
@@ -224,8 +258,18 @@ static int launch_codes_t(const float *A, int64_t nA, const float *B, int64_t nB
         hipLaunchKernelGGL((dtw_codes_kernel<T, c, false>), dim3(blocks), dim3(WAVE * CODES_WAVES), lds, st, g, K, \
                            np, nB, pairing, Ap, Bp, cg.ppitch, cg.padl, out, codes, cg.pitch);                 \
         break;
-        X(1) X(2) X(3) X(4) X(6) X(8) X(9) X(12)
+        X(1) X(2) X(3) X(4) X(6) X(8) X(9)
 #undef X
+    case 12 * 2 + 1:
+        if (sizeof(T) == 8) return fail(NNDTW_EUNSUP, "FP64 codes: no engine for 12 pairs per lane");
+        hipLaunchKernelGGL((dtw_codes_kernel<float, 12, true>), dim3(blocks), dim3(WAVE * CODES_WAVES), lds, st, g,
+                           K, np, nB, pairing, Ap, Bp, cg.ppitch, cg.padl, (float *)out, codes, cg.pitch);
+        break;
+    case 12 * 2:
+        if (sizeof(T) == 8) return fail(NNDTW_EUNSUP, "FP64 codes: no engine for 12 pairs per lane");
+        hipLaunchKernelGGL((dtw_codes_kernel<float, 12, false>), dim3(blocks), dim3(WAVE * CODES_WAVES), lds, st, g,
+                           K, np, nB, pairing, Ap, Bp, cg.ppitch, cg.padl, (float *)out, codes, cg.pitch);
+        break;
     default:
         return fail(NNDTW_EUNSUP, "no DTW engine for %d pairs per lane", g.C);
     }
@@ -247,15 +291,27 @@ int launch_dtw_backward(bool f64, const float *A, int64_t nA, const float *B, in
     CodesGeom cg;
     if (int r = codes_geom(nA, nB, L, W, pairing, f64, &cg)) return r;
     const uint32_t *cw = (const uint32_t *)(codes + cg.offC);
-    const unsigned blocks = (unsigned)(pairing ? ceil_div(nA, BT_THREADS) : nA);
-    const size_t lds = pairing ? 0 : (size_t)L * (f64 ? 8 : 4);
+    const int64_t np = pairing ? nA : nA * nB;
+    if (ceil_div(np, BT_THREADS) > 0x7FFFFFFFLL) return fail(NNDTW_EUNSUP, "backward: too many series pairs");
+    const unsigned blocks = (unsigned)ceil_div(np, BT_THREADS);
+    uint8_t *rs = const_cast<uint8_t *>(codes) + cg.offP;
     if (f64)
-        hipLaunchKernelGGL(dtw_backtrack_kernel<double>, dim3(blocks), dim3(BT_THREADS), lds, st, cg.g, A, nA, B, nB,
-                           pairing, (const double *)gout, cw, cg.pitch, (double *)gA);
+        hipLaunchKernelGGL(dtw_backtrack_kernel<double>, dim3(blocks), dim3(BT_THREADS), 0, st, cg.g, A, nA, B, nB,
+                           pairing, (const double *)gout, cw, cg.pitch, (double *)gA, (double *)rs);
     else
-        hipLaunchKernelGGL(dtw_backtrack_kernel<float>, dim3(blocks), dim3(BT_THREADS), lds, st, cg.g, A, nA, B, nB,
-                           pairing, (const float *)gout, cw, cg.pitch, (float *)gA);
+        hipLaunchKernelGGL(dtw_backtrack_kernel<float>, dim3(blocks), dim3(BT_THREADS), 0, st, cg.g, A, nA, B, nB,
+                           pairing, (const float *)gout, cw, cg.pitch, (float *)gA, (float *)rs);
     NNDTW_LAUNCH_CHECK("dtw backtrack kernel launch");
+    if (!pairing) {
+        const int64_t cb = std::min<int64_t>(ceil_div((int64_t)nA * L, 256), 65536);
+        if (f64)
+            hipLaunchKernelGGL(dtw_backward_combine_kernel<double>, dim3((unsigned)cb), dim3(256), 0, st, nA, nB, L,
+                               (const double *)rs, (double *)gA);
+        else
+            hipLaunchKernelGGL(dtw_backward_combine_kernel<float>, dim3((unsigned)cb), dim3(256), 0, st, nA, nB, L,
+                               (const float *)rs, (float *)gA);
+        NNDTW_LAUNCH_CHECK("dtw backward combine kernel launch");
+    }
     return NNDTW_OK;
 }
 

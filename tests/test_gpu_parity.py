@@ -604,6 +604,33 @@ def test_dtw_backward_full_config():
     assert np.all(np.abs(oz[~same] - odz[~same]) <= 4 * oracle.slack(L) * odz[~same])
 
 
+def test_dtw_backward_deterministic():
+    """The cross backward sums in a fixed order: two runs (and a run with the
+    codes recomputed) give bit-identical gradients, FP32 and FP64, and L=1000
+    (chunks of fewer references than threads) matches the FP64 oracle."""
+    L, W = 256, 26
+    A = series(5, L, seed=4100, kind="sin5")
+    B = series(300, L, seed=4101, kind="sin5")
+    g = np.random.default_rng(9).standard_normal((5, 300))
+    for f64 in (False, True):
+        say("backward deterministic", f64)
+        out, codes = nd.dtw_w_codes(dev(A), dev(B), W, f64=f64)
+        gt = torch.from_numpy(g).to(DEV)
+        g1 = host(nd.dtw_w_backward(dev(A), dev(B), W, gt, codes, f64=f64))
+        g2 = host(nd.dtw_w_backward(dev(A), dev(B), W, gt, codes, f64=f64))
+        _, codes2 = nd.dtw_w_codes(dev(A), dev(B), W, f64=f64)
+        g3 = host(nd.dtw_w_backward(dev(A), dev(B), W, gt, codes2, f64=f64))
+        assert np.array_equal(g1, g2) and np.array_equal(g1, g3)
+    L, W = 1000, 100
+    A = series(2, L, seed=4102)
+    B = series(40, L, seed=4103)
+    w = np.random.default_rng(10).standard_normal((2, 40))
+    out, codes = nd.dtw_w_codes(dev(A), dev(B), W, f64=True)
+    g64 = host(nd.dtw_w_backward(dev(A), dev(B), W, torch.from_numpy(w).to(DEV), codes, f64=True))
+    og, _ = oracle.dtw_grad(A, B, W, gout=w)
+    assert np.allclose(g64, og, rtol=1e-10, atol=1e-10 * np.abs(og).max())
+
+
 # ------------------------------------------------------------------ serving
 def test_serving_results_equal_alone():
     """Requests served in the mix (continuous batching on several streams)
