@@ -188,10 +188,16 @@ int nndtw_lb_enhanced_sym(const float *A, int64_t nA, const float *B, const floa
  *   D(i,j) = (A_i - B_j)^2 + min(D(i-1,j-1), D(i,j-1), D(i-1,j)),
  * result D(L,L) (un-rooted).  FP32 error is at most gamma_{2L+1} of float32
  * relative to the exact value.
+ * Any window W >= 0 at any length up to NNDTW_MAX_L: windows of up to
+ * 63 x 16 diagonal pairs covering less than 60 % of the L x L matrix run on
+ * the anti-diagonal engine, the others on a row-strip engine (each lane a
+ * strip of consecutive columns, rows pipelined across the lanes).
  * cutoff: NULL, or device double[nA]: the computation of a pair may stop
- * with +inf once every cell of two consecutive anti-diagonals exceeds
- * cutoff[a] (every warping path crosses them and costs only grow); a
- * finite result is always the full DTW_W (possibly above the cutoff).
+ * with +inf once every cell of a frontier that every warping path crosses
+ * exceeds cutoff[a] (two consecutive anti-diagonals; on the row-strip
+ * engine, the last computed row of every strip plus the cell that steps
+ * right out of it), since costs only grow along a path; a finite result is
+ * always the full DTW_W (possibly above the cutoff).
  * out: float (CROSS [nA][nB] / ZIP [nA]).
  */
 int nndtw_dtw_w(const float *A, int64_t nA, const float *B, int64_t nB, int32_t L,

@@ -25,6 +25,11 @@ CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off",                       # FP64 sums/products round exactly as written
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Task counters are advanced by whole-wave LDS atomics whose addend is
+    # non-zero in lane 0 only (so that no lane branch surrounds the deal):
+    # issue them as they are, not through a wave scan, which would hold
+    # whole-wave registers across the engines' register-bound loops.
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
     "-I", INCLUDE, "-I", CSRC,
 ]

@@ -87,6 +87,8 @@ int launch_compare_bounds(int what, const float *A, int64_t nA, const float *B, 
                           int pairing, double *out, hipStream_t s);
 size_t compare_lds_bytes(int L, int W);
 // dtw.hip
+// Whether the row-strip engine (strip_engine.hpp) serves window Wp at length L.
+bool strip_preferred(int L, int Wp);
 int launch_dtw_pairs(bool f64, const float *A, int64_t nA, const float *B, int64_t nB, int L,
                      int W, const double *cutoff, int pairing, void *out, hipStream_t s);
 // grad.hip

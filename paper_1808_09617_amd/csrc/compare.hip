@@ -199,8 +199,7 @@ compare_bounds_kernel(int what, const float *__restrict__ A, int64_t nA, const f
             bool skip = false;
             double k1 = 0.0;
             if (cutoff) {                       // second pass only if the first does not exceed the cutoff
-                if (lane == 0) k1 = ordered_sum(0.0, t1, 0, L);
-                k1 = __shfl(k1, 0);
+                k1 = ordered_sum(0.0, t1, 0, L);  // every lane (LDS broadcast reads): no lane branch
                 skip = k1 > cutoff[ia];
             }
             if (skip) {

@@ -1,6 +1,6 @@
 // DTW_W over (A, B) pairs with the anti-diagonal engine, FP32 or FP64, and
 // the engine geometry helpers shared with the search.
-#include "dtw_engine.hpp"
+#include "strip_engine.hpp"
 
 namespace nndtw {
 
@@ -124,6 +124,88 @@ dtw_pairs_kernel(EngineGeom geo, int NB, const float *__restrict__ A, int64_t nA
     }
 }
 
+// Pairs with the row-strip engine (wide windows): one pair per wave at a
+// time, rows read from global memory (L2-resident), batches of sb <= STRIP_SB
+// pairs per workgroup in a grid-stride loop.
+constexpr int STRIP_WAVES = 4, STRIP_SB = 64;
+
+template <typename T, int S, bool WIN>
+__global__ void __launch_bounds__(WAVE * STRIP_WAVES)
+dtw_strip_kernel(int L, int Wp, const float *__restrict__ A, int64_t nA, const float *__restrict__ B, int64_t nB,
+                 const double *__restrict__ cutoff, int pairing, int sb, T *__restrict__ out)
+{
+    __shared__ int next_task;
+    __shared__ int cells[STRIP_SB];
+    const int64_t np = pairing ? nA : nA * nB;
+    for (int64_t base = (int64_t)blockIdx.x * sb; base < np; base += (int64_t)gridDim.x * sb) {
+        const int nt = (int)((np - base) < sb ? (np - base) : sb);
+        __syncthreads();
+        if (threadIdx.x == 0) next_task = 0;
+        __syncthreads();
+        strip_run<T, S, WIN>(
+            L, Wp, nt, &next_task,
+            [&](int i) {
+                const int64_t p = base + i;
+                return A + (pairing ? p : p / nB) * L;
+            },
+            [&](int i) {
+                const int64_t p = base + i;
+                return B + (pairing ? p : p % nB) * L;
+            },
+            [&](int i) -> T {
+                if (!cutoff) return inf_of<T>();
+                const int64_t p = base + i;
+                const double c = cutoff[pairing ? p : p / nB];
+                return sizeof(T) == 4 ? (T)round_up_f32(c) : (T)c;
+            },
+            out + base, cells);
+    }
+}
+
+// Band cells of an L x L matrix within |i - j| <= Wp.
+static int64_t band_cells(int L, int Wp) { return (int64_t)L * (2 * Wp + 1) - (int64_t)Wp * (Wp + 1); }
+
+// Whether the row-strip engine serves window W' at length L: windows the
+// diagonal-pair engine cannot hold (more than 63 x 16 pairs), and windows
+// covering at least 60 % of the matrix, where the pair sweep's parallelogram
+// wastes more than the strips' pipeline fill.
+bool strip_preferred(int L, int Wp)
+{
+    if (!strip_fits(L, Wp)) return false;
+    return Wp + 1 > 63 * 16 || (double)band_cells(L, Wp) >= 0.6 * (double)L * (double)L;
+}
+
+template <typename T>
+static int launch_strip_t(const float *A, int64_t nA, const float *B, int64_t nB, int L, int Wp,
+                          const double *cutoff, int pairing, T *out, hipStream_t st)
+{
+    const int64_t np = pairing ? nA : nA * nB;
+    // pairs per workgroup batch: one per wave while that leaves fewer than
+    // about 2048 workgroups (every wave of the chip busy), up to STRIP_SB
+    int64_t sb = ceil_div(np, 256 * 8);
+    sb = sb < STRIP_WAVES ? STRIP_WAVES : (sb > STRIP_SB ? STRIP_SB : sb);
+    int64_t blocks = ceil_div(np, sb);
+    if (blocks > 256 * 8) blocks = 256 * 8;
+    const bool win = Wp < L - 1;
+    switch (strip_width(L) * 2 + (win ? 1 : 0)) {
+#define X(s)                                                                                                   \
+    case s * 2:                                                                                                \
+        hipLaunchKernelGGL((dtw_strip_kernel<T, s, false>), dim3((unsigned)blocks), dim3(WAVE * STRIP_WAVES), 0, st, \
+                           L, Wp, A, nA, B, nB, cutoff, pairing, (int)sb, out);                                        \
+        break;                                                                                                 \
+    case s * 2 + 1:                                                                                            \
+        hipLaunchKernelGGL((dtw_strip_kernel<T, s, true>), dim3((unsigned)blocks), dim3(WAVE * STRIP_WAVES), 0, st,  \
+                           L, Wp, A, nA, B, nB, cutoff, pairing, (int)sb, out);                                        \
+        break;
+        X(4) X(8) X(12) X(16) X(24) X(32)
+#undef X
+    default:
+        return fail(NNDTW_EUNSUP, "series length %d too long for the row-strip engine", L);
+    }
+    NNDTW_LAUNCH_CHECK("dtw strip kernel launch");
+    return NNDTW_OK;
+}
+
 static size_t pairs_lds(const EngineGeom &g, int NB, size_t esz)
 {
     return (size_t)2 * NB * g.LEN * esz + (size_t)NB * (esz + sizeof(int)) + 32;
@@ -136,6 +218,7 @@ static int launch_pairs_t(const float *A, int64_t nA, const float *B, int64_t nB
     const int64_t np = pairing ? nA : nA * nB;
     if (np == 0) return NNDTW_OK;
     const int Wp = W < L - 1 ? W : L - 1;
+    if (strip_preferred(L, Wp)) return launch_strip_t<T>(A, nA, B, nB, L, Wp, cutoff, pairing, out, st);
     const int C = choose_cpl(Wp, 16, 0);
     if (C < 0) return fail(NNDTW_EUNSUP, "window %d too wide for the DTW engine", W);
     EngineGeom g = make_geom(L, W, C, prefetch_lds(C), window_lds(C));

@@ -271,9 +271,9 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
         const unsigned long long freem = __ballot(in_group && gl == 0 && task < 0);
         const int nfree = __popcll(freem);
         if (nfree > 0 && !exhausted) {
-            int base = 0;
-            if (lane == 0) base = atomicAdd(next_task, nfree);
-            base = __shfl(base, 0);
+            // whole-wave fetch (lane 0 adds nfree, the others 0), lane 0's
+            // result as a scalar: no lane-dependent branch around the deal
+            const int base = __builtin_amdgcn_readfirstlane(atomicAdd(next_task, lane == 0 ? nfree : 0));
             const int left = ntasks - base;
             const int nassign = left < nfree ? (left > 0 ? left : 0) : nfree;
             exhausted = left <= nfree;

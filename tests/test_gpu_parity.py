@@ -112,7 +112,7 @@ def test_cascade_bounds_bit_exact(name, W, V):
 # ------------------------------------------------------------------ a5
 DTW_CASES = [(2, 0), (2, 1), (3, 1), (3, 5), (8, 0), (8, 3), (8, 7), (24, 2), (64, 6), (64, 63), (97, 13),
              (256, 26), (256, 255), (512, 5), (512, 51), (512, 128), (512, 256), (512, 511), (1000, 100),
-             (2048, 205), (2048, 1000)]
+             (2048, 205), (2048, 1000), (700, 699), (1500, 1499), (2048, 1500), (2048, 2047)]
 
 
 @pytest.mark.parametrize("L,W", DTW_CASES)
@@ -132,7 +132,7 @@ def test_dtw_fp64_bit_exact_and_fp32_tolerance(L, W):
     assert np.array_equal(z64, oracle.dtw(A[:5], B[:5], W, zip_=True))
 
 
-@pytest.mark.parametrize("L,W", [(1000, 100), (1000, 999), (2048, 205), (2048, 1007)])
+@pytest.mark.parametrize("L,W", [(1000, 100), (1000, 999), (2048, 205), (2048, 1007), (2048, 2047)])
 def test_dtw_fp32_long_series(L, W):
     """FP32 DTW_W at the longest lengths against the FP64 oracle at 1e-5
     relative (the error of an FP32 path sum is typically sqrt(2L) u, far below
@@ -164,7 +164,7 @@ def test_dtw_special_inputs():
     assert np.array_equal(host(nd.dtw_w(dev(A), dev(B), 0, f64=True)), oracle.ed2(A, B))
 
 
-@pytest.mark.parametrize("L,W", [(64, 6), (256, 26), (512, 128)])
+@pytest.mark.parametrize("L,W", [(64, 6), (256, 26), (512, 128), (300, 299), (2048, 2047), (1200, 900)])
 def test_dtw_cutoff_abandon(L, W):
     A = series(8, L, seed=50 + W)
     B = series(16, L, seed=51 + W)
