@@ -287,11 +287,27 @@ typedef struct nndtw_search_opts {
     int32_t waves;    /* waves per query (1..NNDTW_SEARCH_MAX_WAVES); 0 = default (8
                        * when the query count is at most twice the device's compute
                        * units, else 4); out                                          */
-    int32_t reserved32;
+    int32_t engine;   /* DTW engine, NNDTW_ENGINE_*; 0 = library choice; out          */
     int64_t nq_hint;  /* nndtw_search_plan only: the query count to plan for (0 =
                        * many); nndtw_search plans for its own nQ                    */
     int64_t reserved;
 } nndtw_search_opts;
+
+/* DTW engines of the search (opts->engine).  DIAGONAL: anti-diagonal
+ * sweep, groups of lanes per candidate, cpl diagonal pairs per lane, windows
+ * with min(W, L-1) + 1 <= 567 (63 lanes x 9 pairs).  STRIP: one candidate per
+ * wave, each lane a strip of consecutive columns with the rows pipelined
+ * across the lanes; any window with 2 min(W, L-1) + 2 >= the strip width (4
+ * columns for L <= 256, 8 to 512, 12 to 768, 16 to 1024, 24 to 1536, else
+ * 32), or W >= L - 1; at most 8 waves per query (4 above 1024).  The
+ * library's choice (AUTO): STRIP where the window is too wide for DIAGONAL,
+ * and for unconstrained DTW (W >= L - 1) at L > 192; else DIAGONAL.  Both give the
+ * same result and the same counts except the abandoned-DTW, cell and
+ * recheck counts, which depend on where each engine tests its frontier.
+ * The batched search runs DIAGONAL only. */
+#define NNDTW_ENGINE_AUTO     0
+#define NNDTW_ENGINE_DIAGONAL 1
+#define NNDTW_ENGINE_STRIP    2
 
 /* Workspace bytes nndtw_search needs for nQ queries against refset. */
 int nndtw_search_workspace_bytes(const nndtw_refset *refset, int64_t nQ,
@@ -299,9 +315,10 @@ int nndtw_search_workspace_bytes(const nndtw_refset *refset, int64_t nQ,
 
 /* The launch plan nndtw_search would use for this reference set and these
  * options, decided on the host without enqueuing anything: writes opts->R
- * (round size, >= 1), opts->cpl (diagonal pairs per lane of the DTW engine)
- * and opts->waves.  The search runs windows with min(W, L-1) + 1 <= 567
- * (63 lanes x 9 pairs); wider windows are EUNSUP. */
+ * (round size, >= 1), opts->engine, opts->cpl (diagonal pairs per lane of
+ * the DIAGONAL engine, 0 with STRIP) and opts->waves.  Every window runs on
+ * one of the engines; a forced engine that cannot take the window is
+ * EUNSUP. */
 int nndtw_search_plan(const nndtw_refset *refset, nndtw_search_opts *opts);
 
 /* Q: device float[nQ][L] (L of the reference set); outputs: nn_idx int64[nQ],

@@ -24,6 +24,7 @@ OK, EINVAL, EHIP, EUNSUP = 0, -1, -2, -3
 CROSS, ZIP = 0, 1
 CASCADES = {"none": 0, "keogh": 1, "keogh_enh": 2, "enh": 3,
             "kim": 4, "improved": 5, "new": 6, "enh_sym": 7}
+ENGINES = {"auto": 0, "diagonal": 1, "strip": 2}
 COUNT_NAMES = ("n", "pruned_keogh", "pruned_enh_bands", "pruned_enh", "dtw_started",
                "dtw_abandoned", "cells", "fp64_rechecks")
 MAX_L = 2048
@@ -51,7 +52,7 @@ class _Refset(ctypes.Structure):
 class _SearchOpts(ctypes.Structure):
     _fields_ = [("V", ctypes.c_int32), ("cascade", ctypes.c_int32), ("R", ctypes.c_int64),
                 ("eps", ctypes.c_double), ("init_ub", ctypes.c_int32), ("cpl", ctypes.c_int32),
-                ("events", ctypes.c_void_p), ("waves", ctypes.c_int32), ("reserved32", ctypes.c_int32),
+                ("events", ctypes.c_void_p), ("waves", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("nq_hint", ctypes.c_int64), ("reserved", ctypes.c_int64)]
 
 
@@ -344,10 +345,10 @@ class RefSet:
         return self._view(which, (self.L, self.desc.pitch))[:, : self.n]
 
 
-def _opts(V, cascade, R, eps, init_ub, cpl, waves=0):
+def _opts(V, cascade, R, eps, init_ub, cpl, waves=0, engine="auto"):
     o = _SearchOpts()
     o.V, o.cascade, o.R, o.eps = int(V), CASCADES[cascade], int(R), float(eps)
-    o.init_ub, o.cpl, o.waves = int(bool(init_ub)), int(cpl), int(waves)
+    o.init_ub, o.cpl, o.waves, o.engine = int(bool(init_ub)), int(cpl), int(waves), ENGINES[engine]
     return o
 
 
@@ -355,10 +356,10 @@ class Searcher:
     """Preallocated workspace for repeated nndtw_search calls on one RefSet."""
 
     def __init__(self, refset: RefSet, nQ: int, V: int = 5, cascade: str = "keogh_enh", R: int = 0,
-                 eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0):
+                 eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0, engine: str = "auto"):
         self.refset = refset
         self.nQ = int(nQ)
-        self.opts = _opts(V, cascade, R, eps, init_ub, cpl, waves)
+        self.opts = _opts(V, cascade, R, eps, init_ub, cpl, waves, engine)
         nbytes = ctypes.c_size_t(0)
         _check(lib().nndtw_search_workspace_bytes(ctypes.byref(refset.desc), self.nQ, ctypes.byref(self.opts),
                                                   ctypes.byref(nbytes)))
@@ -393,6 +394,11 @@ class Searcher:
     @property
     def waves(self):
         return int(self.opts.waves)
+
+    @property
+    def engine(self):
+        """The DTW engine of the last call: "diagonal" or "strip"."""
+        return {v: k for k, v in ENGINES.items()}[int(self.opts.engine)]
 
 
 class BatchSearcher:
@@ -445,22 +451,22 @@ class BatchSearcher:
 
 
 def search(refset: RefSet, Q: torch.Tensor, V: int = 5, cascade: str = "keogh_enh", R: int = 0,
-           eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0):
+           eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0, engine: str = "auto"):
     """One-shot NN-DTW search: returns (nn_idx int64, nn_dist float64, counts int64[nQ][8], R used)."""
     Q = _series(Q, "Q")
-    s = Searcher(refset, Q.shape[0], V, cascade, R, eps, init_ub, cpl, waves)
+    s = Searcher(refset, Q.shape[0], V, cascade, R, eps, init_ub, cpl, waves, engine)
     idx, dist, counts = s(Q)
     return idx.clone(), dist.clone(), counts.clone(), s.R
 
 
 def search_noalloc(refset: RefSet, Q: torch.Tensor, idx: torch.Tensor, dist: torch.Tensor, counts=None,
                    V: int = 5, cascade: str = "keogh_enh", R: int = 0, eps: float = 0.0, init_ub: bool = True,
-                   cpl: int = 0, waves: int = 0):
+                   cpl: int = 0, waves: int = 0, engine: str = "auto"):
     """nndtw_search_noalloc: the search into caller-provided outputs (idx int64
     [nQ], dist float64 [nQ], counts int64 [nQ][8] or None) with the library's
     fixed device workspace; returns the R used."""
     Q = _series(Q, "Q")
-    opts = _opts(V, cascade, R, eps, init_ub, cpl, waves)
+    opts = _opts(V, cascade, R, eps, init_ub, cpl, waves, engine)
     _check(lib().nndtw_search_noalloc(ctypes.byref(refset.desc), _ptr(Q), Q.shape[0], ctypes.byref(opts), _ptr(idx),
                                       _ptr(dist), _ptr(counts), _stream()))
     return int(opts.R)

@@ -319,6 +319,7 @@ static int check_opts(const nndtw_search_opts *o)
     REQUIRE(o->waves >= 0 && o->waves <= NNDTW_SEARCH_MAX_WAVES, "waves=%d must be in 0..%d", o->waves,
             NNDTW_SEARCH_MAX_WAVES);
     REQUIRE(o->nq_hint >= 0, "nq_hint=%lld must be >= 0", (long long)o->nq_hint);
+    REQUIRE(o->engine >= NNDTW_ENGINE_AUTO && o->engine <= NNDTW_ENGINE_STRIP, "engine=%d unknown", o->engine);
     return NNDTW_OK;
 }
 
@@ -344,6 +345,7 @@ int nndtw_search_plan(const nndtw_refset *refset, nndtw_search_opts *opts)
     opts->R = plan.R;
     opts->cpl = plan.C;
     opts->waves = plan.NW;
+    opts->engine = plan.S > 0 ? NNDTW_ENGINE_STRIP : NNDTW_ENGINE_DIAGONAL;
     return NNDTW_OK;
 }
 
@@ -371,6 +373,7 @@ int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ, nndtw_s
     opts->R = plan.R;
     opts->cpl = plan.C;
     opts->waves = plan.NW;
+    opts->engine = plan.S > 0 ? NNDTW_ENGINE_STRIP : NNDTW_ENGINE_DIAGONAL;
     return launch_search(refset, Q, nQ, opts, plan, nn_idx, nn_dist, counts, ws, (hipStream_t)stream);
 }
 

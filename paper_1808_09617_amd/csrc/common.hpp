@@ -100,6 +100,7 @@ int launch_dtw_backward(bool f64, const float *A, int64_t nA, const float *B, in
 // search.hip
 struct SearchPlan {
     int Wp, C, G, P, PD, SLOTS, NW, exact, T, LEN;
+    int S;          // row-strip engine: columns per lane (0: anti-diagonal engine)
     int64_t R;
     double eps;
     size_t lds_bytes;

@@ -35,7 +35,7 @@
 // of the recurrence, so every decision is taken on the same values.
 #include <algorithm>
 
-#include "dtw_engine.hpp"
+#include "strip_engine.hpp"
 
 namespace nndtw {
 
@@ -491,13 +491,16 @@ __device__ __forceinline__ int stage_of(int cascade, double b1, double b2, doubl
 // RK: which FP64 recheck engine the code holds: 1 one diagonal pair per lane
 // (windows of up to 63 pairs), 2 the FP32 engine's C pairs per lane, 0 both
 // (chosen at run time).  A kernel holding one of them needs fewer registers.
-template <int C, bool EXACT, int RK = 0>
+// S > 0: the row-strip engine (strip_engine.hpp, S columns per lane, one
+// candidate per wave) runs both the FP32 DTWs and the FP64 rechecks instead
+// (C, EXACT and RK are then unused); WIN: the window constrains.
+template <int C, bool EXACT, int RK = 0, int S = 0, bool WIN = true>
 __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t q, unsigned char *smem)
 {
     const EngineGeom &geo = a.geo, &geoD = a.geoD;
     const int PD = a.PD, SLOTS = a.SLOTS;
     // the query row serves both engines: stage the longer of their rows
-    const int LENA = staged_len(geo, geoD);
+    const int LENA = S > 0 ? geo.L : staged_len(geo, geoD);
     constexpr int DG = prefetch_global(C), MG = window_global(C), DD = recheck_prefetch(C), MD = recheck_window(C);
     float *aF = reinterpret_cast<float *>(smem);
     double *resD = reinterpret_cast<double *>(aF + ((LENA + 1) & ~1));
@@ -523,7 +526,9 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
     const int rot_phase = rotation_phase(a.ncu);
 
-    {
+    if constexpr (S > 0) {
+        for (int e = tid; e < L; e += nthr) aF[e] = a.Q[q * L + e];
+    } else {
         EngineGeom ga = geo;
         ga.LEN = LENA;
         stage_rows<float, C>(aF, a.Q, [&](int) { return q; }, 1, ga, tid, nthr);
@@ -558,10 +563,18 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
             const int h0 = qh;
             if (tid == 0) *next_task = 0;
             __syncthreads();
-            engine_run<float, C, DG, MG, EXACT>(
-                geo, nt, next_task, [&](int) { return (const float *)aF; },
-                [&](int i) { return Bp + (int64_t)ring[(h0 + i) % QCAP] * a.ppitch; }, [&](int) { return thrF; },
-                TaskOut<float>{resF, trunF, run_thr, 1.0 + 2.0 * a.eps, rot_phase});
+            if constexpr (S > 0) {
+                // trunF receives the band cells each task evaluated
+                strip_run<float, S, WIN>(
+                    L, geo.Wp, nt, next_task, [&](int) { return (const float *)aF; },
+                    [&](int i) { return a.B + (int64_t)ring[(h0 + i) % QCAP] * L; }, [&](int) { return thrF; },
+                    resF, trunF, run_thr, 1.0 + 2.0 * a.eps, rot_phase);
+            } else {
+                engine_run<float, C, DG, MG, EXACT>(
+                    geo, nt, next_task, [&](int) { return (const float *)aF; },
+                    [&](int i) { return Bp + (int64_t)ring[(h0 + i) % QCAP] * a.ppitch; },
+                    [&](int) { return thrF; }, TaskOut<float>{resF, trunF, run_thr, 1.0 + 2.0 * a.eps, rot_phase});
+            }
             __syncthreads();
             // the batch's results, 64 tasks per pass: counts and the
             // smallest completed FP32 result
@@ -573,9 +586,13 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                     const int tr = trunF[j];
                     const bool ab = __builtin_isinf(d32);
                     c_ab += ab;
-                    int s_last = s_start + 2 * (tr - 1) + 1;
-                    if (s_last > 2 * L - 2) s_last = 2 * L - 2;
-                    c_cells += s_last >= 0 ? (int64_t)a.prefix[s_last] : 0;
+                    if constexpr (S > 0) {
+                        c_cells += tr;
+                    } else {
+                        int s_last = s_start + 2 * (tr - 1) + 1;
+                        if (s_last > 2 * L - 2) s_last = 2 * L - 2;
+                        c_cells += s_last >= 0 ? (int64_t)a.prefix[s_last] : 0;
+                    }
                     if (!ab && (double)d32 <= thr) mn = __builtin_fminf(mn, d32);
                 }
             }
@@ -612,7 +629,12 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                 // waves of other workgroups sharing the SIMD do not stretch
                 // this query's critical path
                 __builtin_amdgcn_s_setprio(3);
-                if (RK == 1 || (RK == 0 && C > 1 && geoD.C == 1)) {
+                if constexpr (S > 0) {
+                    strip_run<double, S, WIN>(
+                        L, geo.Wp, nd, next_task, [&](int) { return (const float *)aF; },
+                        [&](int i) { return a.B + (int64_t)rq[b0 + i] * L; }, [&](int) { return thr; }, resD,
+                        trunD);
+                } else if (RK == 1 || (RK == 0 && C > 1 && geoD.C == 1)) {
                     // one pair per lane: rows start C - 1 elements later
                     constexpr int D1 = recheck_prefetch(1), M1 = recheck_window(1);
                     engine_run<double, 1, D1, M1, true>(
@@ -742,6 +764,20 @@ search_kernel_wide(SearchArgs a)
 // Whether a plan may use more than SEARCH_MAX_WAVES waves (search_kernel_wide).
 static bool wide_ok(int C, int Wp) { return C <= 6 && recheck_cpl(Wp, C) == 1; }
 
+// The search with the row-strip engine (wide windows): one candidate per
+// wave.  Up to 8 waves per query for strips of up to 16 columns; wider
+// strips hold up to 256 registers per lane in FP64, one wave per SIMD, so
+// their workgroups have at most 4 waves.
+__host__ __device__ constexpr int strip_search_waves(int S) { return S <= 16 ? SEARCH_MAX_WAVES : 4; }
+
+template <int S, bool WIN>
+__global__ void __launch_bounds__(WAVE * strip_search_waves(S))
+search_kernel_strip(SearchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    search_query<1, false, 2, S, WIN>(a, blockIdx.x, smem);
+}
+
 // The search of a batch: persistent workgroups take (set, query) items of
 // one engine shape (C, EXACT) from that shape's counter in the batch header,
 // in the order of the item list (largest expected work first).  One launch
@@ -812,18 +848,93 @@ size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, in
     return (size_t)((LENA + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 12 + QCAP * 4 + 16;
 }
 
+// Plan of the search with the row-strip engine.
+static int plan_search_strip(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan)
+{
+    const int L = rs->L;
+    const int Wp = rs->W < L - 1 ? rs->W : L - 1;
+    if (o->cpl > 0) return fail(NNDTW_EINVAL, "cpl=%d: pairs per lane apply to the diagonal engine only", o->cpl);
+    if (!strip_fits(L, Wp))
+        return fail(NNDTW_EUNSUP, "window W=%d too narrow for the row-strip engine at L=%d (2 min(W, L-1) + 2 >= %d)",
+                    rs->W, L, strip_width(L));
+    const int S = strip_width(L);
+    const int maxw = strip_search_waves(S);
+    int NW = o->waves;
+    if (NW <= 0) {
+        const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
+        const bool few = o->nq_hint > 0 && o->nq_hint <= 2 * (int64_t)cu;
+        NW = few ? maxw : (SEARCH_DEFAULT_WAVES < maxw ? SEARCH_DEFAULT_WAVES : maxw);
+    }
+    if (NW > maxw)
+        return fail(NNDTW_EUNSUP, "waves=%d: the row-strip search takes at most %d waves per query at L=%d", NW, maxw,
+                    L);
+    // one candidate per wave: the same default round as the diagonal engine
+    const int64_t R = o->R > 0 ? o->R : (2 * NW > 256 ? 2 * NW : 256);
+    const int SLOTS = 256, PD = 64;
+    const size_t lds = (size_t)((L + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 12 + QCAP * 4 + 16;
+    *plan = SearchPlan{};
+    plan->Wp = Wp;
+    plan->C = 0;
+    plan->S = S;
+    plan->G = WAVE;
+    plan->P = 1;
+    plan->PD = PD;
+    plan->SLOTS = SLOTS;
+    plan->NW = NW;
+    plan->T = L + (L - 1) / S;
+    plan->LEN = L;
+    plan->R = R;
+    plan->lds_bytes = lds;
+    return NNDTW_OK;
+}
+
+// The FP32 error floor of the slack (see the header): eps >= 2 gamma, with
+// gamma = gamma_{2L+1} of float32.  The default and the smallest value
+// accepted is twice gamma_{2L+2} = 2 n u / (1 - n u), n = 2L + 2.
+static int plan_eps(int L, const nndtw_search_opts *o, SearchPlan *plan)
+{
+    const double nu = (double)(2 * L + 2) * 0x1p-24;
+    const double eps_min = 2.0 * nu / (1.0 - nu);
+    if (o->eps > 0 && o->eps < eps_min)
+        return fail(NNDTW_EINVAL, "eps=%g below the FP32 error floor %.9g for L=%d (2 gamma_{2L+2})", o->eps,
+                    eps_min, L);
+    plan->eps = o->eps > 0 ? o->eps : eps_min;
+    return NNDTW_OK;
+}
+
 int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan, bool batched)
 {
     const int L = rs->L;
     const int Wp = rs->W < L - 1 ? rs->W : L - 1;
+    int engine = o->engine;
+    // The library's choice: strips where the diagonal shapes compiled for the
+    // search cannot hold the window, and for unconstrained DTW (W' = L - 1)
+    // when the strips keep at least 48 lanes busy (L > 192).  Elsewhere the
+    // diagonal engine measured faster in the search, although strips do less
+    // work per complete DTW from 60 % band coverage on (5000 x 500, L=512,
+    // V=5, 8 waves per query: W=256 21 ms diagonal / 47 ms strips, W=450
+    // 40 / 51, W=511 44 / 39): most candidates are abandoned after a third
+    // of their rows, where the strips' pipeline fill and full-width rows
+    // (window cells marked, not skipped) cost most, and a query's work runs
+    // on one compute unit either way.
+    if (engine == NNDTW_ENGINE_AUTO)
+        engine = !batched && o->cpl <= 0 && strip_fits(L, Wp) &&
+                         (Wp + 1 > 63 * SEARCH_MAX_CPL || (Wp >= L - 1 && L > 192))
+                     ? NNDTW_ENGINE_STRIP
+                     : NNDTW_ENGINE_DIAGONAL;
+    if (engine == NNDTW_ENGINE_STRIP) {
+        if (batched) return fail(NNDTW_EUNSUP, "the batched search runs the diagonal engine only");
+        const int r = plan_search_strip(rs, o, plan);
+        return r ? r : plan_eps(L, o, plan);
+    }
     // Only shapes up to SEARCH_MAX_CPL pairs per lane are compiled for the
     // search: it takes windows with min(W, L-1) + 1 <= 63 * SEARCH_MAX_CPL.
     // The batched search keeps the narrow shapes even where one group fills
     // a wave (it has kernels for 1-4 pairs per lane and rejects wider ones).
     const int C = choose_cpl(Wp, 4, o->cpl, SEARCH_MAX_CPL, !batched);
     if (C < 0 && o->cpl <= 0)
-        return fail(NNDTW_EUNSUP, "window W=%d too wide for the search (min(W, L-1) + 1 <= %d)", rs->W,
-                    63 * SEARCH_MAX_CPL);
+        return fail(NNDTW_EUNSUP, "window W=%d too wide for the %s (min(W, L-1) + 1 <= %d)", rs->W,
+                    batched ? "batched search" : "diagonal engine", 63 * SEARCH_MAX_CPL);
     if (C < 0) return fail(NNDTW_EINVAL, "no search engine shape with cpl=%d for W=%d", o->cpl, rs->W);
     EngineGeom g = make_geom(L, rs->W, C, prefetch_global(C), window_global(C));
     const EngineGeom gd = recheck_geom(L, rs->W, C);
@@ -881,17 +992,9 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     plan->T = g.T;
     plan->LEN = g.LEN;
     plan->R = R;
-    // The slack must cover the FP32 error (see the header): eps >= 2 gamma,
-    // with gamma = gamma_{2L+1} of float32.  The default and the smallest
-    // value accepted is twice gamma_{2L+2} = 2 n u / (1 - n u), n = 2L + 2.
-    const double nu = (double)(2 * L + 2) * 0x1p-24;
-    const double eps_min = 2.0 * nu / (1.0 - nu);
-    if (o->eps > 0 && o->eps < eps_min)
-        return fail(NNDTW_EINVAL, "eps=%g below the FP32 error floor %.9g for L=%d (2 gamma_{2L+2})", o->eps,
-                    eps_min, L);
-    plan->eps = o->eps > 0 ? o->eps : eps_min;
+    plan->S = 0;
     plan->lds_bytes = lds;
-    return NNDTW_OK;
+    return plan_eps(L, o, plan);
 }
 
 int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nndtw_search_opts *o,
@@ -940,8 +1043,15 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     if ((r = mark(3))) return r;
 
     SearchArgs a;
-    a.geo = make_geom(L, rs->W, plan.C, prefetch_global(plan.C), window_global(plan.C));
-    a.geoD = recheck_geom(L, rs->W, plan.C);
+    if (plan.S > 0) {
+        a.geo = EngineGeom{};
+        a.geo.L = L;
+        a.geo.Wp = plan.Wp;
+        a.geoD = a.geo;
+    } else {
+        a.geo = make_geom(L, rs->W, plan.C, prefetch_global(plan.C), window_global(plan.C));
+        a.geoD = recheck_geom(L, rs->W, plan.C);
+    }
     a.PD = plan.PD;
     a.SLOTS = plan.SLOTS;
     a.B = rs->B;
@@ -965,6 +1075,24 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     a.counts = counts;
     a.ncu = device_cu_count();
     const size_t lds = plan.lds_bytes;
+    if (plan.S > 0) {
+        const bool win = plan.Wp < L - 1;
+        switch (plan.S * 2 + (win ? 1 : 0)) {
+#define X(s)                                                                                                    \
+    case s * 2:                                                                                                 \
+        hipLaunchKernelGGL((search_kernel_strip<s, false>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a); \
+        break;                                                                                                  \
+    case s * 2 + 1:                                                                                             \
+        hipLaunchKernelGGL((search_kernel_strip<s, true>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);  \
+        break;
+            X(4) X(8) X(12) X(16) X(24) X(32)
+#undef X
+        default:
+            return fail(NNDTW_EUNSUP, "no row-strip search kernel for %d columns per lane", plan.S);
+        }
+        NNDTW_LAUNCH_CHECK("search kernel launch");
+        return mark(4);
+    }
     if (plan.NW > SEARCH_MAX_WAVES) {
         switch (plan.C * 2 + (plan.exact ? 1 : 0)) {
 #define X(c)                                                                                                    \

@@ -56,7 +56,8 @@ def test_struct_layouts():
     assert nd._Refset.B.offset == 32
     assert ctypes.sizeof(nd._SearchOpts) == 64
     assert nd._SearchOpts.eps.offset == 16 and nd._SearchOpts.events.offset == 32
-    assert nd._SearchOpts.waves.offset == 40 and nd._SearchOpts.nq_hint.offset == 48
+    assert nd._SearchOpts.waves.offset == 40 and nd._SearchOpts.engine.offset == 44
+    assert nd._SearchOpts.nq_hint.offset == 48
     assert nd._SearchOpts.reserved.offset == 56
 
 
@@ -205,30 +206,58 @@ def test_python_binding_rejects_cpu_tensors():
         nd.envelopes(torch.zeros(3, 8), 2)
 
 
+def _strip_width(L):
+    return 4 if L <= 256 else 8 if L <= 512 else 12 if L <= 768 else 16 if L <= 1024 else 24 if L <= 1536 else 32
+
+
+def _strip_chosen(L, Wp):
+    """The search's engine choice: row strips where the window is too wide
+    for its diagonal shapes (63 lanes x 9 pairs), and for unconstrained DTW
+    at L > 192."""
+    return Wp + 1 > 63 * 9 or (Wp >= L - 1 and L > 192)
+
+
 def test_search_plan_has_a_shape_for_every_window():
-    """For every window the host plan is a shape whose groups fit a wave
-    (at least one pair of series per wave, so a round of at least one
-    candidate), or EUNSUP beyond 63 lanes x 9 pairs.  (A plan with zero
-    groups per wave once gave a round size of 0, which the kernel divides by.)"""
+    """For every window the host plan is either the row-strip engine (one
+    candidate per wave) or a diagonal shape whose groups fit a wave (at least
+    one pair of series per wave, so a round of at least one candidate).  (A
+    plan with zero groups per wave once gave a round size of 0, which the
+    kernel divides by.)  Forcing the diagonal engine beyond 63 lanes x 9
+    pairs, or the strip engine on a window narrower than its strips, is
+    EUNSUP."""
     lib = nd.lib()
-    for L in (2, 64, 300, 512, 2048):
+    for L in (2, 3, 64, 300, 512, 2048):
         d = nd._Refset()
         d.magic, d.L, d.n = nd.REFSET_MAGIC, L, 100
         d.padl, d.ppitch = 4096, 16384                      # margins wide enough for any shape
-        for W in sorted(set(range(0, min(L, 600) + 1)) | {L - 1, L, 2 * L}):
+        for W in sorted(set(range(0, min(L, 600) + 1)) | {L // 2, L - 2, L - 1, L, 2 * L} - {-1}):
             d.W = W
             Wp = min(W, L - 1)
             opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
             st = lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts))
-            if Wp + 1 > 63 * 9:
-                assert _err(st, "too wide for the search") == nd.EUNSUP
-                continue
             assert st == 0, (L, W, nd.last_error())
-            C = opts.cpl
-            G = -(-(Wp + 1) // C)
-            assert C in (1, 2, 3, 4, 6, 8, 9) and G <= 63, (L, W, C, G)
-            # default round: two candidates per group, at least 256
-            assert opts.R == max(2 * (63 // G) * opts.waves, 256), (L, W, opts.R)
+            if _strip_chosen(L, Wp):
+                assert opts.engine == nd.ENGINES["strip"] and opts.cpl == 0, (L, W)
+                assert opts.waves == 4 and opts.R == 256, (L, W, opts.waves, opts.R)
+            else:
+                assert opts.engine == nd.ENGINES["diagonal"], (L, W)
+                C = opts.cpl
+                G = -(-(Wp + 1) // C)
+                assert C in (1, 2, 3, 4, 6, 8, 9) and G <= 63, (L, W, C, G)
+                # default round: two candidates per group, at least 256
+                assert opts.R == max(2 * (63 // G) * opts.waves, 256), (L, W, opts.R)
+            forced = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, engine="diagonal")
+            st = lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(forced))
+            if Wp + 1 > 63 * 9:
+                assert _err(st, "too wide for the diagonal engine") == nd.EUNSUP
+            else:
+                assert st == 0 and forced.engine == nd.ENGINES["diagonal"], (L, W, nd.last_error())
+            forced = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, engine="strip")
+            st = lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(forced))
+            if Wp >= L - 1 or 2 * Wp + 2 >= _strip_width(L):
+                assert st == 0 and forced.engine == nd.ENGINES["strip"], (L, W, nd.last_error())
+            else:
+                assert _err(st, "too narrow for the row-strip engine") == nd.EUNSUP
     # where the narrow shapes (<= 4 pairs per lane) leave one group per wave
     # with lanes idle, a wider shape is taken: W=128 at L=512 (129 diagonal
     # pairs) runs 4 groups of 15 lanes at 9 pairs per lane, not one group of
@@ -240,6 +269,15 @@ def test_search_plan_has_a_shape_for_every_window():
     d.W = 251
     opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 2)              # 126 lanes per group: no fit
     assert _err(lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)), "cpl=2") == nd.EINVAL
+    # pairs per lane are a diagonal-engine option; strips take up to 4 waves above L = 1024
+    d.W = 2047
+    opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 3, engine="strip")
+    assert _err(lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)), "diagonal engine only") == nd.EINVAL
+    opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, waves=8)
+    assert _err(lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)), "at most 4 waves") == nd.EUNSUP
+    opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
+    opts.engine = 3
+    assert _err(lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)), "engine=3") == nd.EINVAL
 
 
 def test_search_kernels_fit_the_register_file():
@@ -250,9 +288,13 @@ def test_search_kernels_fit_the_register_file():
         hipbuild.build()
     rows = [l.split() for l in open(hipbuild.RESOURCES) if l.strip() and not l.startswith("#")]
     search = [r for r in rows if "search_kernel" in r[0]]
-    assert len(search) >= 2 * 4 + 2 * 4                     # 4 shapes x 2, single-set and batched
+    assert len(search) >= 2 * 4 + 2 * 4 + 2 * 6             # single-set and batched shapes, strips
     for name, v, a, scratch in search:
-        assert int(scratch) == 0 and int(a) == 0 and int(v) <= 256, (name, v, a, scratch)
+        assert int(scratch) == 0, (name, v, a, scratch)
+        # strips of 24 and 32 columns run one wave per SIMD (4-wave
+        # workgroups) and may use accumulation registers as well
+        wide_strip = "search_kernel_strip" in name and ("ILi24E" in name or "ILi32E" in name)
+        assert int(v) <= 256 and (int(v) + int(a) <= 512 if wide_strip else int(a) == 0), (name, v, a)
 
 
 def test_search_eps_floor():

@@ -194,16 +194,17 @@ def test_dtw_tightness_pairs_zip():
 
 
 # ------------------------------------------------------------------ search
-def run_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, waves=0):
+def run_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, waves=0, engine="auto"):
     rs = nd.RefSet(dev(refs), W)
     idx, dist, counts, R_used = nd.search(rs, dev(queries), V=V, cascade=cascade, R=R, init_ub=init_ub, cpl=cpl,
-                                          waves=waves)
+                                          waves=waves, engine=engine)
     return host(idx), host(dist), host(counts), R_used
 
 
-def check_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, brute=True, waves=0):
-    say("search", refs.shape, queries.shape, W, V, cascade, R, init_ub, cpl, waves)
-    gi, gd, gc, R_used = run_search(refs, queries, W, V, cascade, R, init_ub, cpl, waves)
+def check_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, brute=True, waves=0,
+                 engine="auto"):
+    say("search", refs.shape, queries.shape, W, V, cascade, R, init_ub, cpl, waves, engine)
+    gi, gd, gc, R_used = run_search(refs, queries, W, V, cascade, R, init_ub, cpl, waves, engine)
     oi, od, oc = oracle.search(refs, queries, W, V, cascade, R_used, init_ub)
     assert np.array_equal(gi, oi), ("nn_idx", np.nonzero(gi != oi))
     assert np.array_equal(gd, od), ("nn_dist", np.max(np.abs(gd - od)))
@@ -323,15 +324,48 @@ def test_search_mix512_full(W):
 
 @pytest.mark.parametrize("L,W", [(2048, 205), (2048, 566), (1200, 566), (560, 559)])
 def test_search_long_series_and_widest_windows(L, W):
-    """Maximum length and the widest windows the search compiles (9 pairs per
-    lane, min(W, L-1) + 1 = 567), against the oracle at the same R."""
+    """Maximum length and the widest windows the diagonal engine compiles for
+    the search (9 pairs per lane, min(W, L-1) + 1 = 567), forced, and the
+    library's choice, against the oracle at the same R."""
     refs = series(60, L, seed=L + W, kind="rw")
     queries = series(3, L, seed=L + W + 1, kind="rw")
     for V in (1, 5):
-        check_search(refs, queries, W, V, "keogh_enh", 0, True, 0, brute=False)
+        for engine in ("diagonal", "auto"):
+            check_search(refs, queries, W, V, "keogh_enh", 0, True, 0, brute=False, engine=engine)
 
 
-@pytest.mark.parametrize("L,W", [(64, 6), (256, 26), (300, 299), (512, 128)])
+@pytest.mark.parametrize("L,W", [(64, 63), (100, 60), (300, 299), (512, 300), (700, 650), (1100, 1099),
+                                 (2048, 1000), (2048, 2047)])
+def test_search_strip_engine(L, W):
+    """The row-strip engine in the search (the library's choice for windows
+    too wide for the diagonal shapes and for unconstrained DTW at L > 192,
+    forced elsewhere), up to unconstrained DTW at the maximum length, against
+    the oracle at the same R and against brute force."""
+    refs = series(40, L, seed=3 * L + W, kind="rw")
+    queries = series(3, L, seed=3 * L + W + 1, kind="rw")
+    s = nd.Searcher(nd.RefSet(dev(refs), W), 3)
+    s(dev(queries))
+    Wp = min(W, L - 1)
+    auto_strip = Wp + 1 > 567 or (Wp == L - 1 and L > 192)
+    assert s.engine == ("strip" if auto_strip else "diagonal"), (L, W, s.engine)
+    for V in (1, 5):
+        check_search(refs, queries, W, V, "keogh_enh", 0, True, 0, brute=V == 1, engine="strip")
+    check_search(refs, queries, W, 2, "keogh_enh", 7, False, 0, brute=False, engine="strip")
+
+
+@pytest.mark.parametrize("L,W", [(40, 15), (256, 100), (512, 128), (600, 566)])
+def test_search_engines_agree(L, W):
+    """Windows both engines take: the strip engine forced, the diagonal engine
+    forced and the library's choice give the oracle's result and counts, with
+    1 to 8 waves per query."""
+    refs = series(120, L, seed=5 * L + W, kind="sin5")
+    queries = series(4, L, seed=5 * L + W + 1, kind="sin5")
+    for engine in ("strip", "diagonal", "auto"):
+        for waves in (1, 3, 8):
+            check_search(refs, queries, W, 3, "keogh_enh", 0, True, 0, brute=False, waves=waves, engine=engine)
+
+
+@pytest.mark.parametrize("L,W", [(64, 6), (256, 26), (300, 299), (512, 128), (512, 400), (2048, 2047)])
 def test_search_cell_counts_of_complete_dtws(L, W):
     """References identical to the query: every distance is 0, the threshold
     is 0 and no DTW is abandoned (the test is strict), so the cells the search
