@@ -247,6 +247,14 @@ def serving_bench(nd, synth, torch, dev, rate=2000.0, duration=3.0):
     _, summary = server.run(reqs)
     summary.update({"offered_rps": rate, "sets": len(sets), "refs_per_set": sets[0][0].shape[0],
                     "lengths": Ls, "R": R, "cpl": cpl})
+    # saturation: 4000 requests present at the start, served as fast as the
+    # server admits them (batches of up to 512 within the 1 GiB budget)
+    sat = serve.poisson_requests(Ls, rate=float("inf"), duration=4000, seed=3, device=dev,
+                                 make_query=lambda s, L, k: synth.serving_query(s, L, 3 * 10 ** 6 + k))
+    torch.cuda.synchronize()
+    _, ssum = server.run(sat)
+    summary["saturation"] = {k: ssum[k] for k in ("requests", "batches", "mean_batch", "wall_s", "throughput_rps",
+                                                  "max_batches_in_flight", "max_workspace_bytes", "budget_bytes")}
     del rss
     torch.cuda.empty_cache()
     return summary

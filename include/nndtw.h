@@ -448,11 +448,14 @@ int nndtw_batch_workspace_bytes(const nndtw_batch_set *sets, int32_t nsets,
                                 const nndtw_search_opts *opts, size_t *bytes);
 
 /* Plan a batch into ws (device, >= nndtw_batch_workspace_bytes) and *plan:
- * validates every set, writes back each set's R and cpl, copies the set
- * descriptors and item lists into ws and fills the per-set cells tables.
- * Synchronous: returns after the copies on `stream` are complete.  Options
- * (V, cascade, eps, init_ub, waves) are common to all sets; opts->R and
- * opts->cpl are ignored (per set instead); opts->events must be NULL. */
+ * validates every set, writes back each set's R and cpl, and enqueues on
+ * `stream` the copy of the set descriptors and item lists into ws.  Returns
+ * without waiting for the device (the host copy of that control block is
+ * released by the stream once copied); run nndtw_search_batch on the same
+ * stream, or ordered after it.  Options (V, cascade, eps, init_ub, waves)
+ * are common to all sets; opts->R and opts->cpl are ignored (per set
+ * instead); opts->engine must be AUTO or DIAGONAL; opts->events must be
+ * NULL. */
 int nndtw_batch_prepare(nndtw_batch_set *sets, int32_t nsets, const nndtw_search_opts *opts,
                         void *ws, size_t ws_bytes, nndtw_batch_plan *plan, void *stream);
 

@@ -10,8 +10,10 @@
 //      workgroups take (set, query) items from the shape's counter, largest
 //      expected work (n * L * (2W'+1)) first.
 // Everything the kernels need (set descriptors, item lists, tile starts) is
-// copied into the caller's workspace once, at planning time, so the launch
-// sequence allocates and copies nothing and can be captured in a graph.
+// copied into the caller's workspace once, at planning time (enqueued on the
+// stream, without waiting), so the launch sequence allocates and copies
+// nothing and can be captured in a graph.  The ordering kernel of each set's
+// first query also writes the set's cells table.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -175,27 +177,32 @@ int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, 
         ocnt[s] = (int64_t)oitems.size() - ooff[s];
     }
 
-    // one host image of the control block, copied once
-    std::vector<unsigned char> img(y.set_off.empty() ? y.tstart + 8 * (size_t)(nsets + 1) : y.set_off[0], 0);
+    // one host image of the control block, copied once.  The copy is only
+    // enqueued: the image lives until a host function that follows the copy
+    // on the stream releases it, so prepare does not wait for the device.
+    auto *img = new std::vector<unsigned char>(y.set_off.empty() ? y.tstart + 8 * (size_t)(nsets + 1)
+                                                                 : y.set_off[0], 0);
     BatchHdr hdr{};
-    std::memcpy(img.data() + y.hdr, &hdr, sizeof(hdr));
-    std::memcpy(img.data() + y.sets, bs.data(), sizeof(BatchSet) * bs.size());
+    std::memcpy(img->data() + y.hdr, &hdr, sizeof(hdr));
+    std::memcpy(img->data() + y.sets, bs.data(), sizeof(BatchSet) * bs.size());
     if (!items.empty()) {
-        std::memcpy(img.data() + y.items, items.data(), 8 * items.size());
-        std::memcpy(img.data() + y.oitems, oitems.data(), 8 * oitems.size());
+        std::memcpy(img->data() + y.items, items.data(), 8 * items.size());
+        std::memcpy(img->data() + y.oitems, oitems.data(), 8 * oitems.size());
     }
-    std::memcpy(img.data() + y.tstart, tstart.data(), 8 * tstart.size());
-    hipError_t e = hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "batch control block copy");
-    for (int d = 0; d < nsets; ++d) {
-        if (sets[d].nQ == 0) continue;
-        const WsLayout w = ws_layout(sets[d].nQ, sets[d].refset->n, sets[d].refset->L);
-        const int L = sets[d].refset->L;
-        const int Wp = sets[d].refset->W < L - 1 ? sets[d].refset->W : L - 1;
-        if (int r = launch_cells_prefix(L, Wp, (uint32_t *)(base + y.set_off[d] + w.prefix), st)) return r;
+    std::memcpy(img->data() + y.tstart, tstart.data(), 8 * tstart.size());
+    hipError_t e = hipMemcpyAsync(ws, img->data(), img->size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        delete img;
+        return hip_fail(e, "batch control block copy");
     }
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "batch prepare synchronisation");
+    e = hipLaunchHostFunc(
+        st, [](void *p) { delete static_cast<std::vector<unsigned char> *>(p); }, img);
+    if (e != hipSuccess) {
+        // the copy is enqueued: wait for it before releasing its source
+        (void)hipStreamSynchronize(st);
+        delete img;
+        return hip_fail(e, "batch control block release");
+    }
 
     std::memset(plan, 0, sizeof(*plan));
     plan->magic = BATCH_PLAN_MAGIC;

@@ -350,6 +350,10 @@ batch_order_kernel(const BatchSet *__restrict__ sets, const int64_t *__restrict_
     const int64_t q = it & 0xFFFFFFFF;
     const BatchSet &b = sets[d];
     order_query<E, NT>(b.a.n, q, b.ed2w, b.lbk, b.lbeb, b.lbe, b.skw, b.slbkw, b.slbebw, b.slbew, smem);
+    // the set's first query also fills the set's cells table (read only by
+    // the search kernels, which follow on the stream)
+    if (q == 0 && threadIdx.x < WAVE)
+        cells_prefix_wave(b.a.geo.L, b.a.geo.Wp, const_cast<uint32_t *>(b.a.prefix), threadIdx.x);
 }
 
 int order_width(int64_t n)

@@ -2,14 +2,24 @@
 
 Requests (a query series for one of the resident sets) arrive over time.
 The loop batches them continuously: whenever one of its streams is free it
-admits the requests that have arrived, in arrival order, while the batch's
-device workspace stays within a memory budget, and launches one batched
-search (``BatchSearcher``: one bound pass, the sorts, the persistent
-searches) on that stream.  Batches on different streams overlap on the
-device; a request's latency runs from its arrival to the completion event of
-its batch.  Each request's result is that of a search of its query alone
-(same set, options, round size and engine shape): batching changes the
-schedule, not the computation.
+admits the requests that have arrived, in arrival order, as long as the
+batch's device workspace fits in the free part of one device-wide arena of
+``budget_bytes`` (shared by every batch in flight, released when a batch's
+completion event fires), and launches one batched search (one bound pass,
+the sorts, the persistent searches) on that stream.  Batches on different
+streams overlap on the device; a request's latency runs from its arrival to
+the completion event of its batch.
+
+Nothing on the admission path allocates device memory or waits for the
+device: the workspace is carved out of the arena, each stream owns
+preallocated query, output and pinned host result buffers, and
+``nndtw_batch_prepare`` only enqueues its copy.  Results come back by an
+asynchronous copy into the stream's pinned buffers, read once the batch's
+event has fired.
+
+Each request's result is that of a search of its query alone (same set,
+options, round size and engine shape): batching changes the schedule, not
+the computation.
 """
 from __future__ import annotations
 
@@ -19,7 +29,9 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import BatchSearcher, RefSet, _BatchSet, _check, _opts, lib
+from . import BatchSearcher, RefSet, _BatchPlan, _BatchSet, _check, _opts, lib
+
+ALIGN = 256
 
 
 @dataclass
@@ -44,93 +56,198 @@ def batch_bytes(refsets, counts, V=5, cascade="keogh_enh", waves=0):
     return int(nbytes.value)
 
 
+class Arena:
+    """First-fit suballocation of one device buffer (offsets aligned to 256
+    bytes).  ``alloc`` returns an offset or None; ``free`` returns a block."""
+
+    def __init__(self, nbytes: int, device):
+        self.size = (int(nbytes) // ALIGN) * ALIGN
+        self.buf = torch.empty(max(self.size, ALIGN), dtype=torch.uint8, device=device)
+        self.free_blocks = [(0, self.size)]          # sorted, coalesced (offset, size)
+        self.used = 0
+
+    def alloc(self, n: int):
+        n = -(-int(n) // ALIGN) * ALIGN
+        for k, (off, sz) in enumerate(self.free_blocks):
+            if sz >= n:
+                if sz == n:
+                    del self.free_blocks[k]
+                else:
+                    self.free_blocks[k] = (off + n, sz - n)
+                self.used += n
+                return off, n
+        return None
+
+    def free(self, block):
+        off, n = block
+        self.used -= n
+        blocks = self.free_blocks
+        k = 0
+        while k < len(blocks) and blocks[k][0] < off:
+            k += 1
+        blocks.insert(k, (off, n))
+        # coalesce with the neighbours
+        if k + 1 < len(blocks) and blocks[k][0] + blocks[k][1] == blocks[k + 1][0]:
+            blocks[k] = (blocks[k][0], blocks[k][1] + blocks[k + 1][1])
+            del blocks[k + 1]
+        if k > 0 and blocks[k - 1][0] + blocks[k - 1][1] == blocks[k][0]:
+            blocks[k - 1] = (blocks[k - 1][0], blocks[k - 1][1] + blocks[k][1])
+            del blocks[k]
+
+    def ptr(self, off: int):
+        return ctypes.c_void_p(self.buf.data_ptr() + off)
+
+
+class _Slot:
+    """One stream with its preallocated query staging, outputs and pinned
+    host result buffers (``max_batch`` queries of up to ``Lmax`` points)."""
+
+    def __init__(self, device, max_batch: int, Lmax: int):
+        self.stream = torch.cuda.Stream(device=device)
+        self.q = torch.empty(max_batch * Lmax, dtype=torch.float32, device=device)
+        self.idx = torch.empty(max_batch, dtype=torch.int64, device=device)
+        self.dist = torch.empty(max_batch, dtype=torch.float64, device=device)
+        self.counts = torch.empty((max_batch, 8), dtype=torch.int64, device=device)
+        self.h_idx = torch.empty(max_batch, dtype=torch.int64, pin_memory=True)
+        self.h_dist = torch.empty(max_batch, dtype=torch.float64, pin_memory=True)
+        self.h_counts = torch.empty((max_batch, 8), dtype=torch.int64, pin_memory=True)
+        self.plan = _BatchPlan()
+        self.event = torch.cuda.Event()
+
+
 class Server:
     """Continuous batching over ``refsets`` (a list of RefSet) on
-    ``n_streams`` streams, each batch at most ``max_batch`` requests and
-    ``budget_bytes`` of workspace.  ``R`` and ``cpl`` (per set or None) are
-    passed to every batch."""
+    ``n_streams`` streams; each batch holds at most ``max_batch`` requests,
+    and the workspaces of all batches in flight fit in ``budget_bytes``.
+    ``R`` and ``cpl`` (per set or None) are passed to every batch."""
 
     def __init__(self, refsets, n_streams: int = 3, max_batch: int = 512, budget_bytes: int = 1 << 30,
                  V: int = 5, R=None, cpl=None):
         self.refsets = list(refsets)
-        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        dev = self.refsets[0].device
         self.max_batch = max_batch
-        self.budget = budget_bytes
-        self.V, self.R, self.cpl = V, R, cpl
-        # workspace of one query per set, for admission by footprint
+        self.V = V
+        # workspace of one query per set: an upper bound of what each query
+        # adds to a batch (it includes the batch's fixed part once more)
         self.per_query = [batch_bytes([rs], [1], V) for rs in self.refsets]
+        if max(self.per_query) > budget_bytes:
+            raise ValueError(f"budget of {budget_bytes} bytes below one query's workspace {max(self.per_query)}")
+        self.arena = Arena(budget_bytes, dev)
+        Lmax = max(rs.L for rs in self.refsets)
+        self.slots = [_Slot(dev, max_batch, Lmax) for _ in range(n_streams)]
         # the round size and engine shape every batch uses per set (given, or
         # the batched search's defaults): a request's result is that of its
         # query searched alone with these
-        probe = BatchSearcher([(rs, torch.zeros((1, rs.L), dtype=torch.float32, device=rs.device))
+        probe = BatchSearcher([(rs, torch.zeros((1, rs.L), dtype=torch.float32, device=dev))
                                for rs in self.refsets], V=V, R=R, cpl=cpl)
         self.plan_R, self.plan_cpl = list(probe.R), list(probe.cpl)
         del probe
+        torch.cuda.synchronize(dev)
+        self.opts = _opts(V, "keogh_enh", 0, 0.0, True, 0)
+        self.stats = {}
 
-    def _launch(self, reqs, stream):
-        """One batched search over `reqs` on `stream`; returns (searcher,
-        event, per-request (set, row) positions)."""
+    def _launch(self, reqs, slot: _Slot, block):
+        """Enqueue one batched search over `reqs` on the slot's stream, its
+        workspace at arena block `block`; returns per-request result rows."""
         by_set = {}
         for r in reqs:
             by_set.setdefault(r.set_id, []).append(r)
         sets = sorted(by_set)
-        where = {}
-        R = [self.plan_R[s] for s in sets]
-        cpl = [self.plan_cpl[s] for s in sets]
-        with torch.cuda.stream(stream):
-            pairs = []
+        arr = (_BatchSet * len(sets))()
+        row_of = {}
+        qoff = row = 0
+        with torch.cuda.stream(slot.stream):
             for k, s in enumerate(sets):
                 rows = by_set[s]
-                pairs.append((self.refsets[s], torch.stack([r.query for r in rows])))
+                rs = self.refsets[s]
+                n = len(rows)
+                qv = slot.q[qoff:qoff + n * rs.L].view(n, rs.L)
+                torch.stack([r.query for r in rows], out=qv)
+                b = arr[k]
+                b.refset = ctypes.addressof(rs.desc)
+                b.Q, b.nQ = qv.data_ptr(), n
+                b.nn_idx = slot.idx[row:].data_ptr()
+                b.nn_dist = slot.dist[row:].data_ptr()
+                b.counts = slot.counts[row:].data_ptr()
+                b.R, b.cpl = self.plan_R[s], self.plan_cpl[s]
                 for j, r in enumerate(rows):
-                    where[r.rid] = (k, j)
-            bs = BatchSearcher(pairs, V=self.V, R=R, cpl=cpl)
-            bs()
-            ev = torch.cuda.Event()
-            ev.record(stream)
-        return bs, ev, where
+                    row_of[r.rid] = row + j
+                qoff += n * rs.L
+                row += n
+            st = ctypes.c_void_p(slot.stream.cuda_stream)
+            ws = self.arena.ptr(block[0])
+            _check(lib().nndtw_batch_prepare(arr, len(sets), ctypes.byref(self.opts), ws, block[1],
+                                             ctypes.byref(slot.plan), st))
+            _check(lib().nndtw_search_batch(ctypes.byref(slot.plan), ws, st))
+            slot.h_idx[:row].copy_(slot.idx[:row], non_blocking=True)
+            slot.h_dist[:row].copy_(slot.dist[:row], non_blocking=True)
+            slot.h_counts[:row].copy_(slot.counts[:row], non_blocking=True)
+            slot.event.record(slot.stream)
+        return row_of
+
+    def _need(self, reqs):
+        counts = {}
+        for r in reqs:
+            counts[r.set_id] = counts.get(r.set_id, 0) + 1
+        sets = sorted(counts)
+        return batch_bytes([self.refsets[s] for s in sets], [counts[s] for s in sets], self.V)
 
     def run(self, requests, poll_sleep: float = 0.0):
         """Serve `requests` (sorted by arrival time) in real time; returns
         them with completion times and results filled in, and a summary."""
         pending = list(requests)
         queue, inflight = [], []              # queue: arrived, not admitted
-        free = list(range(len(self.streams)))
+        free = list(range(len(self.slots)))
         t0 = time.perf_counter()
         nb = 0
         sizes = []
-        while pending or queue or inflight:
+        max_inflight = max_bytes = 0
+        head = 0
+        while head < len(pending) or queue or inflight:
             now = time.perf_counter() - t0
-            while pending and pending[0].arrival <= now:
-                queue.append(pending.pop(0))
+            while head < len(pending) and pending[head].arrival <= now:
+                queue.append(pending[head])
+                head += 1
             # completions
             still = []
-            for bs, ev, where, reqs, k in inflight:
-                if ev.query():
+            for k, block, row_of, reqs in inflight:
+                slot = self.slots[k]
+                if slot.event.query():
                     tdone = time.perf_counter() - t0
-                    outs = [(i.cpu(), d.cpu(), c.cpu()) for i, d, c in bs.out]
+                    idx, dist, counts = slot.h_idx.numpy(), slot.h_dist.numpy(), slot.h_counts.numpy()
                     for r in reqs:
-                        s, j = where[r.rid]
+                        j = row_of[r.rid]
                         r.done = tdone
-                        r.result = (int(outs[s][0][j]), float(outs[s][1][j]), outs[s][2][j].tolist())
+                        r.result = (int(idx[j]), float(dist[j]), counts[j].tolist())
+                    self.arena.free(block)
                     free.append(k)
                 else:
-                    still.append((bs, ev, where, reqs, k))
+                    still.append((k, block, row_of, reqs))
             inflight = still
-            # admissions: arrival order, within the batch size and the budget
+            # admissions: arrival order, within the batch size and the free
+            # part of the device-wide budget
             while queue and free:
-                batch, used = [], 0
+                avail = max((sz for _, sz in self.arena.free_blocks), default=0)
+                batch, est = [], 0
                 while queue and len(batch) < self.max_batch:
                     need = self.per_query[queue[0].set_id]
-                    if batch and used + need > self.budget:
+                    if est + need > avail:
                         break
-                    used += need
+                    est += need
                     batch.append(queue.pop(0))
+                if not batch:
+                    break                          # wait for memory to free up
+                block = self.arena.alloc(self._need(batch))
+                if block is None:                  # the estimate bounds the need: not reached
+                    queue[:0] = batch
+                    break
                 k = free.pop(0)
-                bs, ev, where = self._launch(batch, self.streams[k])
-                inflight.append((bs, ev, where, batch, k))
+                row_of = self._launch(batch, self.slots[k], block)
+                inflight.append((k, block, row_of, batch))
                 nb += 1
                 sizes.append(len(batch))
+                max_inflight = max(max_inflight, len(inflight))
+                max_bytes = max(max_bytes, self.arena.used)
             if poll_sleep:
                 time.sleep(poll_sleep)
         wall = time.perf_counter() - t0
@@ -141,6 +258,8 @@ class Server:
             "throughput_rps": n / wall,
             "latency_ms": {"p50": 1e3 * lat[n // 2], "p99": 1e3 * lat[min(n - 1, int(0.99 * n))],
                            "max": 1e3 * lat[-1]},
+            "max_batches_in_flight": max_inflight, "max_workspace_bytes": max_bytes,
+            "budget_bytes": self.arena.size,
         }
         return requests, summary
 
@@ -148,14 +267,21 @@ class Server:
 def poisson_requests(sets_L, rate: float, duration: float, seed: int, device, make_query):
     """Requests of a seeded Poisson stream at `rate` per second over
     `duration` seconds; each picks a set uniformly; make_query(set, L, k)
-    returns its float32 series (moved to `device` before the session)."""
+    returns its float32 series (moved to `device` before the session).
+    rate = inf gives every request at time 0 (a saturation run of
+    `duration` requests)."""
     import numpy as np
     rng = np.random.default_rng(seed)
     t, out = 0.0, []
+    n_sat = int(duration) if rate == float("inf") else -1
     while True:
-        t += rng.exponential(1.0 / rate)
-        if t > duration:
-            break
+        if n_sat >= 0:
+            if len(out) >= n_sat:
+                break
+        else:
+            t += rng.exponential(1.0 / rate)
+            if t > duration:
+                break
         s = int(rng.integers(0, len(sets_L)))
         out.append(Request(len(out), s, torch.from_numpy(make_query(s, sets_L[s], len(out))).to(device), t))
     return out

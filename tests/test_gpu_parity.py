@@ -695,6 +695,33 @@ def test_serving_results_equal_alone():
         assert r.result[0] == oi[0] and r.result[1] == od[0] and r.result[2][:5] == oc[0, :5].tolist()
 
 
+def test_serving_budget_and_overlap():
+    """All requests at once (a saturation run): batches overlap on the
+    streams, the workspaces of the batches in flight never exceed the
+    device-wide budget (which holds about two batches, so admissions wait for
+    memory), and every result equals its query searched alone."""
+    from paper_1808_09617_amd import serve
+    sets = synth.serving_sets(n_sets=5, n_refs=250, L_range=(40, 200))
+    rss = [nd.RefSet(dev(refs), W) for refs, W in sets]
+    Ls = [refs.shape[1] for refs, _ in sets]
+    reqs = serve.poisson_requests(Ls, rate=float("inf"), duration=240, seed=21, device=DEV,
+                                  make_query=lambda s, L, k: synth.serving_query(s, L, 5000 + k))
+    torch.cuda.synchronize()
+    budget = int(2.5 * 16 * max(serve.batch_bytes([rs], [1]) for rs in rss))
+    server = serve.Server(rss, n_streams=4, max_batch=16, budget_bytes=budget)
+    done, summary = server.run(reqs)
+    say("serving saturation", summary)
+    assert summary["max_batches_in_flight"] >= 2
+    assert summary["max_workspace_bytes"] <= budget
+    assert summary["batches"] >= 240 // 16
+    assert server.arena.used == 0 and server.arena.free_blocks == [(0, server.arena.size)]
+    for r in done:
+        i, d, c, _ = nd.search(rss[r.set_id], r.query[None], V=5, R=server.plan_R[r.set_id],
+                               cpl=server.plan_cpl[r.set_id])
+        assert r.result[0] == int(host(i)[0]) and r.result[1] == float(host(d)[0])
+        assert r.result[2][:5] == host(c)[0, :5].tolist()
+
+
 def test_serving_full_size():
     """Serving at the configured size: 8 resident sets of 4000 random walks,
     L_s = 64 .. 1024, W = 0.1 L_s, V = 5, a Poisson stream at 2000 requests/s.
