@@ -60,6 +60,8 @@ extern "C" {
  * (windows of up to 63 diagonal pairs with up to 6 pairs per lane);
  * nndtw_search_plan / nndtw_search return EUNSUP for the others. */
 #define NNDTW_SEARCH_MAX_WAVES 16
+/* Largest number of helper workgroups per query (nndtw_search_opts.helpers). */
+#define NNDTW_SEARCH_MAX_HELPERS 7
 
 /* Lower-bound cascades for nndtw_search. */
 #define NNDTW_CASCADE_NONE      0  /* DTW_W of every candidate (with abandon)        */
@@ -290,7 +292,13 @@ typedef struct nndtw_search_opts {
     int32_t engine;   /* DTW engine, NNDTW_ENGINE_*; 0 = library choice; out          */
     int64_t nq_hint;  /* nndtw_search_plan only: the query count to plan for (0 =
                        * many); nndtw_search plans for its own nQ                    */
-    int64_t reserved;
+    int32_t helpers;  /* helper workgroups per query of the DIAGONAL engine (0 =
+                       * default 3, -1 = none, at most NNDTW_SEARCH_MAX_HELPERS):
+                       * launched after the queries' own workgroups, a helper
+                       * joins its query if it is still running and takes DTW
+                       * tasks of its rounds through device-scope atomics; the
+                       * result and the defined counts do not change; out     */
+    int32_t reserved;
 } nndtw_search_opts;
 
 /* DTW engines of the search (opts->engine).  DIAGONAL: anti-diagonal

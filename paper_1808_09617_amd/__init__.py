@@ -30,6 +30,7 @@ COUNT_NAMES = ("n", "pruned_keogh", "pruned_enh_bands", "pruned_enh", "dtw_start
 MAX_L = 2048
 BATCH_MAX_N = 8192
 SEARCH_MAX_WAVES = 16
+SEARCH_MAX_HELPERS = 7
 SEARCH_SCRATCH_BYTES = 64 << 20
 REFSET_MAGIC = 0x4E444157
 
@@ -53,7 +54,7 @@ class _SearchOpts(ctypes.Structure):
     _fields_ = [("V", ctypes.c_int32), ("cascade", ctypes.c_int32), ("R", ctypes.c_int64),
                 ("eps", ctypes.c_double), ("init_ub", ctypes.c_int32), ("cpl", ctypes.c_int32),
                 ("events", ctypes.c_void_p), ("waves", ctypes.c_int32), ("engine", ctypes.c_int32),
-                ("nq_hint", ctypes.c_int64), ("reserved", ctypes.c_int64)]
+                ("nq_hint", ctypes.c_int64), ("helpers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _BatchSet(ctypes.Structure):
@@ -345,10 +346,11 @@ class RefSet:
         return self._view(which, (self.L, self.desc.pitch))[:, : self.n]
 
 
-def _opts(V, cascade, R, eps, init_ub, cpl, waves=0, engine="auto"):
+def _opts(V, cascade, R, eps, init_ub, cpl, waves=0, engine="auto", helpers=0):
     o = _SearchOpts()
     o.V, o.cascade, o.R, o.eps = int(V), CASCADES[cascade], int(R), float(eps)
     o.init_ub, o.cpl, o.waves, o.engine = int(bool(init_ub)), int(cpl), int(waves), ENGINES[engine]
+    o.helpers = int(helpers)
     return o
 
 
@@ -356,10 +358,11 @@ class Searcher:
     """Preallocated workspace for repeated nndtw_search calls on one RefSet."""
 
     def __init__(self, refset: RefSet, nQ: int, V: int = 5, cascade: str = "keogh_enh", R: int = 0,
-                 eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0, engine: str = "auto"):
+                 eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0, engine: str = "auto",
+                 helpers: int = 0):
         self.refset = refset
         self.nQ = int(nQ)
-        self.opts = _opts(V, cascade, R, eps, init_ub, cpl, waves, engine)
+        self.opts = _opts(V, cascade, R, eps, init_ub, cpl, waves, engine, helpers)
         nbytes = ctypes.c_size_t(0)
         _check(lib().nndtw_search_workspace_bytes(ctypes.byref(refset.desc), self.nQ, ctypes.byref(self.opts),
                                                   ctypes.byref(nbytes)))
@@ -394,6 +397,11 @@ class Searcher:
     @property
     def waves(self):
         return int(self.opts.waves)
+
+    @property
+    def helpers(self):
+        """Helper workgroups per query of the last call (0: none)."""
+        return max(0, int(self.opts.helpers))
 
     @property
     def engine(self):
@@ -451,22 +459,23 @@ class BatchSearcher:
 
 
 def search(refset: RefSet, Q: torch.Tensor, V: int = 5, cascade: str = "keogh_enh", R: int = 0,
-           eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0, engine: str = "auto"):
+           eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0, engine: str = "auto",
+           helpers: int = 0):
     """One-shot NN-DTW search: returns (nn_idx int64, nn_dist float64, counts int64[nQ][8], R used)."""
     Q = _series(Q, "Q")
-    s = Searcher(refset, Q.shape[0], V, cascade, R, eps, init_ub, cpl, waves, engine)
+    s = Searcher(refset, Q.shape[0], V, cascade, R, eps, init_ub, cpl, waves, engine, helpers)
     idx, dist, counts = s(Q)
     return idx.clone(), dist.clone(), counts.clone(), s.R
 
 
 def search_noalloc(refset: RefSet, Q: torch.Tensor, idx: torch.Tensor, dist: torch.Tensor, counts=None,
                    V: int = 5, cascade: str = "keogh_enh", R: int = 0, eps: float = 0.0, init_ub: bool = True,
-                   cpl: int = 0, waves: int = 0, engine: str = "auto"):
+                   cpl: int = 0, waves: int = 0, engine: str = "auto", helpers: int = 0):
     """nndtw_search_noalloc: the search into caller-provided outputs (idx int64
     [nQ], dist float64 [nQ], counts int64 [nQ][8] or None) with the library's
     fixed device workspace; returns the R used."""
     Q = _series(Q, "Q")
-    opts = _opts(V, cascade, R, eps, init_ub, cpl, waves, engine)
+    opts = _opts(V, cascade, R, eps, init_ub, cpl, waves, engine, helpers)
     _check(lib().nndtw_search_noalloc(ctypes.byref(refset.desc), _ptr(Q), Q.shape[0], ctypes.byref(opts), _ptr(idx),
                                       _ptr(dist), _ptr(counts), _stream()))
     return int(opts.R)

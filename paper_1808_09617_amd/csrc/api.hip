@@ -320,6 +320,8 @@ static int check_opts(const nndtw_search_opts *o)
             NNDTW_SEARCH_MAX_WAVES);
     REQUIRE(o->nq_hint >= 0, "nq_hint=%lld must be >= 0", (long long)o->nq_hint);
     REQUIRE(o->engine >= NNDTW_ENGINE_AUTO && o->engine <= NNDTW_ENGINE_STRIP, "engine=%d unknown", o->engine);
+    REQUIRE(o->helpers >= -1 && o->helpers <= NNDTW_SEARCH_MAX_HELPERS, "helpers=%d must be in -1..%d", o->helpers,
+            NNDTW_SEARCH_MAX_HELPERS);
     return NNDTW_OK;
 }
 
@@ -346,6 +348,7 @@ int nndtw_search_plan(const nndtw_refset *refset, nndtw_search_opts *opts)
     opts->cpl = plan.C;
     opts->waves = plan.NW;
     opts->engine = plan.S > 0 ? NNDTW_ENGINE_STRIP : NNDTW_ENGINE_DIAGONAL;
+    opts->helpers = plan.helpers > 0 ? plan.helpers : -1;
     return NNDTW_OK;
 }
 
@@ -374,6 +377,7 @@ int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ, nndtw_s
     opts->cpl = plan.C;
     opts->waves = plan.NW;
     opts->engine = plan.S > 0 ? NNDTW_ENGINE_STRIP : NNDTW_ENGINE_DIAGONAL;
+    opts->helpers = plan.helpers > 0 ? plan.helpers : -1;
     return launch_search(refset, Q, nQ, opts, plan, nn_idx, nn_dist, counts, ws, (hipStream_t)stream);
 }
 

@@ -51,7 +51,7 @@ Layout layout(const nndtw_batch_set *sets, int nsets)
     y.set_off.resize(nsets);
     for (int d = 0; d < nsets; ++d) {
         y.set_off[d] = o;
-        o = al256(o + ws_layout(sets[d].nQ, sets[d].refset->n, sets[d].refset->L).total);
+        o = al256(o + ws_layout(sets[d].nQ, sets[d].refset->n, sets[d].refset->L, false).total);
     }
     y.total = o;
     return y;
@@ -98,7 +98,7 @@ int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, 
 
         const int L = rs->L;
         const int64_t n = rs->n, nQ = sets[d].nQ;
-        const WsLayout w = ws_layout(nQ, n, L);
+        const WsLayout w = ws_layout(nQ, n, L, false);
         unsigned char *sb = base + y.set_off[d];
         BatchSet &b = bs[d];
         std::memset(&b, 0, sizeof(b));

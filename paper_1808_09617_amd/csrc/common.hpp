@@ -101,6 +101,7 @@ int launch_dtw_backward(bool f64, const float *A, int64_t nA, const float *B, in
 struct SearchPlan {
     int Wp, C, G, P, PD, SLOTS, NW, exact, T, LEN;
     int S;          // row-strip engine: columns per lane (0: anti-diagonal engine)
+    int helpers;    // helper workgroups per query
     int64_t R;
     double eps;
     size_t lds_bytes;
@@ -113,9 +114,10 @@ int launch_search(const nndtw_refset *rs, const float *Q, int64_t nQ, const nndt
                   const SearchPlan &plan, int64_t *nn_idx, double *nn_dist, int64_t *counts,
                   void *ws, hipStream_t s);
 struct WsLayout {
-    size_t ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, prefix, total;
+    size_t ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, prefix, share, total;
 };
-WsLayout ws_layout(int64_t nQ, int64_t n, int L);
+// share: with the per-query shared batches of helper workgroups (single-set search)
+WsLayout ws_layout(int64_t nQ, int64_t n, int L, bool share = true);
 int launch_cells_prefix(int L, int Wp, uint32_t *prefix, hipStream_t s);
 int order_width(int64_t n);     // visiting-order sort size class: npow = 256 * width
 int launch_batch_order(int E, const BatchSet *sets, const int64_t *items, int64_t nitems, hipStream_t s);
@@ -167,6 +169,23 @@ struct EngineGeom {
     int base0;  // series index of the first super-step's base
     int LEN;    // elements per staged series in LDS (with padding)
 };
+// The FP32 batch of one query that helper workgroups share (search.hip):
+// every field is read and written with device-scope atomics only.
+constexpr int SHARE_SLOTS = 256;
+struct QueryShare {
+    unsigned long long deal;  // (tag << 32) | next task index; tag = (epoch << 12) | batch
+    unsigned done;            // tasks of the current batch finished (by any workgroup)
+    unsigned nt;              // tasks in the current batch
+    unsigned thrF;            // the batch's FP32 threshold (bits)
+    unsigned helpers;         // (epoch << 12) | helper workgroups that joined in that call
+    unsigned finished;        // epoch of the last call in which the query finished
+    unsigned started;         // epoch of the last call in which the query's owner started
+    unsigned pad[8];
+    uint32_t cand[SHARE_SLOTS];
+    unsigned res[SHARE_SLOTS];
+    int trun[SHARE_SLOTS];
+};
+
 // Arguments of the per-query search (search.hip): one query against one
 // reference set, with the workspace of that set.
 struct SearchArgs {
@@ -192,6 +211,9 @@ struct SearchArgs {
     int64_t *counts;
     int ncu;           // compute units of the device (> 0: rotate the FP32
                        // engine's wave priority, see TaskOut)
+    QueryShare *share; // per query, or nullptr (no helper workgroups)
+    int64_t nq;        // queries (workgroups from nq on are helpers)
+    uint32_t epoch;    // this call's tag (1 .. 2^20 - 1)
 };
 
 // One reference set of a batched search: the search arguments plus what the

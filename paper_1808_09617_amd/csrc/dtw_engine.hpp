@@ -154,7 +154,40 @@ template <typename T> struct TaskOut {
     // Optional wave-priority rotation (>= 0: on, the workgroup's phase 0..3;
     // see rotate_priority), checked once per block of M super-steps.
     int rot_phase = -1;
+    // Optional shared batch (several workgroups, see search.hip): tasks are
+    // dealt from the global word *deal64 = (tag << 32) | next index instead
+    // of the LDS counter, only while its tag is `tag`, and res / trun are
+    // global memory written with device-scope atomic stores, each task then
+    // counted in *done.
+    unsigned long long *deal64 = nullptr;
+    uint32_t tag = 0;
+    unsigned *done = nullptr;
 };
+
+// The next `n` task indices of a shared batch (see TaskOut::deal64), or
+// `ntasks` once the batch has moved on (another tag) or is exhausted.  Whole
+// wave, uniform arguments; lane 0 runs the compare-and-swap loop and the
+// result is its value as a scalar.
+__device__ __forceinline__ int shared_deal(unsigned long long *deal64, uint32_t tag, int ntasks, int n, int lane)
+{
+    unsigned long long got = 0ull;
+    if (lane == 0) {
+        unsigned long long cur = __hip_atomic_load(deal64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (true) {
+            if ((uint32_t)(cur >> 32) != tag || (uint32_t)cur >= (uint32_t)ntasks) {
+                got = (unsigned long long)ntasks;
+                break;
+            }
+            unsigned long long want = cur + (unsigned long long)n;
+            if (__hip_atomic_compare_exchange_strong(deal64, &cur, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+                got = cur & 0xFFFFFFFFull;
+                break;
+            }
+        }
+    }
+    return __builtin_amdgcn_readfirstlane((int)got);
+}
 
 // Optional per-cell record of the minimising predecessor (for the argmin
 // warping path): codes(task) is the task's word array [T/8][W'+1]; the
@@ -257,8 +290,25 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
 #pragma unroll
                 for (int m = 0; m < C; ++m)
                     if (m == m0) r = (Wp & 1) ? X1[m] : X0[m];
-                out.res[task] = dead ? INF : r;
-                out.trun[task] = dead ? tl : T_;
+                if constexpr (sizeof(T) == 4) {
+                    if (out.deal64 != nullptr) {
+                        // shared batch: device-scope stores, complete before
+                        // the task is counted
+                        __hip_atomic_store(reinterpret_cast<unsigned *>(out.res) + task,
+                                           __float_as_uint(dead ? INF : r), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(out.trun + task, dead ? tl : T_, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __builtin_amdgcn_s_waitcnt(0);
+                        __hip_atomic_fetch_add(out.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        out.res[task] = dead ? INF : r;
+                        out.trun[task] = dead ? tl : T_;
+                    }
+                } else {
+                    out.res[task] = dead ? INF : r;
+                    out.trun[task] = dead ? tl : T_;
+                }
                 if constexpr (sizeof(T) == 4) {
                     if (out.run_thr != nullptr && !dead)
                         atomicMin(out.run_thr, __float_as_uint(round_up_f32((double)r * out.slack)));
@@ -273,7 +323,9 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
         if (nfree > 0 && !exhausted) {
             // whole-wave fetch (lane 0 adds nfree, the others 0), lane 0's
             // result as a scalar: no lane-dependent branch around the deal
-            const int base = __builtin_amdgcn_readfirstlane(atomicAdd(next_task, lane == 0 ? nfree : 0));
+            const int base = out.deal64 != nullptr
+                                 ? shared_deal(out.deal64, out.tag, ntasks, nfree, lane)
+                                 : __builtin_amdgcn_readfirstlane(atomicAdd(next_task, lane == 0 ? nfree : 0));
             const int left = ntasks - base;
             const int nassign = left < nfree ? (left > 0 ? left : 0) : nfree;
             exhausted = left <= nfree;

@@ -34,6 +34,7 @@
 // the recomputed distances are bit-identical to a sequential FP64 evaluation
 // of the recurrence, so every decision is taken on the same values.
 #include <algorithm>
+#include <atomic>
 
 #include "strip_engine.hpp"
 
@@ -49,11 +50,16 @@ constexpr int QCAP = 512;        // survivor ring (>= the largest batch + one ch
 constexpr int SEARCH_MAX_WAVES = 8;        // workgroup size of the search kernels (waves)
 constexpr int SEARCH_WIDE_WAVES = NNDTW_SEARCH_MAX_WAVES;   // ... of the wide ones
 constexpr int SEARCH_DEFAULT_WAVES = 4;
+constexpr int SEARCH_DEFAULT_HELPERS = 3;
+// Engine shapes whose search kernels hold the shared-batch code (helper
+// workgroups): 3 and 6 pairs per lane fill the 128 registers they are held
+// to without it, and would spill with it.
+__host__ __device__ constexpr bool share_ok(int C) { return C != 3 && C != 6; }
 constexpr int ORDER_THREADS = 256;
 
 // ------------------------------------------------------------ workspace
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
-WsLayout ws_layout(int64_t nQ, int64_t n, int L)
+WsLayout ws_layout(int64_t nQ, int64_t n, int L, bool share)
 {
     WsLayout w;
     const size_t m = (size_t)nQ * (size_t)n;
@@ -67,6 +73,7 @@ WsLayout ws_layout(int64_t nQ, int64_t n, int L)
     w.slbeb = o; o = al256(o + m * 8);
     w.slbe = o;  o = al256(o + m * 8);
     w.prefix = o; o = al256(o + (size_t)(2 * L) * 4);
+    w.share = o;  o = al256(o + (share ? (size_t)nQ * sizeof(QueryShare) : 0));
     w.total = o;
     return w;
 }
@@ -498,7 +505,8 @@ __device__ __forceinline__ int stage_of(int cascade, double b1, double b2, doubl
 // S > 0: the row-strip engine (strip_engine.hpp, S columns per lane, one
 // candidate per wave) runs both the FP32 DTWs and the FP64 rechecks instead
 // (C, EXACT and RK are then unused); WIN: the window constrains.
-template <int C, bool EXACT, int RK = 0, int S = 0, bool WIN = true>
+// SHARE: the code of shared batches (helper workgroups) is compiled in.
+template <int C, bool EXACT, int RK = 0, int S = 0, bool WIN = true, bool SHARE = true>
 __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t q, unsigned char *smem)
 {
     const EngineGeom &geo = a.geo, &geoD = a.geoD;
@@ -515,6 +523,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     uint32_t *rq = ring + QCAP;      // qualifying candidates of a batch
     int *next_task = reinterpret_cast<int *>(rq + SLOTS);
     unsigned *run_thr = reinterpret_cast<unsigned *>(next_task + 1);
+    int *flags = reinterpret_cast<int *>(run_thr + 1);    // [0] shared batch, [1] wait timed out
 
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (WAVE - 1);
@@ -522,6 +531,9 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     const int64_t N = a.n;
     const int L = geo.L;
     const int64_t qo = q * N;
+    constexpr bool SH = SHARE && S == 0 && share_ok(C);
+    QueryShare *const sh = (SH && a.share != nullptr) ? a.share + q : nullptr;
+    uint32_t seq = 0;                    // shared batches of this query so far
     // A candidate's FP32 row is read straight from the padded copy: element e
     // of the row the engines see is series index base0 - PADL + e (base0 is
     // the same in both geometries).
@@ -540,7 +552,12 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     // Smallest completed FP32 result so far, widened by the FP32 error slack
     // (see the recheck rule below): a DTW whose frontier exceeds it cannot tie
     // or beat that result, so it is abandoned.  Pruning still uses thr.
-    if (tid == 0) *run_thr = __float_as_uint(__builtin_inff());
+    if (tid == 0) {
+        *run_thr = __float_as_uint(__builtin_inff());
+        flags[1] = 0;
+        if (sh != nullptr)
+            __hip_atomic_store(&sh->started, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
 
     const double ub = a.init_ub ? a.ed2[qo + a.sk[qo]] : INF;
@@ -565,8 +582,18 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
         // results that can decide the round.
         auto run_batch = [&](int nt) {
             const int h0 = qh;
+            // A batch is shared with the query's helper workgroups (see
+            // help_query) once one has joined; until then it stays in LDS.
+            if (sh != nullptr) {
+                if (tid == 0) {
+                    const unsigned hv = __hip_atomic_load(&sh->helpers, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    flags[0] = ((hv >> 12) == a.epoch && (hv & 0xFFFu) != 0u) ? 1 : 0;
+                }
+            }
             if (tid == 0) *next_task = 0;
             __syncthreads();
+            bool shared = false;
+            if constexpr (SH) shared = sh != nullptr && __builtin_amdgcn_readfirstlane(flags[0]) != 0;
             if constexpr (S > 0) {
                 // trunF receives the band cells each task evaluated
                 strip_run<float, S, WIN>(
@@ -574,10 +601,68 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                     [&](int i) { return a.B + (int64_t)ring[(h0 + i) % QCAP] * L; }, [&](int) { return thrF; },
                     resF, trunF, run_thr, 1.0 + 2.0 * a.eps, rot_phase);
             } else {
+                TaskOut<float> to{resF, trunF, run_thr, 1.0 + 2.0 * a.eps, rot_phase};
+                if (shared) {
+                    // publish the batch (candidates, size, threshold, a zero
+                    // count), then its tag: the stores are complete before
+                    // the tag is, so a workgroup that sees the tag reads this
+                    // batch
+                    ++seq;
+                    const uint32_t tag = (a.epoch << 12) | (seq & 0xFFFu);
+                    for (int i = tid; i < nt; i += nthr)
+                        __hip_atomic_store(&sh->cand[i], ring[(h0 + i) % QCAP], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (tid == 0) {
+                        __hip_atomic_store(&sh->nt, (unsigned)nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&sh->thrF, __float_as_uint(thrF), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&sh->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
+                    if (tid == 0) {
+                        __hip_atomic_store(&sh->deal, (unsigned long long)tag << 32, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __builtin_amdgcn_s_waitcnt(0);
+                    }
+                    __syncthreads();
+                    to.res = reinterpret_cast<float *>(sh->res);
+                    to.trun = sh->trun;
+                    to.deal64 = &sh->deal;
+                    to.tag = tag;
+                    to.done = &sh->done;
+                }
                 engine_run<float, C, DG, MG, EXACT>(
                     geo, nt, next_task, [&](int) { return (const float *)aF; },
-                    [&](int i) { return Bp + (int64_t)ring[(h0 + i) % QCAP] * a.ppitch; },
-                    [&](int) { return thrF; }, TaskOut<float>{resF, trunF, run_thr, 1.0 + 2.0 * a.eps, rot_phase});
+                    [&](int i) {
+                        const uint32_t k = shared ? __hip_atomic_load(&sh->cand[i], __ATOMIC_RELAXED,
+                                                                       __HIP_MEMORY_SCOPE_AGENT)
+                                                  : ring[(h0 + i) % QCAP];
+                        return Bp + (int64_t)k * a.ppitch;
+                    },
+                    [&](int) { return thrF; }, to);
+                if (shared) {
+                    // every task dealt has been taken by a running workgroup:
+                    // wait until all are counted (bounded; a time-out is
+                    // reported as index -2)
+                    if (tid == 0) {
+                        int spins = 0;
+                        while (__hip_atomic_load(&sh->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                               (unsigned)nt) {
+                            __builtin_amdgcn_s_sleep(2);
+                            if (++spins > (1 << 22)) {
+                                flags[1] = 1;
+                                break;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    for (int i = tid; i < nt; i += nthr) {
+                        resF[i] = __uint_as_float(
+                            __hip_atomic_load(&sh->res[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        trunF[i] = __hip_atomic_load(&sh->trun[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
             }
             __syncthreads();
             // the batch's results, 64 tasks per pass: counts and the
@@ -715,6 +800,8 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
         pos = re;
     }
 
+    if (sh != nullptr && tid == 0)
+        __hip_atomic_store(&sh->finished, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!w0) return;
     c_pk = wave_sum(c_pk);
     c_peb = wave_sum(c_peb);
@@ -724,7 +811,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     c_rc = wave_sum(c_rc);
     c_cells = wave_sum(c_cells);
     if (lane == 0) {
-        a.nn_idx[q] = bk;
+        a.nn_idx[q] = flags[1] ? -2 : bk;
         a.nn_dist[q] = bsf;
         if (a.counts) {
             int64_t *c = a.counts + q * NNDTW_NCOUNTS;
@@ -740,6 +827,100 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     }
 }
 
+// A helper workgroup of query q: it takes DTW tasks of the query's shared
+// FP32 batches (QueryShare) until the query finishes.  The owner never waits
+// for a helper: it shares a batch only once a helper has joined, and then
+// waits only for tasks that a running workgroup has taken.  A helper that
+// finds its query finished, or not started, leaves at once.
+template <int C, bool EXACT>
+__device__ __forceinline__ void help_query(const SearchArgs &a, const int64_t q, unsigned char *smem)
+{
+    const EngineGeom &geo = a.geo, &geoD = a.geoD;
+    const int LENA = staged_len(geo, geoD);
+    constexpr int DG = prefetch_global(C), MG = window_global(C);
+    float *aF = reinterpret_cast<float *>(smem);
+    int *ctl = reinterpret_cast<int *>(aF + ((LENA + 1) & ~1));   // next task, go, nt, threshold, tag
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    QueryShare *const sh = a.share + q;
+    if (tid == 0) {
+        int go = 0;
+        // the owner may be starting at the same time: wait for it briefly
+        // (a few hundred microseconds), but never for an owner that is not
+        // running yet
+        bool started = false;
+        for (int k = 0; k < 256 && !started; ++k) {
+            started = __hip_atomic_load(&sh->started, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.epoch;
+            if (!started) __builtin_amdgcn_s_sleep(16);
+        }
+        if (started && __hip_atomic_load(&sh->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != a.epoch) {
+            unsigned cur = __hip_atomic_load(&sh->helpers, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while (true) {
+                const unsigned want = (cur >> 12) == a.epoch ? cur + 1u : ((a.epoch << 12) | 1u);
+                if (__hip_atomic_compare_exchange_strong(&sh->helpers, &cur, want, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    break;
+            }
+            go = 1;
+        }
+        ctl[1] = go;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(ctl[1]) == 0) return;
+    {
+        EngineGeom ga = geo;
+        ga.LEN = LENA;
+        stage_rows<float, C>(aF, a.Q, [&](int) { return q; }, 1, ga, tid, nthr);
+    }
+    const float *Bp = a.Bp + (a.padl + geo.base0 - Stage<C>::PADL);
+    const int64_t N = a.n;
+    uint32_t last = 0u;
+    int idle = 0;
+    while (true) {
+        __syncthreads();
+        if (tid == 0) {
+            int go = 0;
+            const unsigned long long d = __hip_atomic_load(&sh->deal, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t tag = (uint32_t)(d >> 32);
+            if (__hip_atomic_load(&sh->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.epoch) {
+                go = -1;
+            } else if ((tag >> 12) == a.epoch && tag != last) {
+                const unsigned nt = __hip_atomic_load(&sh->nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint32_t)d < nt && nt <= (unsigned)SHARE_SLOTS) {
+                    go = 1;
+                    ctl[2] = (int)nt;
+                    ctl[3] = (int)__hip_atomic_load(&sh->thrF, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ctl[4] = (int)tag;
+                }
+            }
+            ctl[1] = go;
+            ctl[0] = 0;
+        }
+        __syncthreads();
+        const int go = __builtin_amdgcn_readfirstlane(ctl[1]);
+        if (go < 0) break;
+        if (go > 0) {
+            const uint32_t tag = (uint32_t)__builtin_amdgcn_readfirstlane(ctl[4]);
+            const float thrF = __uint_as_float((unsigned)__builtin_amdgcn_readfirstlane(ctl[3]));
+            const int nt = __builtin_amdgcn_readfirstlane(ctl[2]);
+            engine_run<float, C, DG, MG, EXACT>(
+                geo, nt, ctl, [&](int) { return (const float *)aF; },
+                [&](int i) {
+                    uint32_t k = __hip_atomic_load(&sh->cand[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    k = k < (uint32_t)N ? k : 0u;     // an index of the set (the owner writes only such)
+                    return Bp + (int64_t)k * a.ppitch;
+                },
+                [&](int) { return thrF; },
+                TaskOut<float>{reinterpret_cast<float *>(sh->res), sh->trun, nullptr, 1.0, -1, &sh->deal, tag,
+                               &sh->done});
+            last = tag;
+            idle = 0;
+        } else {
+            if (++idle > (1 << 20)) break;
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+}
+
 // Kernels whose registers allow it (no scratch spill) are held to 128 VGPRs,
 // so that two workgroups of 8 waves (a query each) share a compute unit:
 // 512 queries run at once instead of 256, and a query with much more work
@@ -751,6 +932,12 @@ __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES)
 search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    if constexpr (share_ok(C)) {
+        if (a.share != nullptr && (int64_t)blockIdx.x >= a.nq) {
+            help_query<C, EXACT>(a, ((int64_t)blockIdx.x - a.nq) % a.nq, smem);
+            return;
+        }
+    }
     search_query<C, EXACT, RK>(a, blockIdx.x, smem);
 }
 
@@ -762,7 +949,28 @@ __global__ void __launch_bounds__(WAVE * SEARCH_WIDE_WAVES) __attribute__((amdgp
 search_kernel_wide(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    if constexpr (share_ok(C)) {
+        if (a.share != nullptr && (int64_t)blockIdx.x >= a.nq) {
+            help_query<C, EXACT>(a, ((int64_t)blockIdx.x - a.nq) % a.nq, smem);
+            return;
+        }
+    }
     search_query<C, EXACT, C == 1 ? 2 : 1>(a, blockIdx.x, smem);
+}
+
+// Resets the shared-batch headers of nq queries (before a search with
+// helper workgroups, so that nothing left in the workspace matches the call).
+__global__ void __launch_bounds__(256) share_reset_kernel(QueryShare *share, int64_t nq)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq) {
+        share[q].deal = 0ull;
+        share[q].done = 0u;
+        share[q].nt = 0u;
+        share[q].helpers = 0u;
+        share[q].finished = 0u;
+        share[q].started = 0u;
+    }
 }
 
 // Whether a plan may use more than SEARCH_MAX_WAVES waves (search_kernel_wide).
@@ -803,7 +1011,7 @@ batch_search_kernel(const BatchSet *__restrict__ sets, const int64_t *__restrict
         if (i >= nitems) break;
         const int64_t it = items[i];
         const int d = __builtin_amdgcn_readfirstlane((int)(it >> 32));
-        search_query<C, EXACT>(sets[d].a, it & 0xFFFFFFFF, smem);
+        search_query<C, EXACT, 0, 0, true, false>(sets[d].a, it & 0xFFFFFFFF, smem);
     }
 }
 
@@ -849,7 +1057,7 @@ int device_cu_count()
 size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD)
 {
     const int LENA = staged_len(g, gd);
-    return (size_t)((LENA + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 12 + QCAP * 4 + 16;
+    return (size_t)((LENA + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 12 + QCAP * 4 + 32;
 }
 
 // Plan of the search with the row-strip engine.
@@ -875,7 +1083,7 @@ static int plan_search_strip(const nndtw_refset *rs, const nndtw_search_opts *o,
     // one candidate per wave: the same default round as the diagonal engine
     const int64_t R = o->R > 0 ? o->R : (2 * NW > 256 ? 2 * NW : 256);
     const int SLOTS = 256, PD = 64;
-    const size_t lds = (size_t)((L + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 12 + QCAP * 4 + 16;
+    const size_t lds = (size_t)((L + 1) & ~1) * 4 + (size_t)PD * 12 + (size_t)SLOTS * 12 + QCAP * 4 + 32;
     *plan = SearchPlan{};
     plan->Wp = Wp;
     plan->C = 0;
@@ -997,6 +1205,13 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     plan->LEN = g.LEN;
     plan->R = R;
     plan->S = 0;
+    // Helper workgroups per query (help_query): they start once the owners
+    // have been dispatched, so they serve the queries still running then,
+    // which are the heavy ones (the kernel lasts as long as its heaviest
+    // query).  Not in the batched search (persistent workgroups).
+    plan->helpers = (batched || !share_ok(C)) ? 0
+                                               : (o->helpers > 0 ? o->helpers
+                                                                 : (o->helpers < 0 ? 0 : SEARCH_DEFAULT_HELPERS));
     plan->lds_bytes = lds;
     return plan_eps(L, o, plan);
 }
@@ -1078,6 +1293,21 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     a.nn_dist = nn_dist;
     a.counts = counts;
     a.ncu = device_cu_count();
+    a.share = nullptr;
+    a.nq = nQ;
+    a.epoch = 0;
+    int64_t grid = nQ;
+    if (plan.S == 0 && plan.helpers > 0) {
+        // helper workgroups (help_query) follow the nQ owners in dispatch order
+        static std::atomic<uint32_t> g_epoch{0};
+        a.epoch = (g_epoch.fetch_add(1u) % 0xFFFFFu) + 1u;
+        a.share = (QueryShare *)(base + w.share);
+        grid = nQ * (1 + plan.helpers);
+        if (grid > 0x7FFFFFFF) grid = nQ;
+        hipLaunchKernelGGL(share_reset_kernel, dim3((unsigned)ceil_div(nQ, 256)), dim3(256), 0, st, a.share, nQ);
+        NNDTW_LAUNCH_CHECK("share reset kernel launch");
+        if (grid == nQ) a.share = nullptr;
+    }
     const size_t lds = plan.lds_bytes;
     if (plan.S > 0) {
         const bool win = plan.Wp < L - 1;
@@ -1101,10 +1331,10 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
         switch (plan.C * 2 + (plan.exact ? 1 : 0)) {
 #define X(c)                                                                                                    \
     case c * 2:                                                                                                 \
-        hipLaunchKernelGGL((search_kernel_wide<c, false>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a); \
+        hipLaunchKernelGGL((search_kernel_wide<c, false>), dim3((unsigned)grid), dim3(WAVE * plan.NW), lds, st, a); \
         break;                                                                                                  \
     case c * 2 + 1:                                                                                             \
-        hipLaunchKernelGGL((search_kernel_wide<c, true>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);  \
+        hipLaunchKernelGGL((search_kernel_wide<c, true>), dim3((unsigned)grid), dim3(WAVE * plan.NW), lds, st, a);  \
         break;
             X(1) X(2) X(3) X(4) X(6)
 #undef X
@@ -1119,16 +1349,16 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     switch (plan.C * 4 + (plan.exact ? 2 : 0) + (rk1 ? 1 : 0)) {
 #define X(c)                                                                                                       \
     case c * 4 + 0:                                                                                                \
-        hipLaunchKernelGGL((search_kernel<c, false, 2>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);   \
+        hipLaunchKernelGGL((search_kernel<c, false, 2>), dim3((unsigned)grid), dim3(WAVE * plan.NW), lds, st, a);   \
         break;                                                                                                     \
     case c * 4 + 1:                                                                                                \
-        hipLaunchKernelGGL((search_kernel<c, false, 1>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);   \
+        hipLaunchKernelGGL((search_kernel<c, false, 1>), dim3((unsigned)grid), dim3(WAVE * plan.NW), lds, st, a);   \
         break;                                                                                                     \
     case c * 4 + 2:                                                                                                \
-        hipLaunchKernelGGL((search_kernel<c, true, 2>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);    \
+        hipLaunchKernelGGL((search_kernel<c, true, 2>), dim3((unsigned)grid), dim3(WAVE * plan.NW), lds, st, a);    \
         break;                                                                                                     \
     case c * 4 + 3:                                                                                                \
-        hipLaunchKernelGGL((search_kernel<c, true, 1>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);    \
+        hipLaunchKernelGGL((search_kernel<c, true, 1>), dim3((unsigned)grid), dim3(WAVE * plan.NW), lds, st, a);    \
         break;
         NNDTW_FOR_EACH_CPL(X)
 #undef X

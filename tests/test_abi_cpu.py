@@ -58,7 +58,7 @@ def test_struct_layouts():
     assert nd._SearchOpts.eps.offset == 16 and nd._SearchOpts.events.offset == 32
     assert nd._SearchOpts.waves.offset == 40 and nd._SearchOpts.engine.offset == 44
     assert nd._SearchOpts.nq_hint.offset == 48
-    assert nd._SearchOpts.reserved.offset == 56
+    assert nd._SearchOpts.helpers.offset == 56 and nd._SearchOpts.reserved.offset == 60
 
 
 def _err(status, fragment):
@@ -239,8 +239,12 @@ def test_search_plan_has_a_shape_for_every_window():
             if _strip_chosen(L, Wp):
                 assert opts.engine == nd.ENGINES["strip"] and opts.cpl == 0, (L, W)
                 assert opts.waves == 4 and opts.R == 256, (L, W, opts.waves, opts.R)
+                assert opts.helpers == -1                          # no helper workgroups on strips
             else:
                 assert opts.engine == nd.ENGINES["diagonal"], (L, W)
+                # 3 helper workgroups per query, except for the shapes whose
+                # kernels hold no shared-batch code (3 and 6 pairs per lane)
+                assert opts.helpers == (-1 if opts.cpl in (3, 6) else 3), (L, W, opts.cpl, opts.helpers)
                 C = opts.cpl
                 G = -(-(Wp + 1) // C)
                 assert C in (1, 2, 3, 4, 6, 8, 9) and G <= 63, (L, W, C, G)
@@ -278,6 +282,13 @@ def test_search_plan_has_a_shape_for_every_window():
     opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0)
     opts.engine = 3
     assert _err(lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)), "engine=3") == nd.EINVAL
+    for bad in (-2, nd.SEARCH_MAX_HELPERS + 1):
+        opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, helpers=bad)
+        assert _err(lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)), f"helpers={bad}") == nd.EINVAL
+    d.L, d.W = 512, 51                                             # 4 pairs per lane
+    for h, want in ((-1, -1), (0, 3), (5, 5)):
+        opts = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, helpers=h)
+        assert lib.nndtw_search_plan(ctypes.byref(d), ctypes.byref(opts)) == 0 and opts.helpers == want
 
 
 def test_search_kernels_fit_the_register_file():

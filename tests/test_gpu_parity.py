@@ -194,17 +194,18 @@ def test_dtw_tightness_pairs_zip():
 
 
 # ------------------------------------------------------------------ search
-def run_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, waves=0, engine="auto"):
+def run_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, waves=0, engine="auto",
+               helpers=0):
     rs = nd.RefSet(dev(refs), W)
     idx, dist, counts, R_used = nd.search(rs, dev(queries), V=V, cascade=cascade, R=R, init_ub=init_ub, cpl=cpl,
-                                          waves=waves, engine=engine)
+                                          waves=waves, engine=engine, helpers=helpers)
     return host(idx), host(dist), host(counts), R_used
 
 
 def check_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, brute=True, waves=0,
-                 engine="auto"):
-    say("search", refs.shape, queries.shape, W, V, cascade, R, init_ub, cpl, waves, engine)
-    gi, gd, gc, R_used = run_search(refs, queries, W, V, cascade, R, init_ub, cpl, waves, engine)
+                 engine="auto", helpers=0):
+    say("search", refs.shape, queries.shape, W, V, cascade, R, init_ub, cpl, waves, engine, helpers)
+    gi, gd, gc, R_used = run_search(refs, queries, W, V, cascade, R, init_ub, cpl, waves, engine, helpers)
     oi, od, oc = oracle.search(refs, queries, W, V, cascade, R_used, init_ub)
     assert np.array_equal(gi, oi), ("nn_idx", np.nonzero(gi != oi))
     assert np.array_equal(gd, od), ("nn_dist", np.max(np.abs(gd - od)))
@@ -351,6 +352,50 @@ def test_search_strip_engine(L, W):
     for V in (1, 5):
         check_search(refs, queries, W, V, "keogh_enh", 0, True, 0, brute=V == 1, engine="strip")
     check_search(refs, queries, W, 2, "keogh_enh", 7, False, 0, brute=False, engine="strip")
+
+
+def _helpers_joined(searcher, n, L, nq):
+    """Helper workgroups that joined each query in the last call, read from
+    the workspace (the shared-batch headers follow the bound and order
+    arrays and the cells table; QueryShare: 3136 bytes, helpers word at byte
+    20 = (call tag << 12) | count)."""
+    al = lambda x: (x + 255) // 256 * 256
+    m = nq * n
+    off = 4 * al(8 * m) + al(4 * m) + 3 * al(8 * m) + al(8 * L)
+    raw = searcher.ws[off: off + nq * 3136].cpu().numpy().view(np.uint32).reshape(nq, 3136 // 4)
+    say("share header of query 0 (deal lo/hi, done, nt, thrF, helpers, finished, started):", raw[0, :8].tolist())
+    return raw[:, 5] & 0xFFF
+
+
+@pytest.mark.parametrize("W,helpers", [(12, -1), (12, 1), (12, 3), (12, 7), (40, 7)])
+def test_search_helper_workgroups(W, helpers):
+    """Helper workgroups (launched after the queries' own, they take DTW tasks
+    of the queries still running) change neither the result nor the defined
+    counts: against the oracle at the same R, with few enough queries that
+    the helpers start at once and join every query."""
+    L = 128
+    refs = series(3000, L, seed=810 + W, kind="rw")
+    queries = series(24, L, seed=811 + W, kind="rw")
+    check_search(refs, queries, W, 3, "keogh_enh", 0, True, 0, brute=False, helpers=helpers)
+    if helpers <= 0:
+        return
+    rs = nd.RefSet(dev(refs), W)
+    s = nd.Searcher(rs, 24, V=3, helpers=helpers)
+    s(dev(queries))
+    torch.cuda.synchronize()
+    joined = _helpers_joined(s, 3000, L, 24)
+    say("helpers", W, helpers, "engine", s.engine, "cpl", s.cpl, "joined", joined.tolist())
+    assert s.cpl not in (3, 6) and s.helpers == helpers
+    assert np.all(joined == helpers)              # every helper joined its query
+
+
+def test_search_helpers_headline_shape():
+    """The headline launch shape (5000 references, L=512, W=51, 16 waves per
+    query, 4 pairs per lane) with 7 helpers per query for 40 queries: every
+    query against the oracle."""
+    wl = synth.workload("nndtw-mix512", n_refs=5000, n_queries=500)
+    qs = np.ascontiguousarray(wl.queries[::12][:40])
+    check_search(wl.refs, qs, 51, 5, "keogh_enh", 0, True, 0, brute=False, helpers=7)
 
 
 @pytest.mark.parametrize("L,W", [(40, 15), (256, 100), (512, 128), (600, 566)])
