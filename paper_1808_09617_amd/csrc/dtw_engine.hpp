@@ -167,20 +167,27 @@ template <typename T> struct TaskOut {
 // The next `n` task indices of a shared batch (see TaskOut::deal64), or
 // `ntasks` once the batch has moved on (another tag) or is exhausted.  Whole
 // wave, uniform arguments; lane 0 runs the compare-and-swap loop and the
-// result is its value as a scalar.
+// result is its value as a scalar.  The lane test goes through an empty asm
+// statement, so that the compiler cannot relate it to the engines' lane-0
+// result stores: with both plain `lane == 0` tests in one task loop it once
+// merged them across the loop's back edge and sent lanes 1-63 round the task
+// loop without lane 0, re-reading task 0 forever.  (Every lane issuing the
+// compare-and-swap avoids the branch but made each deal 64 atomics on one
+// word: the search ran several times slower.)
 __device__ __forceinline__ int shared_deal(unsigned long long *deal64, uint32_t tag, int ntasks, int n, int lane)
 {
+    int first = lane == 0;
+    asm volatile("" : "+v"(first));
     unsigned long long got = 0ull;
-    if (lane == 0) {
+    if (first) {
         unsigned long long cur = __hip_atomic_load(deal64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         while (true) {
             if ((uint32_t)(cur >> 32) != tag || (uint32_t)cur >= (uint32_t)ntasks) {
                 got = (unsigned long long)ntasks;
                 break;
             }
-            unsigned long long want = cur + (unsigned long long)n;
-            if (__hip_atomic_compare_exchange_strong(deal64, &cur, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+            if (__hip_atomic_compare_exchange_strong(deal64, &cur, cur + (unsigned long long)n, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 got = cur & 0xFFFFFFFFull;
                 break;
             }

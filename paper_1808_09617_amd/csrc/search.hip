@@ -531,7 +531,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     const int64_t N = a.n;
     const int L = geo.L;
     const int64_t qo = q * N;
-    constexpr bool SH = SHARE && S == 0 && share_ok(C);
+    constexpr bool SH = SHARE && (S > 0 || share_ok(C));
     QueryShare *const sh = (SH && a.share != nullptr) ? a.share + q : nullptr;
     uint32_t seq = 0;                    // shared batches of this query so far
     // A candidate's FP32 row is read straight from the padded copy: element e
@@ -594,38 +594,44 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
             __syncthreads();
             bool shared = false;
             if constexpr (SH) shared = sh != nullptr && __builtin_amdgcn_readfirstlane(flags[0]) != 0;
+            uint32_t tag = 0u;
+            if (shared) {
+                // publish the batch (candidates, size, threshold, a zero
+                // count), then its tag: the stores are complete before the
+                // tag is, so a workgroup that sees the tag reads this batch
+                ++seq;
+                tag = (a.epoch << 12) | (seq & 0xFFFu);
+                for (int i = tid; i < nt; i += nthr)
+                    __hip_atomic_store(&sh->cand[i], ring[(h0 + i) % QCAP], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (tid == 0) {
+                    __hip_atomic_store(&sh->nt, (unsigned)nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&sh->thrF, __float_as_uint(thrF), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&sh->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (tid == 0) {
+                    __hip_atomic_store(&sh->deal, (unsigned long long)tag << 32, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_s_waitcnt(0);
+                }
+                __syncthreads();
+            }
+            // candidate row of task i (a shared batch reads the published list)
+            auto cand_of = [&](int i) -> uint32_t {
+                return shared ? __hip_atomic_load(&sh->cand[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : ring[(h0 + i) % QCAP];
+            };
             if constexpr (S > 0) {
                 // trunF receives the band cells each task evaluated
                 strip_run<float, S, WIN>(
                     L, geo.Wp, nt, next_task, [&](int) { return (const float *)aF; },
-                    [&](int i) { return a.B + (int64_t)ring[(h0 + i) % QCAP] * L; }, [&](int) { return thrF; },
-                    resF, trunF, run_thr, 1.0 + 2.0 * a.eps, rot_phase);
+                    [&](int i) { return a.B + (int64_t)cand_of(i) * L; }, [&](int) { return thrF; },
+                    shared ? reinterpret_cast<float *>(sh->res) : resF, shared ? sh->trun : trunF, run_thr,
+                    1.0 + 2.0 * a.eps, rot_phase, shared ? &sh->deal : nullptr, tag, shared ? &sh->done : nullptr);
             } else {
                 TaskOut<float> to{resF, trunF, run_thr, 1.0 + 2.0 * a.eps, rot_phase};
                 if (shared) {
-                    // publish the batch (candidates, size, threshold, a zero
-                    // count), then its tag: the stores are complete before
-                    // the tag is, so a workgroup that sees the tag reads this
-                    // batch
-                    ++seq;
-                    const uint32_t tag = (a.epoch << 12) | (seq & 0xFFFu);
-                    for (int i = tid; i < nt; i += nthr)
-                        __hip_atomic_store(&sh->cand[i], ring[(h0 + i) % QCAP], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    if (tid == 0) {
-                        __hip_atomic_store(&sh->nt, (unsigned)nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(&sh->thrF, __float_as_uint(thrF), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(&sh->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __syncthreads();
-                    if (tid == 0) {
-                        __hip_atomic_store(&sh->deal, (unsigned long long)tag << 32, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        __builtin_amdgcn_s_waitcnt(0);
-                    }
-                    __syncthreads();
                     to.res = reinterpret_cast<float *>(sh->res);
                     to.trun = sh->trun;
                     to.deal64 = &sh->deal;
@@ -634,34 +640,26 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                 }
                 engine_run<float, C, DG, MG, EXACT>(
                     geo, nt, next_task, [&](int) { return (const float *)aF; },
-                    [&](int i) {
-                        const uint32_t k = shared ? __hip_atomic_load(&sh->cand[i], __ATOMIC_RELAXED,
-                                                                       __HIP_MEMORY_SCOPE_AGENT)
-                                                  : ring[(h0 + i) % QCAP];
-                        return Bp + (int64_t)k * a.ppitch;
-                    },
-                    [&](int) { return thrF; }, to);
-                if (shared) {
-                    // every task dealt has been taken by a running workgroup:
-                    // wait until all are counted (bounded; a time-out is
-                    // reported as index -2)
-                    if (tid == 0) {
-                        int spins = 0;
-                        while (__hip_atomic_load(&sh->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                               (unsigned)nt) {
-                            __builtin_amdgcn_s_sleep(2);
-                            if (++spins > (1 << 22)) {
-                                flags[1] = 1;
-                                break;
-                            }
+                    [&](int i) { return Bp + (int64_t)cand_of(i) * a.ppitch; }, [&](int) { return thrF; }, to);
+            }
+            if (shared) {
+                // every task dealt has been taken by a running workgroup:
+                // wait until all are counted (bounded; a time-out is
+                // reported as index -2)
+                if (tid == 0) {
+                    int spins = 0;
+                    while (__hip_atomic_load(&sh->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)nt) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++spins > (1 << 22)) {
+                            flags[1] = 1;
+                            break;
                         }
                     }
-                    __syncthreads();
-                    for (int i = tid; i < nt; i += nthr) {
-                        resF[i] = __uint_as_float(
-                            __hip_atomic_load(&sh->res[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                        trunF[i] = __hip_atomic_load(&sh->trun[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
+                }
+                __syncthreads();
+                for (int i = tid; i < nt; i += nthr) {
+                    resF[i] = __uint_as_float(__hip_atomic_load(&sh->res[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    trunF[i] = __hip_atomic_load(&sh->trun[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
             __syncthreads();
@@ -832,11 +830,11 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
 // for a helper: it shares a batch only once a helper has joined, and then
 // waits only for tasks that a running workgroup has taken.  A helper that
 // finds its query finished, or not started, leaves at once.
-template <int C, bool EXACT>
+template <int C, bool EXACT, int S = 0, bool WIN = true>
 __device__ __forceinline__ void help_query(const SearchArgs &a, const int64_t q, unsigned char *smem)
 {
     const EngineGeom &geo = a.geo, &geoD = a.geoD;
-    const int LENA = staged_len(geo, geoD);
+    const int LENA = S > 0 ? geo.L : staged_len(geo, geoD);
     constexpr int DG = prefetch_global(C), MG = window_global(C);
     float *aF = reinterpret_cast<float *>(smem);
     int *ctl = reinterpret_cast<int *>(aF + ((LENA + 1) & ~1));   // next task, go, nt, threshold, tag
@@ -866,7 +864,9 @@ __device__ __forceinline__ void help_query(const SearchArgs &a, const int64_t q,
     }
     __syncthreads();
     if (__builtin_amdgcn_readfirstlane(ctl[1]) == 0) return;
-    {
+    if constexpr (S > 0) {
+        for (int e = tid; e < geo.L; e += nthr) aF[e] = a.Q[q * geo.L + e];
+    } else {
         EngineGeom ga = geo;
         ga.LEN = LENA;
         stage_rows<float, C>(aF, a.Q, [&](int) { return q; }, 1, ga, tid, nthr);
@@ -902,16 +902,22 @@ __device__ __forceinline__ void help_query(const SearchArgs &a, const int64_t q,
             const uint32_t tag = (uint32_t)__builtin_amdgcn_readfirstlane(ctl[4]);
             const float thrF = __uint_as_float((unsigned)__builtin_amdgcn_readfirstlane(ctl[3]));
             const int nt = __builtin_amdgcn_readfirstlane(ctl[2]);
-            engine_run<float, C, DG, MG, EXACT>(
-                geo, nt, ctl, [&](int) { return (const float *)aF; },
-                [&](int i) {
-                    uint32_t k = __hip_atomic_load(&sh->cand[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    k = k < (uint32_t)N ? k : 0u;     // an index of the set (the owner writes only such)
-                    return Bp + (int64_t)k * a.ppitch;
-                },
-                [&](int) { return thrF; },
-                TaskOut<float>{reinterpret_cast<float *>(sh->res), sh->trun, nullptr, 1.0, -1, &sh->deal, tag,
-                               &sh->done});
+            auto cand_of = [&](int i) -> int64_t {
+                uint32_t k = __hip_atomic_load(&sh->cand[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return k < (uint32_t)N ? k : 0;       // an index of the set (the owner writes only such)
+            };
+            if constexpr (S > 0) {
+                strip_run<float, S, WIN>(geo.L, geo.Wp, nt, ctl, [&](int) { return (const float *)aF; },
+                                         [&](int i) { return a.B + cand_of(i) * geo.L; }, [&](int) { return thrF; },
+                                         reinterpret_cast<float *>(sh->res), sh->trun, nullptr, 1.0, -1, &sh->deal,
+                                         tag, &sh->done);
+            } else {
+                engine_run<float, C, DG, MG, EXACT>(
+                    geo, nt, ctl, [&](int) { return (const float *)aF; },
+                    [&](int i) { return Bp + cand_of(i) * a.ppitch; }, [&](int) { return thrF; },
+                    TaskOut<float>{reinterpret_cast<float *>(sh->res), sh->trun, nullptr, 1.0, -1, &sh->deal, tag,
+                                   &sh->done});
+            }
             last = tag;
             idle = 0;
         } else {
@@ -987,6 +993,10 @@ __global__ void __launch_bounds__(WAVE * strip_search_waves(S))
 search_kernel_strip(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    if (a.share != nullptr && (int64_t)blockIdx.x >= a.nq) {
+        help_query<1, false, S, WIN>(a, ((int64_t)blockIdx.x - a.nq) % a.nq, smem);
+        return;
+    }
     search_query<1, false, 2, S, WIN>(a, blockIdx.x, smem);
 }
 
@@ -1097,6 +1107,7 @@ static int plan_search_strip(const nndtw_refset *rs, const nndtw_search_opts *o,
     plan->LEN = L;
     plan->R = R;
     plan->lds_bytes = lds;
+    plan->helpers = o->helpers > 0 ? o->helpers : (o->helpers < 0 ? 0 : SEARCH_DEFAULT_HELPERS);
     return NNDTW_OK;
 }
 
@@ -1297,7 +1308,7 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     a.nq = nQ;
     a.epoch = 0;
     int64_t grid = nQ;
-    if (plan.S == 0 && plan.helpers > 0) {
+    if (plan.helpers > 0) {
         // helper workgroups (help_query) follow the nQ owners in dispatch order
         static std::atomic<uint32_t> g_epoch{0};
         a.epoch = (g_epoch.fetch_add(1u) % 0xFFFFFu) + 1u;
@@ -1314,10 +1325,10 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
         switch (plan.S * 2 + (win ? 1 : 0)) {
 #define X(s)                                                                                                    \
     case s * 2:                                                                                                 \
-        hipLaunchKernelGGL((search_kernel_strip<s, false>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a); \
+        hipLaunchKernelGGL((search_kernel_strip<s, false>), dim3((unsigned)grid), dim3(WAVE * plan.NW), lds, st, a); \
         break;                                                                                                  \
     case s * 2 + 1:                                                                                             \
-        hipLaunchKernelGGL((search_kernel_strip<s, true>), dim3((unsigned)nQ), dim3(WAVE * plan.NW), lds, st, a);  \
+        hipLaunchKernelGGL((search_kernel_strip<s, true>), dim3((unsigned)grid), dim3(WAVE * plan.NW), lds, st, a);  \
         break;
             X(4) X(8) X(12) X(16) X(24) X(32)
 #undef X

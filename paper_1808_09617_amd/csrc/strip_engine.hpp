@@ -52,10 +52,15 @@ __host__ __device__ constexpr bool strip_fits(int L, int Wp) { return Wp >= L - 
 // thr_of(i) (or the shared run_thr, FP32 only, as in the diagonal engine).
 // res[i]: DTW_W or +inf; cells[i]: band cells evaluated.  WIN: the window
 // constrains (W' < L - 1).  Whole-wave call.
+// deal64 != nullptr: a shared batch (several workgroups, see search.hip):
+// tasks are dealt from the tagged global word as in the diagonal engine
+// (shared_deal), and res / cells are global memory written with
+// device-scope atomic stores, each task then counted in *done.
 template <typename T, int S, bool WIN, typename ARow, typename BRow, typename Thr>
 __device__ __forceinline__ void strip_run(int L, int Wp, int ntasks, int *next_task, ARow arow, BRow brow, Thr thr_of,
                                           T *res, int *cells, unsigned *run_thr = nullptr, double slack = 1.0,
-                                          int rot_phase = -1)
+                                          int rot_phase = -1, unsigned long long *deal64 = nullptr,
+                                          uint32_t tag = 0, unsigned *done = nullptr)
 {
     constexpr int BLK = 8;                    // steps between abandon tests (even: ping-pong rows)
     const int lane = threadIdx.x & (WAVE - 1);
@@ -68,7 +73,9 @@ __device__ __forceinline__ void strip_run(int L, int Wp, int ntasks, int *next_t
         // the whole wave takes part in the fetch (lane 0 adds 1, the others
         // 0) and the task is lane 0's result: no branch on the lane, so no
         // lane can re-enter the loop apart from the others
-        const int task = __builtin_amdgcn_readfirstlane(atomicAdd(next_task, lane == 0 ? 1 : 0));
+        const int task = deal64 != nullptr
+                             ? shared_deal(deal64, tag, ntasks, 1, lane)
+                             : __builtin_amdgcn_readfirstlane(atomicAdd(next_task, lane == 0 ? 1 : 0));
         if (task >= ntasks) break;
         const auto a = arow(task);
         const auto b = brow(task);
@@ -168,8 +175,21 @@ __device__ __forceinline__ void strip_run(int L, int Wp, int ntasks, int *next_t
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) nc += __shfl_xor(nc, off);
         if (lane == 0) {
-            res[task] = dead ? INF : r;
-            cells[task] = nc;
+            if constexpr (sizeof(T) == 4) {
+                if (deal64 != nullptr) {
+                    __hip_atomic_store(reinterpret_cast<unsigned *>(res) + task, __float_as_uint(dead ? INF : r),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(cells + task, nc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    res[task] = dead ? INF : r;
+                    cells[task] = nc;
+                }
+            } else {
+                res[task] = dead ? INF : r;
+                cells[task] = nc;
+            }
             if constexpr (sizeof(T) == 4) {
                 if (run_thr != nullptr && !dead) atomicMin(run_thr, __float_as_uint(round_up_f32((double)r * slack)));
             }

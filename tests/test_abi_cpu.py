@@ -239,7 +239,7 @@ def test_search_plan_has_a_shape_for_every_window():
             if _strip_chosen(L, Wp):
                 assert opts.engine == nd.ENGINES["strip"] and opts.cpl == 0, (L, W)
                 assert opts.waves == 4 and opts.R == 256, (L, W, opts.waves, opts.R)
-                assert opts.helpers == -1                          # no helper workgroups on strips
+                assert opts.helpers == 3                           # helper workgroups, as on the diagonal shapes
             else:
                 assert opts.engine == nd.ENGINES["diagonal"], (L, W)
                 # 3 helper workgroups per query, except for the shapes whose

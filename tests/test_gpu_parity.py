@@ -389,6 +389,22 @@ def test_search_helper_workgroups(W, helpers):
     assert np.all(joined == helpers)              # every helper joined its query
 
 
+@pytest.mark.parametrize("L,W", [(300, 299), (700, 650)])
+def test_search_helper_workgroups_strips(L, W):
+    """Helper workgroups on the row-strip engine: results and defined counts
+    equal the oracle's, and every helper joined its query."""
+    refs = series(600, L, seed=820 + W, kind="rw")
+    queries = series(12, L, seed=821 + W, kind="rw")
+    check_search(refs, queries, W, 3, "keogh_enh", 0, True, 0, brute=False, helpers=3)
+    rs = nd.RefSet(dev(refs), W)
+    s = nd.Searcher(rs, 12, V=3, helpers=3)
+    s(dev(queries))
+    torch.cuda.synchronize()
+    joined = _helpers_joined(s, 600, L, 12)
+    say("helpers strips", L, W, "engine", s.engine, "joined", joined.tolist())
+    assert s.engine == "strip" and np.all(joined == 3)
+
+
 def test_search_helpers_headline_shape():
     """The headline launch shape (5000 references, L=512, W=51, 16 waves per
     query, 4 pairs per lane) with 7 helpers per query for 40 queries: every
