@@ -96,7 +96,8 @@ def profiled_traffic(kernel, workload):
     for line in open(path):
         if line.startswith("# device code fingerprint"):
             fp = line.split(":", 1)[1].strip()
-        if line.startswith("# bytes_per_launch ") and line.split()[2] == kernel:
+        # the kernel's family (search_kernel covers search_kernel_wide, ...)
+        if line.startswith("# bytes_per_launch ") and kernel in line.split()[2] and "batch" not in line:
             val = int(line.split()[3])
     return val if fp is not None and fp == device_code_fingerprint() else None
 
@@ -625,6 +626,8 @@ def main():
                     help="only the batching workload (defaults and autotuned), one JSON line each")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only the window sweep and the comparison bounds, one JSON line")
+    ap.add_argument("--windows-only", action="store_true", help="only the window sweep, one JSON line")
+    ap.add_argument("--backward-only", action="store_true", help="only the DTW backward, one JSON line")
     ap.add_argument("--hbm-only", action="store_true",
                     help="only the streaming kernels on the 200,000 x 512 reference set, one JSON line")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -645,6 +648,13 @@ def main():
         dev = torch.device("cuda:0")
         for tuned in (None, "auto"):
             print(json.dumps(batch_bench(nd, synth, torch, dev, tuned=tuned)), flush=True)
+        return
+
+    if args.windows_only:
+        print(json.dumps({"window_sweep": window_sweep(nd, synth, torch, torch.device("cuda:0"))}), flush=True)
+        return
+    if args.backward_only:
+        print(json.dumps({"backward": backward_bench(nd, synth, torch, torch.device("cuda:0"), cpu=False)}), flush=True)
         return
 
     if args.hbm_only:

@@ -332,7 +332,8 @@ int nndtw_search_plan(const nndtw_refset *refset, nndtw_search_opts *opts);
 /* Q: device float[nQ][L] (L of the reference set); outputs: nn_idx int64[nQ],
  * nn_dist double[nQ], counts int64[nQ][NNDTW_NCOUNTS] (NULL allowed).
  * ws: device workspace of at least nndtw_search_workspace_bytes() bytes
- * (60 bytes per (query, reference) pair plus a table of 8L bytes).  Any
+ * (60 bytes per (query, reference) pair, 3136 bytes per query for the
+ * batches shared with helper workgroups, and a table of 8L bytes).  Any
  * reference-set size: above 8192 references the visiting order is sorted in
  * chunks of 8192 that are then merged in the workspace. */
 int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ,
@@ -346,8 +347,9 @@ int nndtw_search(const nndtw_refset *refset, const float *Q, int64_t nQ,
  * device's first use until the process ends; the call allocates nothing and
  * otherwise behaves exactly as nndtw_search (same validation, kernels and
  * results).  EUNSUP when the workspace nndtw_search_workspace_bytes reports
- * exceeds NNDTW_SEARCH_SCRATCH_BYTES (60 bytes per (query, reference) pair:
- * up to about 1.1 million pairs, e.g. 1000 queries x 1000 references; split
+ * exceeds NNDTW_SEARCH_SCRATCH_BYTES (60 bytes per (query, reference) pair
+ * and 3136 per query: up to about 1.1 million pairs, e.g. 1000 queries x 1000
+ * references; split
  * larger query sets into several calls).  Every call on one GPU uses that
  * GPU's single array: calls that overlap on the same GPU (other streams or
  * threads) race and corrupt each other's results; serialise them. */
