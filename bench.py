@@ -243,11 +243,17 @@ def serving_bench(nd, synth, torch, dev, rate=2000.0, duration=3.0):
     sample = [(rs, torch.stack([torch.from_numpy(synth.serving_query(s, Ls[s], 2 * 10 ** 6 + k)).to(dev)
                                 for k in range(16)])) for s, rs in enumerate(rss)]
     R, cpl, _ = tune.autotune(sample, V=5)
+    # the same stream without helper workgroups, for comparison
+    server = serve.Server(rss, n_streams=3, R=R, cpl=cpl, helpers=-1)
+    server.run(warm)
+    _, nohelp = server.run(reqs)
+    del server
     server = serve.Server(rss, n_streams=3, R=R, cpl=cpl)
     server.run(warm)
     _, summary = server.run(reqs)
     summary.update({"offered_rps": rate, "sets": len(sets), "refs_per_set": sets[0][0].shape[0],
-                    "lengths": Ls, "R": R, "cpl": cpl})
+                    "lengths": Ls, "R": R, "cpl": cpl,
+                    "without_helpers": {"mean_batch": nohelp["mean_batch"], "latency_ms": nohelp["latency_ms"]}})
     # saturation: 4000 requests present at the start, served as fast as the
     # server admits them (batches of up to 512 within the 1 GiB budget)
     sat = serve.poisson_requests(Ls, rate=float("inf"), duration=4000, seed=3, device=dev,
@@ -278,31 +284,41 @@ def batch_bench(nd, synth, torch, dev, reps=3, tuned=None):
         t0 = time.perf_counter()
         R, cpl, report = tune.autotune(pairs, V=5)
         tune_s = time.perf_counter() - t0
+    def graph_time(bsr):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            bsr()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            bsr()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.replay()
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        del g
+        return sorted(times)[len(times) // 2]
+
+    # without helper workgroups first (same plan otherwise), for comparison
+    bsr = nd.BatchSearcher(pairs, V=5, R=R, cpl=cpl, helpers=-1)
+    t_nohelp = graph_time(bsr)
+    del bsr
+    torch.cuda.empty_cache()
     bsr = nd.BatchSearcher(pairs, V=5, R=R, cpl=cpl)
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        bsr()
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        bsr()
-    times = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        g.replay()
-        e1.record()
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1) / 1e3)
-    t = sorted(times)[len(times) // 2]
+    t = graph_time(bsr)
     cells = sum(int(c[:, 6].sum()) for _, _, c in bsr.out)
     started = sum(int(c[:, 4].sum()) for _, _, c in bsr.out)
     pairs_total = sum(ds.refs.shape[0] * ds.queries.shape[0] for ds in sets)
     out = {"workload": "batch64-rw", "sets": len(sets), "queries": nq, "pairs": pairs_total,
            "schedule": "autotuned" if tuned is not None else "library defaults",
-           "ms": t * 1e3, "queries_per_s": nq / t, "dtw_cells_per_s": cells / t,
+           "ms": t * 1e3, "helpers": bsr.helpers, "ms_without_helpers": t_nohelp * 1e3,
+           "queries_per_s": nq / t, "dtw_cells_per_s": cells / t,
            "valu_frac_dtw": 3.0 * cells / t / VALU_PEAK_OPS, "pruning_rate": 1.0 - started / pairs_total,
            "launches": 1 + sum(1 for c in bsr.plan.order_cnt if c) + sum(1 for c in bsr.plan.search_cnt if c),
            "shapes": {f"C{sh // 2 + 1}{'x' if sh & 1 else ''}": int(bsr.plan.search_cnt[sh])
@@ -324,7 +340,7 @@ def batch_bench(nd, synth, torch, dev, reps=3, tuned=None):
     if report is not None:
         out["tuning_s"] = tune_s
         out["buckets"] = {k: {"sets": v["sets"], "cpl": v["cpl"], "R": v["R"]} for k, v in report.items()}
-    del g, bsr, srs, pairs
+    del bsr, srs, pairs
     torch.cuda.empty_cache()
     return out
 
@@ -628,6 +644,7 @@ def main():
                     help="only the window sweep and the comparison bounds, one JSON line")
     ap.add_argument("--windows-only", action="store_true", help="only the window sweep, one JSON line")
     ap.add_argument("--backward-only", action="store_true", help="only the DTW backward, one JSON line")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving loop, one JSON line")
     ap.add_argument("--hbm-only", action="store_true",
                     help="only the streaming kernels on the 200,000 x 512 reference set, one JSON line")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -652,6 +669,9 @@ def main():
 
     if args.windows_only:
         print(json.dumps({"window_sweep": window_sweep(nd, synth, torch, torch.device("cuda:0"))}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(nd, synth, torch, torch.device("cuda:0"))}), flush=True)
         return
     if args.backward_only:
         print(json.dumps({"backward": backward_bench(nd, synth, torch, torch.device("cuda:0"), cpu=False)}), flush=True)

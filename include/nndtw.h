@@ -292,12 +292,15 @@ typedef struct nndtw_search_opts {
     int32_t engine;   /* DTW engine, NNDTW_ENGINE_*; 0 = library choice; out          */
     int64_t nq_hint;  /* nndtw_search_plan only: the query count to plan for (0 =
                        * many); nndtw_search plans for its own nQ                    */
-    int32_t helpers;  /* helper workgroups per query of the DIAGONAL engine (0 =
-                       * default 3, -1 = none, at most NNDTW_SEARCH_MAX_HELPERS):
-                       * launched after the queries' own workgroups, a helper
-                       * joins its query if it is still running and takes DTW
-                       * tasks of its rounds through device-scope atomics; the
-                       * result and the defined counts do not change; out     */
+    int32_t helpers;  /* helper workgroups per query (0 = default, -1 = none, at
+                       * most NNDTW_SEARCH_MAX_HELPERS).  nndtw_search: default 3,
+                       * launched after the queries' own workgroups (none at 3
+                       * or 6 pairs per lane); a helper joins its query if it is
+                       * still running and takes DTW tasks of its rounds through
+                       * device-scope atomics.  Batch: default 7, the most that
+                       * may join one query once a search kernel's items are all
+                       * taken (idle persistent workgroups).  The result and the
+                       * defined counts do not change; out (nndtw_search)     */
     int32_t reserved;
 } nndtw_search_opts;
 
@@ -451,9 +454,14 @@ typedef struct nndtw_batch_plan {
     int64_t search_off[8];       /* item-list offset and count per engine shape      */
     int64_t search_cnt[8];       /*   (C, exact) = (1,0), (1,1), ..., (4,1)          */
     int64_t reserved[4];
+    int32_t helpers;             /* most helper workgroups per query (0: none)       */
+    uint32_t share_shapes;       /* engine shapes whose kernel lends idle workgroups */
+    int64_t share_off;           /* workspace offset of the items' helper headers    */
 } nndtw_batch_plan;
 
-/* Device workspace bytes for a batch (sets as passed to prepare). */
+/* Device workspace bytes for a batch (sets as passed to prepare, the same
+ * opts): the per-set search workspaces, the item lists and, unless
+ * opts->helpers is -1, a 3136-byte helper header per query. */
 int nndtw_batch_workspace_bytes(const nndtw_batch_set *sets, int32_t nsets,
                                 const nndtw_search_opts *opts, size_t *bytes);
 
@@ -470,7 +478,8 @@ int nndtw_batch_prepare(nndtw_batch_set *sets, int32_t nsets, const nndtw_search
                         void *ws, size_t ws_bytes, nndtw_batch_plan *plan, void *stream);
 
 /* Run a prepared batch: 1 + (sort widths used) + (engine shapes used)
- * kernels on `stream`.  The
+ * kernels on `stream`, and one that resets the helper headers when
+ * plan->helpers > 0.  The
  * sets' reference sets, queries, outputs and ws must be those of prepare. */
 int nndtw_search_batch(const nndtw_batch_plan *plan, void *ws, void *stream);
 

@@ -68,7 +68,8 @@ class _BatchPlan(ctypes.Structure):
                 ("tiles", ctypes.c_int64), ("waves", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("lds", ctypes.c_int64), ("ws_bytes", ctypes.c_int64), ("order_off", ctypes.c_int64 * 6),
                 ("order_cnt", ctypes.c_int64 * 6), ("search_off", ctypes.c_int64 * 8),
-                ("search_cnt", ctypes.c_int64 * 8), ("reserved", ctypes.c_int64 * 4)]
+                ("search_cnt", ctypes.c_int64 * 8), ("reserved", ctypes.c_int64 * 4),
+                ("helpers", ctypes.c_int32), ("share_shapes", ctypes.c_uint32), ("share_off", ctypes.c_int64)]
 
 
 _P, _I32, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -417,10 +418,12 @@ class BatchSearcher:
     whole batch on the current stream (no allocation or copy, so it can be
     captured in a CUDA/HIP graph) and returns per set (nn_idx, nn_dist, counts).
     Each set's result equals ``search`` on that set with the R and cpl
-    reported in ``self.R`` / ``self.cpl``."""
+    reported in ``self.R`` / ``self.cpl``.  ``helpers``: the most idle
+    workgroups that may join one query at a search kernel's end (0 = the
+    library default, -1 = none); the result does not depend on it."""
 
     def __init__(self, sets, V: int = 5, cascade: str = "keogh_enh", R=None, cpl=None, eps: float = 0.0,
-                 init_ub: bool = True, waves: int = 0):
+                 init_ub: bool = True, waves: int = 0, helpers: int = 0):
         n = len(sets)
         if n == 0:
             raise ValueError("empty batch")
@@ -443,7 +446,7 @@ class BatchSearcher:
             b.R = 0 if R is None else int(R[d])
             b.cpl = 0 if cpl is None else int(cpl[d])
         self.sets = arr
-        self.opts = _opts(V, cascade, 0, eps, init_ub, 0, waves)
+        self.opts = _opts(V, cascade, 0, eps, init_ub, 0, waves, helpers=helpers)
         nbytes = ctypes.c_size_t(0)
         _check(lib().nndtw_batch_workspace_bytes(arr, n, ctypes.byref(self.opts), ctypes.byref(nbytes)))
         self.ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)
@@ -452,6 +455,11 @@ class BatchSearcher:
                                          ctypes.byref(self.plan), _stream()))
         self.R = [int(arr[d].R) for d in range(n)]
         self.cpl = [int(arr[d].cpl) for d in range(n)]
+
+    @property
+    def helpers(self) -> int:
+        """Most helper workgroups per query the plan allows (0: none)."""
+        return int(self.plan.helpers)
 
     def __call__(self):
         _check(lib().nndtw_search_batch(ctypes.byref(self.plan), _ptr(self.ws), _stream()))

@@ -548,7 +548,7 @@ int nndtw_batch_workspace_bytes(const nndtw_batch_set *sets, int32_t nsets, cons
     g_err[0] = 0;
     TRY(check_batch(sets, nsets, opts, false));
     REQUIRE(bytes != nullptr, "bytes is NULL");
-    *bytes = batch_ws_bytes(sets, nsets);
+    *bytes = batch_ws_bytes(sets, nsets, opts);
     return NNDTW_OK;
 }
 

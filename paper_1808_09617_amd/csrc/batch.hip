@@ -8,7 +8,10 @@
 //      set has that width;
 //   3. per engine shape (C, EXACT), one persistent search kernel whose
 //      workgroups take (set, query) items from the shape's counter, largest
-//      expected work (n * L * (2W'+1)) first.
+//      expected work (n * L * (2W'+1)) first; once the items are all taken,
+//      idle workgroups help the queries still running (shared FP32 batches,
+//      as the single-query search's helper workgroups), after a reset of the
+//      items' helper headers.
 // Everything the kernels need (set descriptors, item lists, tile starts) is
 // copied into the caller's workspace once, at planning time (enqueued on the
 // stream, without waiting), so the launch sequence allocates and copies
@@ -28,16 +31,19 @@ constexpr uint32_t BATCH_PLAN_MAGIC = 0x4E444242u;   // "NDBB"
 constexpr int BATCH_TQ = 4;                           // queries per bound-pass tile
 constexpr int BATCH_CB_THREADS = 256;                 // references per bound-pass tile
 constexpr int N_WIDTHS = 6;                           // sort widths 1, 2, 4, ..., 32
+constexpr int BATCH_DEFAULT_HELPERS = 7;              // helpers per query in a search's tail
+constexpr int64_t BATCH_FEW_ITEMS = 32;               // items of a shape that get helpers at launch
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t hdr, sets, items, oitems, tstart;
+    size_t hdr, sets, items, oitems, tstart, share;
     std::vector<size_t> set_off;                      // per-set search workspace
     size_t total;
 };
 
-Layout layout(const nndtw_batch_set *sets, int nsets)
+// share: room for a helper header (QueryShare) per item.
+Layout layout(const nndtw_batch_set *sets, int nsets, bool share)
 {
     Layout y;
     int64_t items = 0;
@@ -48,6 +54,7 @@ Layout layout(const nndtw_batch_set *sets, int nsets)
     y.items = o;  o = al256(o + 8 * (size_t)items);
     y.oitems = o; o = al256(o + 8 * (size_t)items);
     y.tstart = o; o = al256(o + 8 * (size_t)(nsets + 1));
+    y.share = o;  o = al256(o + (share ? sizeof(QueryShare) * (size_t)items : 0));
     y.set_off.resize(nsets);
     for (int d = 0; d < nsets; ++d) {
         y.set_off[d] = o;
@@ -66,12 +73,23 @@ int width_slot(int E)
 
 }  // namespace
 
-size_t batch_ws_bytes(const nndtw_batch_set *sets, int nsets) { return layout(sets, nsets).total; }
+// Helper workgroups per query in a search's tail: opts->helpers < 0 none,
+// 0 the default, else at most that many.
+int batch_helpers(const nndtw_search_opts *o)
+{
+    return o->helpers < 0 ? 0 : o->helpers == 0 ? BATCH_DEFAULT_HELPERS : o->helpers;
+}
+
+size_t batch_ws_bytes(const nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o)
+{
+    return layout(sets, nsets, batch_helpers(o) > 0).total;
+}
 
 int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, void *ws, size_t ws_bytes,
                   nndtw_batch_plan *plan, hipStream_t st)
 {
-    const Layout y = layout(sets, nsets);
+    const int H = batch_helpers(o);
+    const Layout y = layout(sets, nsets, H > 0);
     if (ws_bytes < y.total) return fail(NNDTW_EINVAL, "workspace too small: %zu bytes given, %zu needed", ws_bytes, y.total);
     unsigned char *base = (unsigned char *)ws;
 
@@ -160,11 +178,20 @@ int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, 
     std::stable_sort(order.begin(), order.end(), [&](int x, int z) { return cost[x] > cost[z]; });
     std::vector<int64_t> items, oitems;
     int64_t soff[BATCH_SHAPES] = {0}, scnt[BATCH_SHAPES] = {0};
+    QueryShare *share = H > 0 ? (QueryShare *)(base + y.share) : nullptr;
     for (int sh = 0; sh < BATCH_SHAPES; ++sh) {
         soff[sh] = (int64_t)items.size();
         for (int d : order)
-            if ((bs[d].C - 1) * 2 + bs[d].exact == sh)
+            if ((bs[d].C - 1) * 2 + bs[d].exact == sh) {
+                // the set's queries are consecutive items: header of query q
+                // at the set's first item + q
+                if (share != nullptr) {
+                    bs[d].a.share = share + items.size();
+                    bs[d].a.nq = sets[d].nQ;
+                    bs[d].a.epoch = 1u;          // the headers are reset before every launch
+                }
                 for (int64_t q = 0; q < sets[d].nQ; ++q) items.push_back(((int64_t)d << 32) | q);
+            }
         scnt[sh] = (int64_t)items.size() - soff[sh];
     }
     // ordering items grouped by sort width
@@ -225,6 +252,12 @@ int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, 
     plan->reserved[1] = (int64_t)y.items;
     plan->reserved[2] = (int64_t)y.oitems;
     plan->reserved[3] = (int64_t)y.tstart;
+    plan->helpers = H;
+    plan->share_shapes = 0u;
+    if (H > 0)
+        for (int sh = 0; sh < BATCH_SHAPES; ++sh)
+            if (scnt[sh] > 0) plan->share_shapes |= 1u << sh;
+    plan->share_off = H > 0 ? (int64_t)y.share : 0;
     return NNDTW_OK;
 }
 
@@ -239,15 +272,24 @@ int batch_launch(const nndtw_batch_plan *plan, void *ws, hipStream_t st)
     const int64_t *tstart = (const int64_t *)(base + plan->reserved[3]);
     BatchHdr *hdr = (BatchHdr *)base;
     if (int r = launch_batch_bounds(sets, plan->nsets, tstart, plan->tiles, hdr, st)) return r;
+    if (plan->share_shapes != 0u)
+        if (int r = launch_share_reset((QueryShare *)(base + plan->share_off), plan->items, st)) return r;
     for (int s = 0; s < N_WIDTHS; ++s)
         if (plan->order_cnt[s] > 0)
             if (int r = launch_batch_order(1 << s, sets, oitems + plan->order_off[s], plan->order_cnt[s], st)) return r;
     for (int sh = 0; sh < BATCH_SHAPES; ++sh) {
         const int64_t cnt = plan->search_cnt[sh];
         if (cnt == 0) continue;
-        const int grid = (int)std::min<int64_t>(cnt, plan->grid);
+        // a sharing shape with few items (a serving batch) launches up to
+        // `helpers` more workgroups per item; with more, the workgroups that
+        // run out of items help (extra ones would take compute units from
+        // the kernels of other streams)
+        const int H = (plan->share_shapes >> sh) & 1u ? plan->helpers : 0;
+        const int64_t want = cnt <= BATCH_FEW_ITEMS ? cnt * (1 + H) : cnt;
+        const int grid = (int)std::min<int64_t>(want, plan->grid);
         if (int r = launch_batch_search(sh / 2 + 1, sh & 1, sets, items + plan->search_off[sh], cnt,
-                                        &hdr->counter[sh], plan->waves, grid, (size_t)plan->lds, st))
+                                        &hdr->counter[sh], hdr->running, plan->waves, grid, (size_t)plan->lds, H,
+                                        st))
             return r;
     }
     return NNDTW_OK;

@@ -78,6 +78,7 @@ int launch_cascade_bounds(const nndtw_refset *rs, const float *Q, int64_t nQ, in
                           double *ed2, double *lbk, double *lbeb, double *lbe, hipStream_t s);
 struct BatchSet;
 struct BatchHdr;
+struct QueryShare;
 struct EngineGeom;
 int launch_batch_bounds(const BatchSet *sets, int nsets, const int64_t *tile_start, int64_t tiles,
                         BatchHdr *hdr, hipStream_t s);
@@ -121,13 +122,18 @@ WsLayout ws_layout(int64_t nQ, int64_t n, int L, bool share = true);
 int launch_cells_prefix(int L, int Wp, uint32_t *prefix, hipStream_t s);
 int order_width(int64_t n);     // visiting-order sort size class: npow = 256 * width
 int launch_batch_order(int E, const BatchSet *sets, const int64_t *items, int64_t nitems, hipStream_t s);
+// helpers > 0: the kernel lends idle workgroups to running queries, at most
+// `helpers` per query (their QueryShare headers reset by launch_share_reset)
 int launch_batch_search(int C, bool exact, const BatchSet *sets, const int64_t *items, int64_t nitems,
-                        unsigned *counter, int waves, int grid, size_t lds, hipStream_t s);
+                        unsigned *counter, unsigned *running, int waves, int grid, size_t lds, int helpers,
+                        hipStream_t s);
+// Zeroes the helper headers of nq queries.
+int launch_share_reset(QueryShare *share, int64_t nq, hipStream_t s);
 size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD);
 // Compute units of the current device (0 if it cannot be queried).
 int device_cu_count();
 // batch.hip
-size_t batch_ws_bytes(const nndtw_batch_set *sets, int nsets);
+size_t batch_ws_bytes(const nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o);
 int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, void *ws, size_t ws_bytes,
                   nndtw_batch_plan *plan, hipStream_t s);
 int batch_launch(const nndtw_batch_plan *plan, void *ws, hipStream_t s);
@@ -230,8 +236,12 @@ struct BatchSet {
     double *slbkw, *slbebw, *slbew;
 };
 constexpr int BATCH_SHAPES = 8;  // engine shapes (C, EXACT), C = 1..4
+constexpr int BATCH_MAX_GRID = 4096;  // persistent search workgroups at most
 struct BatchHdr {
     unsigned counter[BATCH_SHAPES];   // next search item per shape (reset by the bound pass)
+    // item + 1 that each persistent search workgroup runs (0: none; values
+    // left by an earlier kernel name items that have been taken as well)
+    unsigned running[BATCH_MAX_GRID];
 };
 
 // Choose the diagonal-pairs-per-lane C for a window (cmax bounds latency).

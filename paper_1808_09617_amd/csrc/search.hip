@@ -51,9 +51,10 @@ constexpr int SEARCH_MAX_WAVES = 8;        // workgroup size of the search kerne
 constexpr int SEARCH_WIDE_WAVES = NNDTW_SEARCH_MAX_WAVES;   // ... of the wide ones
 constexpr int SEARCH_DEFAULT_WAVES = 4;
 constexpr int SEARCH_DEFAULT_HELPERS = 3;
-// Engine shapes whose search kernels hold the shared-batch code (helper
-// workgroups): 3 and 6 pairs per lane fill the 128 registers they are held
-// to without it, and would spill with it.
+// Engine shapes whose single-query search kernels hold the shared-batch code
+// (helper workgroups): 3 and 6 pairs per lane fill the 128 registers those
+// kernels are held to without it, and would spill with it.  (The batch's
+// kernels are not held to 128 and share at every shape.)
 __host__ __device__ constexpr bool share_ok(int C) { return C != 3 && C != 6; }
 constexpr int ORDER_THREADS = 256;
 
@@ -531,7 +532,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     const int64_t N = a.n;
     const int L = geo.L;
     const int64_t qo = q * N;
-    constexpr bool SH = SHARE && (S > 0 || share_ok(C));
+    constexpr bool SH = SHARE;
     QueryShare *const sh = (SH && a.share != nullptr) ? a.share + q : nullptr;
     uint32_t seq = 0;                    // shared batches of this query so far
     // A candidate's FP32 row is read straight from the padded copy: element e
@@ -829,9 +830,11 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
 // FP32 batches (QueryShare) until the query finishes.  The owner never waits
 // for a helper: it shares a batch only once a helper has joined, and then
 // waits only for tasks that a running workgroup has taken.  A helper that
-// finds its query finished, or not started, leaves at once.
+// finds its query finished, or not started, or `cap` helpers already joined,
+// leaves at once.
 template <int C, bool EXACT, int S = 0, bool WIN = true>
-__device__ __forceinline__ void help_query(const SearchArgs &a, const int64_t q, unsigned char *smem)
+__device__ __forceinline__ void help_query(const SearchArgs &a, const int64_t q, unsigned char *smem,
+                                           unsigned cap = 0xFFFu)
 {
     const EngineGeom &geo = a.geo, &geoD = a.geoD;
     const int LENA = S > 0 ? geo.L : staged_len(geo, geoD);
@@ -852,13 +855,18 @@ __device__ __forceinline__ void help_query(const SearchArgs &a, const int64_t q,
         }
         if (started && __hip_atomic_load(&sh->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != a.epoch) {
             unsigned cur = __hip_atomic_load(&sh->helpers, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            go = 1;
             while (true) {
-                const unsigned want = (cur >> 12) == a.epoch ? cur + 1u : ((a.epoch << 12) | 1u);
+                const bool mine = (cur >> 12) == a.epoch;
+                if (mine && (cur & 0xFFFu) >= cap) {
+                    go = 0;
+                    break;
+                }
+                const unsigned want = mine ? cur + 1u : ((a.epoch << 12) | 1u);
                 if (__hip_atomic_compare_exchange_strong(&sh->helpers, &cur, want, __ATOMIC_RELAXED,
                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                     break;
             }
-            go = 1;
         }
         ctl[1] = go;
     }
@@ -944,7 +952,7 @@ search_kernel(SearchArgs a)
             return;
         }
     }
-    search_query<C, EXACT, RK>(a, blockIdx.x, smem);
+    search_query<C, EXACT, RK, 0, true, share_ok(C)>(a, blockIdx.x, smem);
 }
 
 // Up to 16 waves per query for the shapes with the one-pair FP64 recheck
@@ -961,7 +969,7 @@ search_kernel_wide(SearchArgs a)
             return;
         }
     }
-    search_query<C, EXACT, C == 1 ? 2 : 1>(a, blockIdx.x, smem);
+    search_query<C, EXACT, C == 1 ? 2 : 1, 0, true, share_ok(C)>(a, blockIdx.x, smem);
 }
 
 // Resets the shared-batch headers of nq queries (before a search with
@@ -977,6 +985,14 @@ __global__ void __launch_bounds__(256) share_reset_kernel(QueryShare *share, int
         share[q].finished = 0u;
         share[q].started = 0u;
     }
+}
+
+int launch_share_reset(QueryShare *share, int64_t nq, hipStream_t st)
+{
+    if (nq <= 0) return NNDTW_OK;
+    hipLaunchKernelGGL(share_reset_kernel, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, st, share, nq);
+    NNDTW_LAUNCH_CHECK("share reset kernel launch");
+    return NNDTW_OK;
 }
 
 // Whether a plan may use more than SEARCH_MAX_WAVES waves (search_kernel_wide).
@@ -1006,43 +1022,106 @@ search_kernel_strip(SearchArgs a)
 // per shape present: a kernel with several engine bodies would need the
 // register count of their union.  The counters are reset by the batch's
 // bound pass.
-template <int C, bool EXACT>
+// SHARE: once the items are all taken, a workgroup lends itself to the
+// queries still running (help_query, at most `cap` helpers per query).
+// Every workgroup records the item it runs in running[blockIdx.x]; an idle
+// one keeps drawing from the counter, and draw h past the end names the item
+// of workgroup h mod gridDim.x, until it finds a query not finished and
+// below the cap, or `probes` draws past the end have been made in all.  Each
+// item's helper header (QueryShare) is reset before the launch.
+template <int C, bool EXACT, bool SHARE>
 __global__ void __launch_bounds__(WAVE * SEARCH_MAX_WAVES)
 batch_search_kernel(const BatchSet *__restrict__ sets, const int64_t *__restrict__ items, int64_t nitems,
-                    unsigned *counter)
+                    unsigned *counter, unsigned *running, unsigned cap, unsigned probes)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t cur;
     while (true) {
         __syncthreads();                 // the previous item is finished by every wave
-        if (threadIdx.x == 0) cur = (int64_t)atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) {
+            cur = (int64_t)atomicAdd(counter, 1u);
+            if constexpr (SHARE)
+                __hip_atomic_store(&running[blockIdx.x], cur < nitems ? (unsigned)cur + 1u : 0u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
         const int64_t i = cur;
         if (i >= nitems) break;
         const int64_t it = items[i];
         const int d = __builtin_amdgcn_readfirstlane((int)(it >> 32));
-        search_query<C, EXACT, 0, 0, true, false>(sets[d].a, it & 0xFFFFFFFF, smem);
+        search_query<C, EXACT, 0, 0, true, SHARE>(sets[d].a, it & 0xFFFFFFFF, smem);
+    }
+    if constexpr (SHARE) {
+        const unsigned G = gridDim.x;
+        while (true) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int64_t found = -1;
+                for (unsigned k = 0; k < G; ++k) {
+                    const unsigned drawn = atomicAdd(counter, 1u);
+                    if ((int64_t)drawn < nitems) break;          // not reached: the items are all taken
+                    const unsigned h = drawn - (unsigned)nitems;
+                    if (h >= probes) break;
+                    const unsigned r =
+                        __hip_atomic_load(&running[h % G], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (r == 0u || (int64_t)r > nitems) continue;
+                    const int64_t j = (int64_t)r - 1;
+                    const int64_t it = items[j];
+                    const SearchArgs &aj = sets[(int)(it >> 32)].a;
+                    const QueryShare *sh = aj.share + (it & 0xFFFFFFFF);
+                    // not finished and not at the cap (a query whose owner
+                    // has not written `started` yet is about to: every item
+                    // has been taken by a running workgroup)
+                    const unsigned hv = __hip_atomic_load(&sh->helpers, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (__hip_atomic_load(&sh->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != aj.epoch &&
+                        !((hv >> 12) == aj.epoch && (hv & 0xFFFu) >= cap)) {
+                        found = j;
+                        break;
+                    }
+                }
+                cur = found;
+            }
+            __syncthreads();
+            const int64_t j = cur;
+            if (j < 0) break;
+            const int64_t it = items[j];
+            const int d = __builtin_amdgcn_readfirstlane((int)(it >> 32));
+            help_query<C, EXACT>(sets[d].a, it & 0xFFFFFFFF, smem, cap);
+        }
     }
 }
 
 int launch_batch_search(int C, bool exact, const BatchSet *sets, const int64_t *items, int64_t nitems,
-                        unsigned *counter, int waves, int grid, size_t lds, hipStream_t st)
+                        unsigned *counter, unsigned *running, int waves, int grid, size_t lds, int helpers,
+                        hipStream_t st)
 {
     if (nitems == 0) return NNDTW_OK;
-    switch (C * 2 + (exact ? 1 : 0)) {
-#define NNDTW_BSEARCH_CASE(c, e)                                                                             \
-    case c * 2 + e:                                                                                       \
-        hipLaunchKernelGGL((batch_search_kernel<c, e>), dim3((unsigned)grid), dim3(WAVE * waves), lds, st, sets, \
-                           items, nitems, counter);                                                       \
+    if (grid > BATCH_MAX_GRID) return fail(NNDTW_EINVAL, "batch search: grid %d above %d", grid, BATCH_MAX_GRID);
+    const unsigned cap = helpers > 0 ? (unsigned)helpers : 0u;
+    // draws past the end in all: every workgroup's slot probed 64 times over
+    const unsigned probes = 64u * (unsigned)grid;
+    switch (C * 4 + (exact ? 2 : 0) + (helpers > 0 ? 1 : 0)) {
+#define NNDTW_BSEARCH_CASE(c, e, h)                                                                            \
+    case c * 4 + e * 2 + h:                                                                                   \
+        hipLaunchKernelGGL((batch_search_kernel<c, e, h>), dim3((unsigned)grid), dim3(WAVE * waves), lds, st, sets, \
+                           items, nitems, counter, running, cap, probes);                                     \
         break;
-        NNDTW_BSEARCH_CASE(1, 0)
-        NNDTW_BSEARCH_CASE(1, 1)
-        NNDTW_BSEARCH_CASE(2, 0)
-        NNDTW_BSEARCH_CASE(2, 1)
-        NNDTW_BSEARCH_CASE(3, 0)
-        NNDTW_BSEARCH_CASE(3, 1)
-        NNDTW_BSEARCH_CASE(4, 0)
-        NNDTW_BSEARCH_CASE(4, 1)
+        NNDTW_BSEARCH_CASE(1, 0, 0)
+        NNDTW_BSEARCH_CASE(1, 0, 1)
+        NNDTW_BSEARCH_CASE(1, 1, 0)
+        NNDTW_BSEARCH_CASE(1, 1, 1)
+        NNDTW_BSEARCH_CASE(2, 0, 0)
+        NNDTW_BSEARCH_CASE(2, 0, 1)
+        NNDTW_BSEARCH_CASE(2, 1, 0)
+        NNDTW_BSEARCH_CASE(2, 1, 1)
+        NNDTW_BSEARCH_CASE(3, 0, 0)
+        NNDTW_BSEARCH_CASE(3, 0, 1)
+        NNDTW_BSEARCH_CASE(3, 1, 0)
+        NNDTW_BSEARCH_CASE(3, 1, 1)
+        NNDTW_BSEARCH_CASE(4, 0, 0)
+        NNDTW_BSEARCH_CASE(4, 0, 1)
+        NNDTW_BSEARCH_CASE(4, 1, 0)
+        NNDTW_BSEARCH_CASE(4, 1, 1)
 #undef NNDTW_BSEARCH_CASE
     default:
         return fail(NNDTW_EUNSUP, "batch search: %d pairs per lane not supported", C);

@@ -44,13 +44,13 @@ class Request:
     result: tuple = field(default=None)   # (nn index, nn distance, counts[8])
 
 
-def batch_bytes(refsets, counts, V=5, cascade="keogh_enh", waves=0):
+def batch_bytes(refsets, counts, V=5, cascade="keogh_enh", waves=0, helpers=0):
     """Device workspace of a batch with counts[s] queries for set s."""
     arr = (_BatchSet * len(refsets))()
     for d, (rs, c) in enumerate(zip(refsets, counts)):
         arr[d].refset = ctypes.addressof(rs.desc)
         arr[d].nQ = int(c)
-    opts = _opts(V, cascade, 0, 0.0, True, 0, waves)
+    opts = _opts(V, cascade, 0, 0.0, True, 0, waves, helpers=helpers)
     nbytes = ctypes.c_size_t(0)
     _check(lib().nndtw_batch_workspace_bytes(arr, len(refsets), ctypes.byref(opts), ctypes.byref(nbytes)))
     return int(nbytes.value)
@@ -119,17 +119,19 @@ class Server:
     """Continuous batching over ``refsets`` (a list of RefSet) on
     ``n_streams`` streams; each batch holds at most ``max_batch`` requests,
     and the workspaces of all batches in flight fit in ``budget_bytes``.
-    ``R`` and ``cpl`` (per set or None) are passed to every batch."""
+    ``R`` and ``cpl`` (per set or None) are passed to every batch;
+    ``helpers`` too (idle workgroups that join a batch's running queries)."""
 
     def __init__(self, refsets, n_streams: int = 3, max_batch: int = 512, budget_bytes: int = 1 << 30,
-                 V: int = 5, R=None, cpl=None):
+                 V: int = 5, R=None, cpl=None, helpers: int = 0):
         self.refsets = list(refsets)
         dev = self.refsets[0].device
         self.max_batch = max_batch
         self.V = V
+        self.helpers = helpers
         # workspace of one query per set: an upper bound of what each query
         # adds to a batch (it includes the batch's fixed part once more)
-        self.per_query = [batch_bytes([rs], [1], V) for rs in self.refsets]
+        self.per_query = [batch_bytes([rs], [1], V, helpers=helpers) for rs in self.refsets]
         if max(self.per_query) > budget_bytes:
             raise ValueError(f"budget of {budget_bytes} bytes below one query's workspace {max(self.per_query)}")
         self.arena = Arena(budget_bytes, dev)
@@ -143,7 +145,7 @@ class Server:
         self.plan_R, self.plan_cpl = list(probe.R), list(probe.cpl)
         del probe
         torch.cuda.synchronize(dev)
-        self.opts = _opts(V, "keogh_enh", 0, 0.0, True, 0)
+        self.opts = _opts(V, "keogh_enh", 0, 0.0, True, 0, helpers=helpers)
         self.stats = {}
 
     def _launch(self, reqs, slot: _Slot, block):
@@ -190,7 +192,7 @@ class Server:
         for r in reqs:
             counts[r.set_id] = counts.get(r.set_id, 0) + 1
         sets = sorted(counts)
-        return batch_bytes([self.refsets[s] for s in sets], [counts[s] for s in sets], self.V)
+        return batch_bytes([self.refsets[s] for s in sets], [counts[s] for s in sets], self.V, helpers=self.helpers)
 
     def run(self, requests, poll_sleep: float = 0.0):
         """Serve `requests` (sorted by arrival time) in real time; returns

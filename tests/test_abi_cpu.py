@@ -149,9 +149,11 @@ def test_refset_and_search_validation():
 def test_batch_struct_layouts():
     assert ctypes.sizeof(nd._BatchSet) == 64
     assert nd._BatchSet.R.offset == 48 and nd._BatchSet.cpl.offset == 56
-    assert ctypes.sizeof(nd._BatchPlan) == 304
+    assert ctypes.sizeof(nd._BatchPlan) == 320
     assert nd._BatchPlan.order_off.offset == 48 and nd._BatchPlan.search_off.offset == 144
     assert nd._BatchPlan.reserved.offset == 272
+    assert nd._BatchPlan.helpers.offset == 304 and nd._BatchPlan.share_shapes.offset == 308
+    assert nd._BatchPlan.share_off.offset == 312
 
 
 def test_batch_validation_and_workspace_size():
@@ -170,6 +172,14 @@ def test_batch_validation_and_workspace_size():
     assert lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(opts), ctypes.byref(nbytes)) == 0
     # at least the three sets' search workspaces (bounds, order, gathered bounds)
     assert nbytes.value >= sum(8 * 7 * (5 + i) * d.n for i, d in enumerate(descs))
+    # without helper workgroups: no helper header per query (18 queries)
+    no_help = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, helpers=-1)
+    nb2 = ctypes.c_size_t(0)
+    assert lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(no_help), ctypes.byref(nb2)) == 0
+    assert nbytes.value - nb2.value == (18 * 3136 + 255) // 256 * 256
+    bad = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, helpers=8)
+    assert _err(lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(bad), ctypes.byref(nb2)),
+                "helpers=8") == nd.EINVAL
     assert _err(lib.nndtw_batch_workspace_bytes(sets, 0, ctypes.byref(opts), ctypes.byref(nbytes)),
                 "nsets=0") == nd.EINVAL
     assert _err(lib.nndtw_batch_workspace_bytes(None, 3, ctypes.byref(opts), ctypes.byref(nbytes)),

@@ -478,9 +478,9 @@ def test_search_eps_floor_with_duplicates():
 
 
 # ------------------------------------------------------------------ batching
-def run_batch(datasets, V=5, R=None, cpl=None, waves=0):
+def run_batch(datasets, V=5, R=None, cpl=None, waves=0, helpers=0):
     pairs = [(nd.RefSet(dev(ds.refs), ds.W), dev(ds.queries)) for ds in datasets]
-    bsr = nd.BatchSearcher(pairs, V=V, R=R, cpl=cpl, waves=waves)
+    bsr = nd.BatchSearcher(pairs, V=V, R=R, cpl=cpl, waves=waves, helpers=helpers)
     out = bsr()
     return bsr, pairs, [(host(i), host(d), host(c)) for i, d, c in out]
 
@@ -550,6 +550,39 @@ def test_batch_graph_replay():
         for d, (i, dd, c) in enumerate(bsr.out):
             assert np.array_equal(host(i), ref[d][0]) and np.array_equal(host(dd), ref[d][1])
             assert np.array_equal(host(c)[:, :5], ref[d][2][:, :5])
+
+
+def _batch_helper_counts(bsr):
+    """Helper workgroups that joined each item's query in the last call: the
+    helpers word of the items' headers in the workspace (3136-byte
+    QueryShare at plan.share_off per item, byte 20 = (1 << 12) | count)."""
+    n, off = int(bsr.plan.items), int(bsr.plan.share_off)
+    raw = bsr.ws[off:off + n * 3136].view(n, 3136)[:, 20:24].contiguous().cpu().numpy().view(np.uint32).ravel()
+    return np.where((raw >> 12) == 1, raw & 0xFFF, 0)
+
+
+@pytest.mark.parametrize("helpers", [-1, 1, 3, 0])
+def test_batch_helper_workgroups(helpers):
+    """A batch of a few long queries (each search kernel is all tail): the
+    idle persistent workgroups join the running queries, at most `helpers`
+    per query (0: the default 7, -1: none), and every result and defined
+    count equals the oracle's at the batch's R."""
+    sets = synth.batch_workload(n_sets=3, L_range=(500, 900), N_range=(500, 700), q_frac=0.004)
+    say("batch helpers", helpers, [ds.queries.shape for ds in sets])
+    bsr, pairs, res = run_batch(sets, helpers=helpers)
+    cap = {-1: 0, 0: 7}.get(helpers, helpers)
+    assert bsr.helpers == cap
+    if cap > 0:
+        assert int(bsr.plan.share_shapes) != 0
+        joined = _batch_helper_counts(bsr)
+        say("batch helpers joined", joined.tolist())
+        assert joined.max() >= 1 and joined.max() <= cap
+    else:
+        assert int(bsr.plan.share_shapes) == 0
+    for d, ds in enumerate(sets):
+        gi, gd, gc = res[d]
+        oi, od, oc = oracle.search(ds.refs, ds.queries, ds.W, 5, "keogh_enh", bsr.R[d], True)
+        assert np.array_equal(gi, oi) and np.array_equal(gd, od) and np.array_equal(gc[:, :5], oc[:, :5])
 
 
 def test_batch_full_workload():
