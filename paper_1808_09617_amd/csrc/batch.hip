@@ -10,8 +10,8 @@
 //      workgroups take (set, query) items from the shape's counter, largest
 //      expected work (n * L * (2W'+1)) first; once the items are all taken,
 //      idle workgroups help the queries still running (shared FP32 batches,
-//      as the single-query search's helper workgroups), after a reset of the
-//      items' helper headers.
+//      as the single-query search's helper workgroups; the bound pass clears
+//      the items' helper headers).
 // Everything the kernels need (set descriptors, item lists, tile starts) is
 // copied into the caller's workspace once, at planning time (enqueued on the
 // stream, without waiting), so the launch sequence allocates and copies
@@ -99,11 +99,16 @@ int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, 
     std::vector<int> width(nsets);
     int NW = 0;
     size_t lds = 0;
+    // the waves per query follow the whole batch's query count (8 when the
+    // batch's queries do not fill the device at 4 waves each)
+    int64_t nitems = 0;
+    for (int d = 0; d < nsets; ++d) nitems += sets[d].nQ;
     for (int d = 0; d < nsets; ++d) {
         const nndtw_refset *rs = sets[d].refset;
         nndtw_search_opts od = *o;
         od.R = sets[d].R;
         od.cpl = sets[d].cpl;
+        od.nq_hint = nitems;
         SearchPlan sp;
         if (int r = plan_search(rs, &od, &sp, true)) return r;
         if (sp.C > 4)
@@ -271,9 +276,9 @@ int batch_launch(const nndtw_batch_plan *plan, void *ws, hipStream_t st)
     const int64_t *oitems = (const int64_t *)(base + plan->reserved[2]);
     const int64_t *tstart = (const int64_t *)(base + plan->reserved[3]);
     BatchHdr *hdr = (BatchHdr *)base;
-    if (int r = launch_batch_bounds(sets, plan->nsets, tstart, plan->tiles, hdr, st)) return r;
-    if (plan->share_shapes != 0u)
-        if (int r = launch_share_reset((QueryShare *)(base + plan->share_off), plan->items, st)) return r;
+    QueryShare *share = plan->share_shapes != 0u ? (QueryShare *)(base + plan->share_off) : nullptr;
+    if (int r = launch_batch_bounds(sets, plan->nsets, tstart, plan->tiles, hdr, share, share ? plan->items : 0, st))
+        return r;
     for (int s = 0; s < N_WIDTHS; ++s)
         if (plan->order_cnt[s] > 0)
             if (int r = launch_batch_order(1 << s, sets, oitems + plan->order_off[s], plan->order_cnt[s], st)) return r;

@@ -228,14 +228,19 @@ cascade_bounds_kernel(const float *__restrict__ Bt, const float *__restrict__ Ut
 
 // The bound pass of a batch: one workgroup per tile of any set; the set is
 // found by binary search over the tiles' start indices.  Also resets the
-// work counter of the batch's search kernel, which runs after it.
+// work counters of the batch's search kernels and clears the items' helper
+// headers (those kernels run after it).  A tile with a single query (the
+// usual case of a serving batch) runs the one-query body: the per-point
+// chain of each thread is then a quarter as long.
 template <int TQ>
 __global__ void __launch_bounds__(CB_THREADS)
 batch_bounds_kernel(const BatchSet *__restrict__ sets, int nsets, const int64_t *__restrict__ tile_start,
-                    BatchHdr *hdr)
+                    BatchHdr *hdr, QueryShare *share, int64_t nshare)
 {
     const int64_t tile = blockIdx.x;
     if (tile == 0 && threadIdx.x < BATCH_SHAPES) hdr->counter[threadIdx.x] = 0u;
+    for (int64_t i = tile * CB_THREADS + threadIdx.x; i < nshare; i += (int64_t)gridDim.x * CB_THREADS)
+        share_clear(share[i]);
     int lo = 0, hi = nsets - 1;                 // last set with tile_start <= tile
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -244,18 +249,23 @@ batch_bounds_kernel(const BatchSet *__restrict__ sets, int nsets, const int64_t 
     const int d = __builtin_amdgcn_readfirstlane(lo);
     const BatchSet &b = sets[d];
     const int64_t local = tile - tile_start[d];
-    bounds_tile<TQ>(local % b.nrt, local / b.nrt, b.Bt, b.Ut, b.Lt, b.pitch, b.a.n, b.a.Q, b.nQ, b.L, b.W,
-                    b.nb, b.ed2w, b.lbk, b.lbeb, b.lbe, rotation_phase(b.a.ncu));
+    const int64_t rt = local % b.nrt, qt = local / b.nrt;
+    if (b.nQ - qt * TQ == 1)
+        bounds_tile<1>(rt, qt * TQ, b.Bt, b.Ut, b.Lt, b.pitch, b.a.n, b.a.Q, b.nQ, b.L, b.W, b.nb, b.ed2w, b.lbk,
+                       b.lbeb, b.lbe, rotation_phase(b.a.ncu));
+    else
+        bounds_tile<TQ>(rt, qt, b.Bt, b.Ut, b.Lt, b.pitch, b.a.n, b.a.Q, b.nQ, b.L, b.W, b.nb, b.ed2w, b.lbk,
+                        b.lbeb, b.lbe, rotation_phase(b.a.ncu));
 }
 
 constexpr int BATCH_TQ = 4;
 
 int launch_batch_bounds(const BatchSet *sets, int nsets, const int64_t *tile_start, int64_t tiles, BatchHdr *hdr,
-                        hipStream_t st)
+                        QueryShare *share, int64_t nshare, hipStream_t st)
 {
     if (tiles == 0) return NNDTW_OK;
     hipLaunchKernelGGL(batch_bounds_kernel<BATCH_TQ>, dim3((unsigned)tiles), dim3(CB_THREADS), 0, st, sets, nsets,
-                       tile_start, hdr);
+                       tile_start, hdr, share, nshare);
     NNDTW_LAUNCH_CHECK("batch bound kernel launch");
     return NNDTW_OK;
 }

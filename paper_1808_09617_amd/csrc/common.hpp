@@ -80,8 +80,9 @@ struct BatchSet;
 struct BatchHdr;
 struct QueryShare;
 struct EngineGeom;
+// Also clears the helper headers share[0 .. nshare) of the batch's items.
 int launch_batch_bounds(const BatchSet *sets, int nsets, const int64_t *tile_start, int64_t tiles,
-                        BatchHdr *hdr, hipStream_t s);
+                        BatchHdr *hdr, QueryShare *share, int64_t nshare, hipStream_t s);
 // compare.hip: what = 0 LB_Kim, 1 LB_Improved, 2 LB_New, 3 symmetric LB_Enhanced
 int launch_compare_bounds(int what, const float *A, int64_t nA, const float *B, const float *U,
                           const float *Lo, int64_t nB, int L, int W, int V, const double *cutoff,
@@ -123,12 +124,10 @@ int launch_cells_prefix(int L, int Wp, uint32_t *prefix, hipStream_t s);
 int order_width(int64_t n);     // visiting-order sort size class: npow = 256 * width
 int launch_batch_order(int E, const BatchSet *sets, const int64_t *items, int64_t nitems, hipStream_t s);
 // helpers > 0: the kernel lends idle workgroups to running queries, at most
-// `helpers` per query (their QueryShare headers reset by launch_share_reset)
+// `helpers` per query (their QueryShare headers cleared by the bound pass)
 int launch_batch_search(int C, bool exact, const BatchSet *sets, const int64_t *items, int64_t nitems,
                         unsigned *counter, unsigned *running, int waves, int grid, size_t lds, int helpers,
                         hipStream_t s);
-// Zeroes the helper headers of nq queries.
-int launch_share_reset(QueryShare *share, int64_t nq, hipStream_t s);
 size_t search_lds_bytes(const EngineGeom &g, const EngineGeom &gd, int SLOTS, int PD);
 // Compute units of the current device (0 if it cannot be queried).
 int device_cu_count();
@@ -191,6 +190,17 @@ struct QueryShare {
     unsigned res[SHARE_SLOTS];
     int trun[SHARE_SLOTS];
 };
+// Clears the header words of a QueryShare (before a launch whose epoch may
+// repeat an earlier one); the slots need no clearing.
+__device__ __forceinline__ void share_clear(QueryShare &s)
+{
+    s.deal = 0ull;
+    s.done = 0u;
+    s.nt = 0u;
+    s.helpers = 0u;
+    s.finished = 0u;
+    s.started = 0u;
+}
 
 // Arguments of the per-query search (search.hip): one query against one
 // reference set, with the workspace of that set.

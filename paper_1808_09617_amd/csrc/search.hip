@@ -977,22 +977,7 @@ search_kernel_wide(SearchArgs a)
 __global__ void __launch_bounds__(256) share_reset_kernel(QueryShare *share, int64_t nq)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nq) {
-        share[q].deal = 0ull;
-        share[q].done = 0u;
-        share[q].nt = 0u;
-        share[q].helpers = 0u;
-        share[q].finished = 0u;
-        share[q].started = 0u;
-    }
-}
-
-int launch_share_reset(QueryShare *share, int64_t nq, hipStream_t st)
-{
-    if (nq <= 0) return NNDTW_OK;
-    hipLaunchKernelGGL(share_reset_kernel, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, st, share, nq);
-    NNDTW_LAUNCH_CHECK("share reset kernel launch");
-    return NNDTW_OK;
+    if (q < nq) share_clear(share[q]);
 }
 
 // Whether a plan may use more than SEARCH_MAX_WAVES waves (search_kernel_wide).
@@ -1247,15 +1232,14 @@ int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *
     // Waves per query: a query's rounds are a chain of dependent steps, so the
     // kernel lasts as long as its most expensive query (on the 5000 x 500,
     // L=512 workload one query does 3.7 times the mean work).  When the
-    // queries do not fill the device at 4 waves each, each gets 8.
-    // When the queries do not fill the device at 4 waves each, each gets 8,
+    // queries do not fill the device at 4 waves each, each gets 8,
     // or 16 where the shape fits 128 VGPRs (5000 x 500, L=512, W=51: search
     // kernel 5.1 ms at 4 waves, 3.3 ms at 8, 2.5 ms at 16).
     int NW = o->waves;
     if (NW <= 0) {
         const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
-        const bool few = !batched && o->nq_hint > 0 && o->nq_hint <= 2 * (int64_t)cu;
-        NW = few ? (wide_ok(C, Wp) ? SEARCH_WIDE_WAVES : 8) : SEARCH_DEFAULT_WAVES;
+        const bool few = o->nq_hint > 0 && o->nq_hint <= 2 * (int64_t)cu;
+        NW = few ? (!batched && wide_ok(C, Wp) ? SEARCH_WIDE_WAVES : 8) : SEARCH_DEFAULT_WAVES;
     }
     if (NW > SEARCH_MAX_WAVES && (batched || !wide_ok(C, Wp)))
         return fail(NNDTW_EUNSUP, "waves=%d: more than %d waves per query need a window of at most 63 diagonal "

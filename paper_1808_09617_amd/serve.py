@@ -105,14 +105,19 @@ class _Slot:
     def __init__(self, device, max_batch: int, Lmax: int):
         self.stream = torch.cuda.Stream(device=device)
         self.q = torch.empty(max_batch * Lmax, dtype=torch.float32, device=device)
-        self.idx = torch.empty(max_batch, dtype=torch.int64, device=device)
-        self.dist = torch.empty(max_batch, dtype=torch.float64, device=device)
-        self.counts = torch.empty((max_batch, 8), dtype=torch.int64, device=device)
-        self.h_idx = torch.empty(max_batch, dtype=torch.int64, pin_memory=True)
-        self.h_dist = torch.empty(max_batch, dtype=torch.float64, pin_memory=True)
-        self.h_counts = torch.empty((max_batch, 8), dtype=torch.int64, pin_memory=True)
+        # one buffer [nn_idx | nn_dist | counts] (so that one copy returns a
+        # batch's results), and its pinned host twin
+        mb = max_batch
+        self.out = torch.empty(10 * mb, dtype=torch.int64, device=device)
+        self.h_out = torch.empty(10 * mb, dtype=torch.int64, pin_memory=True)
+        self.idx, self.dist, self.counts = self._views(self.out, mb)
+        self.h_idx, self.h_dist, self.h_counts = self._views(self.h_out, mb)
         self.plan = _BatchPlan()
         self.event = torch.cuda.Event()
+
+    @staticmethod
+    def _views(buf, mb):
+        return buf[:mb], buf[mb:2 * mb].view(torch.float64), buf[2 * mb:].view(mb, 8)
 
 
 class Server:
@@ -181,9 +186,8 @@ class Server:
             _check(lib().nndtw_batch_prepare(arr, len(sets), ctypes.byref(self.opts), ws, block[1],
                                              ctypes.byref(slot.plan), st))
             _check(lib().nndtw_search_batch(ctypes.byref(slot.plan), ws, st))
-            slot.h_idx[:row].copy_(slot.idx[:row], non_blocking=True)
-            slot.h_dist[:row].copy_(slot.dist[:row], non_blocking=True)
-            slot.h_counts[:row].copy_(slot.counts[:row], non_blocking=True)
+            end = 2 * self.max_batch + 8 * row      # through the batch's last counts row
+            slot.h_out[:end].copy_(slot.out[:end], non_blocking=True)
             slot.event.record(slot.stream)
         return row_of
 
