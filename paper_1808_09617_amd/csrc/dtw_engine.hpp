@@ -197,23 +197,34 @@ __device__ __forceinline__ int shared_deal(unsigned long long *deal64, uint32_t 
 }
 
 // Optional per-cell record of the minimising predecessor (for the argmin
-// warping path): codes(task) is the task's word array [T/8][W'+1]; the
-// nibble 4*(t%8) of word (t/8, p) holds the code of pair p's bottom cell at
-// super-step t in its bits 0-1 and of its top cell in bits 2-3:
-// 0 = (i-1, j-1), 1 = (i-1, j), 2 = (i, j-1), the first of them that
-// attains the minimum.  Needs M % 8 == 0 (then T % 8 == 0 too).
+// warping path): codes(task) is the task's word array [T/8][W'+1]; word
+// (t/8, p) holds pair p's cells of the 8 super-steps 8(t/8) .. 8(t/8)+7,
+// four bits each, the first super-step in the top bits.  For super-step u
+// of the word: bit 31-4u is set when the bottom cell's predecessor
+// (i-1, j-1) is above the smaller of the other two, bit 30-4u when (i-1, j)
+// is above (i, j-1); bits 29-4u and 28-4u the same for the top cell.  The
+// path takes (i-1, j-1) if the first bit is clear, else (i-1, j) if the
+// second is, else (i, j-1): the first of the three that attains the minimum.
+// Needs M % 8 == 0 (then T % 8 == 0 too).
 struct NoCodes {
     static constexpr bool on = false;
     __device__ uint32_t *operator()(int) const { return nullptr; }
 };
 
-__device__ __forceinline__ unsigned argmin_code(float dg, float up, float lf)
+// Shifts into the bottom of cw whether x > ref.  DTW values are
+// non-negative floats or +inf, whose bit patterns order like the values and
+// lie below 2^31, so the sign bit of the 32-bit difference ref - x is set
+// exactly when x > ref: one subtract and one funnel shift, no lane mask
+// (whose write and read would need wait states between them).  A cell's
+// bits compare its predecessors with each other, not with their minimum,
+// which then need not outlive the cell's update.
+__device__ __forceinline__ uint32_t push_code(uint32_t cw, float x, float ref)
 {
-    return dg <= __builtin_fminf(up, lf) ? 0u : (up <= lf ? 1u : 2u);
+    return __builtin_amdgcn_alignbit(cw, __float_as_uint(ref) - __float_as_uint(x), 31);
 }
-__device__ __forceinline__ unsigned argmin_code(double dg, double up, double lf)
+__device__ __forceinline__ uint32_t push_code(uint32_t cw, double x, double ref)
 {
-    return dg <= __builtin_fmin(up, lf) ? 0u : (up <= lf ? 1u : 2u);
+    return (cw << 1) | (x > ref ? 1u : 0u);
 }
 
 // Run `ntasks` DTW tasks on the P groups of each calling wave.  Tasks are
@@ -367,13 +378,13 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
         for (int u = 0; u < M; ++u) {
             // bottom diagonals: anti-diagonal s_b(t)
             const T nb = from_lower(X1[C - 1]);
-            unsigned code[C];
 #pragma unroll
             for (int m = 0; m < C; ++m) {
                 const T lo = (m == 0) ? nb : X1[m - 1];
                 const T d = Aw[(u + m) % M] - Bw[(u - m + M) % M];
                 // predecessors: (i-1,j-1) = X0[m], (i-1,j) = lo, (i,j-1) = X1[m]
-                if constexpr (Codes::on) code[m] = argmin_code(X0[m], lo, X1[m]);
+                if constexpr (Codes::on)
+                    cw[m] = push_code(push_code(cw[m], X0[m], vmin(lo, X1[m])), lo, X1[m]);
                 X0[m] = cell(d, min3(X0[m], lo, X1[m]));
             }
             // top diagonals: anti-diagonal s_b(t) + 1
@@ -383,12 +394,13 @@ __device__ __forceinline__ void engine_run(const EngineGeom &geo, int ntasks, in
                 const T hi = (m == C - 1) ? nt : X0[m + 1];
                 const T d = Aw[(u + m + 1) % M] - Bw[(u - m + M) % M];
                 // predecessors: (i-1,j-1) = X1[m], (i-1,j) = X0[m], (i,j-1) = hi
-                if constexpr (Codes::on) code[m] |= argmin_code(X1[m], X0[m], hi) << 2;
+                if constexpr (Codes::on)
+                    cw[m] = push_code(push_code(cw[m], X1[m], vmin(X0[m], hi)), X0[m], hi);
                 X1[m] = cell(d, min3(X1[m], X0[m], hi));
             }
+            // a word holds 8 super-steps (32 bits); cleared once stored, so
+            // that no code word is live outside this loop
             if constexpr (Codes::on) {
-#pragma unroll
-                for (int m = 0; m < C; ++m) cw[m] |= code[m] << (4 * (u % 8));
                 if (u % 8 == 7) {
                     if (task >= 0) {
 #pragma unroll

@@ -152,9 +152,12 @@ __device__ __forceinline__ void walk_path(const EngineGeom &geo, const uint32_t 
             widx = wi;
             word = codes[wi];
         }
-        const unsigned c = (word >> (4 * (t & 7) + (top ? 2 : 0))) & 3u;
-        if (c == 0) { --i; --j; }
-        else if (c == 1) { --i; }
+        // the cell's two bits: bit 1 (i-1, j-1) above the smaller of the
+        // other two predecessors, bit 0 (i-1, j) above (i, j-1)
+        const unsigned nib = (word >> (28 - 4 * (t & 7))) & 0xFu;
+        const unsigned c = top ? (nib & 3u) : (nib >> 2);
+        if ((c & 2u) == 0u) { --i; --j; }
+        else if ((c & 1u) == 0u) { --i; }
         else { --j; }
         if (i < 0 || j < 0 || i - j > Wp || j - i > Wp) break;
     }
