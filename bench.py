@@ -409,10 +409,31 @@ def small_latency(nd, synth, torch, dev, calls=1000):
         e1.record()
     torch.cuda.synchronize()
     lat = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    # the same call captured once in a graph and replayed (one launch per call)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        sr(qs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sr(qs)
+    for _ in range(10):
+        g.replay()
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record()
+        g.replay()
+        e1.record()
+    torch.cuda.synchronize()
+    glat = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    pct = lambda v: {"p50": v[calls // 2], "p99": v[int(math.ceil(0.99 * calls)) - 1], "max": v[-1]}
     return {"workload": "nndtw-small", "N": wl.refs.shape[0], "Q": wl.queries.shape[0], "L": wl.L,
-            "W": wl.windows[0], "V": wl.vs[0], "calls": calls, "latency_ms": {
-                "p50": lat[calls // 2], "p99": lat[int(math.ceil(0.99 * calls)) - 1], "max": lat[-1]},
-            "queries_per_s_at_p50": wl.queries.shape[0] / (lat[calls // 2] / 1e3)}
+            "W": wl.windows[0], "V": wl.vs[0], "calls": calls, "latency_ms": pct(lat),
+            "graph_latency_ms": pct(glat),
+            "queries_per_s_at_p50": wl.queries.shape[0] / (lat[calls // 2] / 1e3),
+            "queries_per_s_at_p50_graph": wl.queries.shape[0] / (glat[calls // 2] / 1e3)}
 
 
 def arms_2x2(nd, torch, rs, qs, V, nq_per_query=100, reps=3):

@@ -585,6 +585,42 @@ def test_batch_helper_workgroups(helpers):
         assert np.array_equal(gi, oi) and np.array_equal(gd, od) and np.array_equal(gc[:, :5], oc[:, :5])
 
 
+@pytest.mark.parametrize("name,W,V,helpers", [("nndtw-small", 6, 1, 0), ("nndtw-sin256", 26, 5, 3)])
+def test_search_graph_replay(name, W, V, helpers):
+    """The single search captured in a graph (one launch per call): every
+    replay, with eager work and synchronisation between replays, reproduces
+    the eager result (with helper workgroups too, whose headers the captured
+    reset kernel clears on every replay)."""
+    wl = synth.workload(name)
+    nq = min(wl.queries.shape[0], 200)
+    rs = nd.RefSet(dev(wl.refs), W)
+    qs = dev(wl.queries[:nq])
+    sr = nd.Searcher(rs, nq, V=V, helpers=helpers)
+    ref = [host(x).copy() for x in sr(qs)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        sr(qs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sr(qs)
+    for rep in range(3):
+        say("search graph replay", name, rep)
+        sr.idx.fill_(-7)
+        sr.dist.fill_(-1.0)
+        sr.counts.fill_(-3)
+        x = torch.randn(4096, device=DEV)
+        (x * x).sum().item()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(sr.idx), ref[0]) and np.array_equal(host(sr.dist), ref[1])
+        assert np.array_equal(host(sr.counts)[:, :5], ref[2][:, :5])
+    oi, od, oc = oracle.search(wl.refs, wl.queries[:4], W, V, "keogh_enh", sr.R, True)
+    assert np.array_equal(ref[0][:4], oi) and np.array_equal(ref[1][:4], od)
+
+
 def test_batch_full_workload():
     """The full batching workload (64 sets, L 25..1839, 26,583 queries) in the
     benchmarked launch shape: every query against size-independent
