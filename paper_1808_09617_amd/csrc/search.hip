@@ -57,6 +57,7 @@ constexpr int SEARCH_DEFAULT_HELPERS = 3;
 // kernels are not held to 128 and share at every shape.)
 __host__ __device__ constexpr bool share_ok(int C) { return C != 3 && C != 6; }
 constexpr int ORDER_THREADS = 256;
+constexpr int ORDER_LDS_PER_POSITION = 10;  // FP64 key + 16-bit index (order_query)
 
 // ------------------------------------------------------------ workspace
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -136,12 +137,15 @@ __device__ __forceinline__ void keep(double &k, uint32_t &x, double ko, uint32_t
 
 // Bitonic sort of the (key, index) pairs held in registers: thread t of NT
 // holds positions t*E .. t*E+E-1 before and after.  Whole-workgroup call.
-template <int E, int NT>
+// IX: the type the indices take in LDS (uint16_t when every index, padding
+// included, is below 2^16: 10 bytes per position instead of 12, so that two
+// 8192-position sorts fit a compute unit's LDS).
+template <int E, int NT, typename IX = uint32_t>
 __device__ __forceinline__ void sort_pairs(double (&k)[E], uint32_t (&x)[E], unsigned char *smem)
 {
     constexpr int npow = NT * E;
     double *key = reinterpret_cast<double *>(smem);
-    uint32_t *idx = reinterpret_cast<uint32_t *>(key + npow);
+    IX *idx = reinterpret_cast<IX *>(key + npow);
     const int t = threadIdx.x;
     for (int size = 2; size <= npow; size <<= 1) {
         int stride = size >> 1;
@@ -149,13 +153,13 @@ __device__ __forceinline__ void sort_pairs(double (&k)[E], uint32_t (&x)[E], uns
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 key[t * E + r] = k[r];
-                idx[t * E + r] = x[r];
+                idx[t * E + r] = (IX)x[r];
             }
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 const int e = t * E + r, p = e ^ stride;
-                keep(k[r], x[r], key[p], idx[p], ((e & stride) == 0) == ((e & size) == 0));
+                keep(k[r], x[r], key[p], (uint32_t)idx[p], ((e & stride) == 0) == ((e & size) == 0));
             }
             __syncthreads();
         }
@@ -188,8 +192,9 @@ __device__ __forceinline__ void sort_pairs(double (&k)[E], uint32_t (&x)[E], uns
     }
 }
 
-// Visiting order of one query of a set of n <= NT * E references, sorted on
-// chip, with the bounds gathered in that order.
+// Visiting order of one query of a set of n <= NT * E <= 8192 references,
+// sorted on chip, with the bounds gathered in that order.  Indices (and the
+// padding's 0xFFFF) fit 16 bits, which is how they are kept in LDS.
 template <int E, int NT>
 __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *__restrict__ ed2,
                                             const double *__restrict__ lbk, const double *__restrict__ lbeb,
@@ -198,8 +203,9 @@ __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *
                                             double *__restrict__ slbe, unsigned char *smem)
 {
     constexpr int npow = NT * E;
+    static_assert(npow <= 0xFFFF, "16-bit indices");
     double *key = reinterpret_cast<double *>(smem);
-    uint32_t *idx = reinterpret_cast<uint32_t *>(key + npow);
+    uint16_t *idx = reinterpret_cast<uint16_t *>(key + npow);
     const int t = threadIdx.x;
     const double *e2 = ed2 + q * n;
     double k[E];
@@ -208,14 +214,14 @@ __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *
     for (int r = 0; r < E; ++r) {
         const int e = t * E + r;
         k[r] = e < n ? e2[e] : __builtin_inf();
-        x[r] = e < n ? (uint32_t)e : 0xFFFFFFFFu;
+        x[r] = e < n ? (uint32_t)e : 0xFFFFu;
     }
-    sort_pairs<E, NT>(k, x, smem);
+    sort_pairs<E, NT, uint16_t>(k, x, smem);
 #pragma unroll
-    for (int r = 0; r < E; ++r) idx[t * E + r] = x[r];
+    for (int r = 0; r < E; ++r) idx[t * E + r] = (uint16_t)x[r];
     __syncthreads();
     for (int i = t; i < n; i += NT) {
-        const uint32_t kk = idx[i];
+        const uint32_t kk = (uint32_t)idx[i];
         const int64_t o = q * n + i;
         sk[o] = kk;
         slbk[o] = lbk[q * n + kk];
@@ -333,8 +339,13 @@ __device__ void cells_prefix_wave(int L, int Wp, uint32_t *__restrict__ prefix, 
     }
 }
 
+// The 8192-position sort (512 threads of 16 positions, 80 KB of LDS) is held
+// to 128 VGPRs so that two of its workgroups share a compute unit: each alone
+// is bound by the latency of its barrier-separated steps (1024 threads of 8
+// positions took 96 KB with 32-bit indices, one workgroup per unit, and
+// spilled when held to the 64 VGPRs two such workgroups would need).
 template <int E, int NT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * E >= 8192 ? 4 : 1)))
 order_kernel(int64_t n, const double *__restrict__ ed2, const double *__restrict__ lbk,
              const double *__restrict__ lbeb, const double *__restrict__ lbe, uint32_t *__restrict__ sk,
              double *__restrict__ slbk, double *__restrict__ slbeb, double *__restrict__ slbe, int L, int Wp,
@@ -349,7 +360,7 @@ order_kernel(int64_t n, const double *__restrict__ ed2, const double *__restrict
 // The ordering of a batch: one workgroup per (set, query) item of the sets
 // whose sort width is E (items are (set << 32) | query).
 template <int E, int NT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * E >= 8192 ? 4 : 1)))
 batch_order_kernel(const BatchSet *__restrict__ sets, const int64_t *__restrict__ items)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -371,15 +382,15 @@ int order_width(int64_t n)
     return E;
 }
 
-// Sort shapes by padded size npow = 256 * W (W = order_width): at most 8
-// positions per thread, so large sorts run 512 or 1024 threads (more waves
-// share the one workgroup an LDS-heavy sort leaves on a CU).
-#define NNDTW_FOR_EACH_SORT(X) X(1, 1, 256) X(2, 2, 256) X(4, 4, 256) X(8, 8, 256) X(16, 8, 512) X(32, 8, 1024)
+// Sort shapes by padded size npow = 256 * W (W = order_width): up to 4096
+// positions at most 8 per thread, 8192 as 512 threads of 16 (two workgroups
+// per compute unit, see order_kernel).
+#define NNDTW_FOR_EACH_SORT(X) X(1, 1, 256) X(2, 2, 256) X(4, 4, 256) X(8, 8, 256) X(16, 8, 512) X(32, 16, 512)
 
 int launch_batch_order(int Wd, const BatchSet *sets, const int64_t *items, int64_t nitems, hipStream_t st)
 {
     if (nitems == 0) return NNDTW_OK;
-    const size_t lds = (size_t)ORDER_THREADS * Wd * 12;
+    const size_t lds = (size_t)ORDER_THREADS * Wd * ORDER_LDS_PER_POSITION;
     switch (Wd) {
 #define NNDTW_BORDER_CASE(WW, EE, NT)                                                                \
     case WW:                                                                                         \
@@ -441,7 +452,7 @@ static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *
 {
     if (n > CHUNK) return launch_order_large(n, nQ, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, L, Wp, prefix, st);
     const int Wd = order_width(n);
-    const size_t lds = (size_t)ORDER_THREADS * Wd * 12;
+    const size_t lds = (size_t)ORDER_THREADS * Wd * ORDER_LDS_PER_POSITION;
     switch (Wd) {
 #define NNDTW_ORDER_CASE(WW, EE, NT)                                                                     \
     case WW:                                                                                             \
