@@ -10,6 +10,8 @@
 //   two blocks:               max(S(a), P(b))
 //   one block, a its start:   P(b)          (a clipped to 0)
 //   one block, otherwise:     S(a)          (then b is the block's end or L-1)
+// (an unclipped window is either two blocks' or exactly one whole block,
+// where S(a) = P(b), so only the clipped ends need the one-block forms).
 // About three comparisons per element whatever W is, and max/min are exact,
 // so the result equals a direct scan bit for bit.
 //
@@ -234,24 +236,24 @@ envelopes_kernel(const float *__restrict__ B, int64_t n, int L, int Wp, float *_
         }
         wave_lds_sync();
         float uo[E], lo[E];
-        // position of the window start i - W' inside its block (positive
-        // remainder, advanced incrementally along the lane's elements)
+        // The window [a, c] of i: unclipped it has k elements, so it spans
+        // two blocks or is one whole block (where S(a) = P(c)): max(S(a),
+        // P(c)) either way.  Clipped at 0 it lies in block 0 from its start:
+        // P(c) alone.  Clipped at L-1 inside the last block (a at or after
+        // that block's start): S(a) alone.  Otherwise clipped at L-1 it
+        // spans the last two blocks: max(S(a), P(c)) again.
         const int lb = ln * E;
-        int ra = ((lb - Wp) % k + k) % k;
+        const int last_start = (L - 1) / k * k;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int i = lb + r;
             const int a = max(0, i - Wp), c = min(L - 1, i + Wp);
-            // a clipped to 0 starts block 0; the window [a, c] (at most k
-            // elements) crosses into the next block iff pos(a) + (c - a) >= k
-            const int pa = i - Wp <= 0 ? 0 : ra;
-            const bool two = pa + (c - a) >= k;
-            const bool from_start = pa == 0;
-            ra = ra + 1 == k ? 0 : ra + 1;
+            const bool no_s = i - Wp < 0;
+            const bool no_p = a >= last_start && c == L - 1 && !no_s;
             const int sa = slot<E>(a), sb = slot<E>(c);
             const float sx = sc[1][sa], px = sc[0][sb], sn = sc[3][sa], pn = sc[2][sb];
-            uo[r] = two ? __builtin_fmaxf(sx, px) : (from_start ? px : sx);
-            lo[r] = two ? __builtin_fminf(sn, pn) : (from_start ? pn : sn);
+            uo[r] = __builtin_fmaxf(no_s ? -__builtin_inff() : sx, no_p ? -__builtin_inff() : px);
+            lo[r] = __builtin_fminf(no_s ? __builtin_inff() : sn, no_p ? __builtin_inff() : pn);
         }
         store_row<E, VEC, FULL>(U + s * (int64_t)L, uo, base, L);
         store_row<E, VEC, FULL>(Lo + s * (int64_t)L, lo, base, L);
