@@ -224,6 +224,34 @@ def backward_bench(nd, synth, torch, dev, reps=5, cpu=True):
     return res
 
 
+def one_request_latency(nd, synth, torch, dev, serve, rss, Ls, R, cpl, reps=30):
+    """GPU time of a batch holding one request, per serving set (HIP events
+    around the batch's launch on its stream; median and maximum over `reps`
+    requests), with the server's own buffers and plan."""
+    server = serve.Server(rss, n_streams=1, R=R, cpl=cpl)
+    slot = server.slots[0]
+    out = {}
+    for s, L in enumerate(Ls):
+        ms = []
+        for k in range(-2, reps):                  # two untimed warm-up requests
+            q = torch.from_numpy(synth.serving_query(s, L, 5 * 10 ** 6 + k)).to(dev)
+            r = serve.Request(k, s, q, 0.0)
+            torch.cuda.synchronize()
+            blk = server.arena.alloc(server._need([r]))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(slot.stream)
+            server._launch([r], slot, blk)
+            e1.record(slot.stream)
+            e1.synchronize()
+            server.arena.free(blk)
+            if k >= 0:
+                ms.append(e0.elapsed_time(e1))
+        ms.sort()
+        out[str(L)] = {"median_ms": ms[len(ms) // 2], "max_ms": ms[-1]}
+    del server
+    return out
+
+
 def serving_bench(nd, synth, torch, dev, rate=2000.0, duration=3.0):
     """A seeded Poisson stream of NN-DTW requests at `rate` per second for
     `duration` seconds against 8 resident reference sets of 4000 random walks
@@ -262,6 +290,8 @@ def serving_bench(nd, synth, torch, dev, rate=2000.0, duration=3.0):
     _, ssum = server.run(sat)
     summary["saturation"] = {k: ssum[k] for k in ("requests", "batches", "mean_batch", "wall_s", "throughput_rps",
                                                   "max_batches_in_flight", "max_workspace_bytes", "budget_bytes")}
+    del server
+    summary["one_request"] = one_request_latency(nd, synth, torch, dev, serve, rss, Ls, R, cpl)
     del rss
     torch.cuda.empty_cache()
     return summary
@@ -666,6 +696,8 @@ def main():
     ap.add_argument("--windows-only", action="store_true", help="only the window sweep, one JSON line")
     ap.add_argument("--backward-only", action="store_true", help="only the DTW backward, one JSON line")
     ap.add_argument("--serving-only", action="store_true", help="only the serving loop, one JSON line")
+    ap.add_argument("--one-request-only", action="store_true",
+                    help="only the GPU time of one-request serving batches per set, one JSON line")
     ap.add_argument("--hbm-only", action="store_true",
                     help="only the streaming kernels on the 200,000 x 512 reference set, one JSON line")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -690,6 +722,18 @@ def main():
 
     if args.windows_only:
         print(json.dumps({"window_sweep": window_sweep(nd, synth, torch, torch.device("cuda:0"))}), flush=True)
+        return
+    if args.one_request_only:
+        from paper_1808_09617_amd import serve
+        dev = torch.device("cuda:0")
+        sets = synth.serving_sets()
+        rss = [nd.RefSet(torch.from_numpy(refs).to(dev), W) for refs, W in sets]
+        Ls = [refs.shape[1] for refs, _ in sets]
+        # the round size and shape the serving benchmark's tuner picks on this workload
+        R = [512, 512, 256, 256, 256, 256, 256, 256]
+        cpl = [3, 3, 3, 2, 2, 2, 2, 2]
+        print(json.dumps({"one_request": one_request_latency(nd, synth, torch, dev, serve, rss, Ls, R, cpl)}),
+              flush=True)
         return
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(nd, synth, torch, torch.device("cuda:0"))}), flush=True)
