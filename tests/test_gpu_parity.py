@@ -621,6 +621,36 @@ def test_search_graph_replay(name, W, V, helpers):
     assert np.array_equal(ref[0][:4], oi) and np.array_equal(ref[1][:4], od)
 
 
+@pytest.mark.parametrize("seed,helpers", [(1, -1), (2, 1), (3, 0), (4, 7)])
+def test_batch_random_edge_shapes(seed, helpers):
+    """Seeded random batches of edge shapes through the batched search: series
+    of 2 to 300 points, windows from 0 to beyond L (unconstrained), single
+    references, sets without queries, several V, with and without helper
+    workgroups; every query of every set against the oracle at the batch's R."""
+    rng = np.random.default_rng(9000 + seed)
+    sets = []
+    for d in range(7):
+        L = int(rng.choice([2, 3, 5, 17, 64, 130, 300]))
+        n = int(rng.choice([1, 2, 63, 257, 400]))
+        W = int(rng.choice([0, 1, L // 10, L // 3, L - 1, L + 5]))
+        W = min(W, 250)                                # the batch takes up to 252 diagonal pairs
+        nq = int(rng.choice([0, 1, 3, 6]))
+        refs = series(n, L, seed=10000 + 100 * seed + d, kind=("rw", "sin5")[d % 2])
+        qs = series(max(nq, 1), L, seed=20000 + 100 * seed + d, kind="rw")[:nq]
+        sets.append(synth.BatchDataset(refs, np.ascontiguousarray(qs.reshape(nq, L)), W, 5))
+    V = int(rng.choice([1, 2, 5]))
+    say("batch random", seed, helpers, V, [(ds.L, ds.refs.shape[0], ds.W, ds.queries.shape[0]) for ds in sets])
+    bsr, pairs, res = run_batch(sets, V=V, helpers=helpers)
+    for d, ds in enumerate(sets):
+        gi, gd, gc = res[d]
+        if ds.queries.shape[0] == 0:
+            assert gi.shape == (0,)
+            continue
+        oi, od, oc = oracle.search(ds.refs, ds.queries, ds.W, V, "keogh_enh", bsr.R[d], True)
+        assert np.array_equal(gi, oi), (d, gi, oi)
+        assert np.array_equal(gd, od) and np.array_equal(gc[:, :5], oc[:, :5])
+
+
 def test_batch_full_workload():
     """The full batching workload (64 sets, L 25..1839, 26,583 queries) in the
     benchmarked launch shape: every query against size-independent
