@@ -621,6 +621,33 @@ def test_search_graph_replay(name, W, V, helpers):
     assert np.array_equal(ref[0][:4], oi) and np.array_equal(ref[1][:4], od)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_search_random_edge_shapes(seed):
+    """Seeded random single searches over edge shapes: L from 2, windows from
+    0 to unconstrained, one reference, round sizes 1, 7 and the default, both
+    engines where they apply, helper workgroups off, default and at the
+    maximum; index, distance and defined counts against the oracle."""
+    rng = np.random.default_rng(7000 + seed)
+    L = int(rng.choice([2, 3, 9, 64, 200, 513, 700]))
+    n = int(rng.choice([1, 5, 100, 700]))
+    W = int(rng.choice([0, 1, max(1, L // 10), L // 2, L - 1, L + 3]))
+    nq = int(rng.choice([1, 3, 8]))
+    V = int(rng.choice([1, 3, 5]))
+    R = int(rng.choice([0, 1, 7]))
+    helpers = int(rng.choice([-1, 0, 7]))
+    engines = ["auto", "diagonal"] + (["strip"] if W >= L - 1 and L > 2 else [])
+    refs = series(n, L, seed=30000 + seed, kind="sin5")
+    qs = series(nq, L, seed=31000 + seed, kind="sin5")
+    rs = nd.RefSet(dev(refs), W)
+    for engine in engines:
+        say("search random", seed, L, n, W, nq, V, R, helpers, engine)
+        idx, dist, counts, R_used = nd.search(rs, dev(qs), V=V, R=R, engine=engine, helpers=helpers)
+        oi, od, oc = oracle.search(refs, qs, W, V, "keogh_enh", R_used, True)
+        gi, gd, gc = host(idx), host(dist), host(counts)
+        assert np.array_equal(gi, oi), (engine, gi, oi)
+        assert np.array_equal(gd, od) and np.array_equal(gc[:, :5], oc[:, :5])
+
+
 @pytest.mark.parametrize("seed,helpers", [(1, -1), (2, 1), (3, 0), (4, 7)])
 def test_batch_random_edge_shapes(seed, helpers):
     """Seeded random batches of edge shapes through the batched search: series
