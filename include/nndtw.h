@@ -478,8 +478,8 @@ int nndtw_batch_prepare(nndtw_batch_set *sets, int32_t nsets, const nndtw_search
                         void *ws, size_t ws_bytes, nndtw_batch_plan *plan, void *stream);
 
 /* Run a prepared batch: 1 + (sort widths used) + (engine shapes used)
- * kernels on `stream`, and one that resets the helper headers when
- * plan->helpers > 0.  The
+ * kernels on `stream` (the first, the bound pass, also clears the helper
+ * headers when plan->helpers > 0).  The
  * sets' reference sets, queries, outputs and ws must be those of prepare. */
 int nndtw_search_batch(const nndtw_batch_plan *plan, void *ws, void *stream);
 
