@@ -11,7 +11,13 @@ cascade.  Inputs are resident in HBM before timing starts.  The 1000 x 1000,
 L=256 class-sinusoid configuration, the whole window sweep, batching,
 serving, the backward pass and the comparison bounds are reported beside it.
 
-Prints ONE JSON line (see the design doc for every field).
+Prints ONE JSON line: the headline throughput (queries/s, whole step), the
+step's latency and stage times, the search kernel's roofline (3 VALU lane
+operations per band cell it evaluates, over its average duration from HIP
+events and, when the committed rocprofv3 summary was taken from the same
+device code, from that trace; HBM bytes per launch from the committed
+FETCH_SIZE / WRITE_SIZE summary), the pruning rates and stage counts, the CPU
+oracle's rate on a sample, and the extras above.
 """
 import argparse
 import ctypes
@@ -704,8 +710,9 @@ def main():
                     help="after timing, one plain device copy of this many MiB (memory-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(f"bench.py measures one GPU only (the search shards with no exchange; see DESIGN.md); "
-              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py measures one GPU only (queries shard across GPUs with no exchange, reference sets "
+              f"with one exchange of the per-shard minima per query); --gpus {args.gpus} is not supported",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
