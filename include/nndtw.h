@@ -301,7 +301,8 @@ typedef struct nndtw_search_opts {
                        * may join one query once a search kernel's items are all
                        * taken (idle persistent workgroups).  The result and the
                        * defined counts do not change; out (nndtw_search)     */
-    int32_t reserved;
+    int32_t order;    /* how the visiting order is found, NNDTW_ORDER_*; 0 = library
+                       * choice                                                    */
 } nndtw_search_opts;
 
 /* DTW engines of the search (opts->engine).  DIAGONAL: anti-diagonal
@@ -319,6 +320,18 @@ typedef struct nndtw_search_opts {
 #define NNDTW_ENGINE_AUTO     0
 #define NNDTW_ENGINE_DIAGONAL 1
 #define NNDTW_ENGINE_STRIP    2
+
+/* Visiting-order methods (opts->order).  SORT: one workgroup per query sorts
+ * its (squared ED, index) pairs.  RANK: each reference's place is the count
+ * of pairs that precede it, over many workgroups per query (n^2 comparisons
+ * per query, but no step depends on another; at most 8192 references and
+ * 2^20 workgroups of 64 references, else EUNSUP).  The library's choice
+ * (AUTO): RANK while the sum of n^2 over the queries is at most 2^26, else
+ * SORT.  Both give the same order, so the same results and counts; any
+ * other value is EINVAL. */
+#define NNDTW_ORDER_AUTO 0
+#define NNDTW_ORDER_SORT 1
+#define NNDTW_ORDER_RANK 2
 
 /* Workspace bytes nndtw_search needs for nQ queries against refset. */
 int nndtw_search_workspace_bytes(const nndtw_refset *refset, int64_t nQ,
@@ -414,8 +427,8 @@ int nndtw_dtw_w_backward(const float *A, int64_t nA, const float *B, int64_t nB,
 /* ------------------------------------------------------------------------
  * Batched search over many independent reference sets of different lengths
  * (the search of Sections 1 and 4, per set exactly as nndtw_search with the
- * same options, R and shape): every set's bound pass runs in one kernel, its
- * visiting-order sort in one kernel per sort width, and the (set, query)
+ * same options, R and shape): every set's bound pass runs in one kernel, the
+ * visiting orders in one kernel (ranking) or one per sort width, and the (set, query)
  * items in one persistent search kernel per engine shape that takes items
  * from a device counter, largest expected work first.  After nndtw_batch_prepare, the
  * launch nndtw_search_batch allocates, copies and synchronises nothing, so it
@@ -457,6 +470,8 @@ typedef struct nndtw_batch_plan {
     int32_t helpers;             /* most helper workgroups per query (0: none)       */
     uint32_t share_shapes;       /* engine shapes whose kernel lends idle workgroups */
     int64_t share_off;           /* workspace offset of the items' helper headers    */
+    int32_t order_rank;          /* 1: every visiting order by ranking, one launch   */
+    int32_t order_nmax;          /* ... for sets of at most this many references     */
 } nndtw_batch_plan;
 
 /* Device workspace bytes for a batch (sets as passed to prepare, the same
@@ -470,15 +485,17 @@ int nndtw_batch_workspace_bytes(const nndtw_batch_set *sets, int32_t nsets,
  * `stream` the copy of the set descriptors and item lists into ws.  Returns
  * without waiting for the device (the host copy of that control block is
  * released by the stream once copied); run nndtw_search_batch on the same
- * stream, or ordered after it.  Options (V, cascade, eps, init_ub, waves)
- * are common to all sets; opts->R and opts->cpl are ignored (per set
+ * stream, or ordered after it.  Options (V, cascade, eps, init_ub, waves,
+ * helpers, order) are common to all sets, opts->order deciding for the
+ * batch as a whole (AUTO: RANK while the sum of n^2 over its queries is at
+ * most 2^26); opts->R and opts->cpl are ignored (per set
  * instead); opts->engine must be AUTO or DIAGONAL; opts->events must be
  * NULL. */
 int nndtw_batch_prepare(nndtw_batch_set *sets, int32_t nsets, const nndtw_search_opts *opts,
                         void *ws, size_t ws_bytes, nndtw_batch_plan *plan, void *stream);
 
-/* Run a prepared batch: 1 + (sort widths used) + (engine shapes used)
- * kernels on `stream` (the first, the bound pass, also clears the helper
+/* Run a prepared batch: 1 + (1 if plan->order_rank, else the sort widths
+ * used) + (engine shapes used) kernels on `stream` (the first, the bound pass, also clears the helper
  * headers when plan->helpers > 0).  The
  * sets' reference sets, queries, outputs and ws must be those of prepare. */
 int nndtw_search_batch(const nndtw_batch_plan *plan, void *ws, void *stream);

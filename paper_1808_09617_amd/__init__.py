@@ -25,6 +25,7 @@ CROSS, ZIP = 0, 1
 CASCADES = {"none": 0, "keogh": 1, "keogh_enh": 2, "enh": 3,
             "kim": 4, "improved": 5, "new": 6, "enh_sym": 7}
 ENGINES = {"auto": 0, "diagonal": 1, "strip": 2}
+ORDERS = {"auto": 0, "sort": 1, "rank": 2}
 COUNT_NAMES = ("n", "pruned_keogh", "pruned_enh_bands", "pruned_enh", "dtw_started",
                "dtw_abandoned", "cells", "fp64_rechecks")
 MAX_L = 2048
@@ -54,7 +55,7 @@ class _SearchOpts(ctypes.Structure):
     _fields_ = [("V", ctypes.c_int32), ("cascade", ctypes.c_int32), ("R", ctypes.c_int64),
                 ("eps", ctypes.c_double), ("init_ub", ctypes.c_int32), ("cpl", ctypes.c_int32),
                 ("events", ctypes.c_void_p), ("waves", ctypes.c_int32), ("engine", ctypes.c_int32),
-                ("nq_hint", ctypes.c_int64), ("helpers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("nq_hint", ctypes.c_int64), ("helpers", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 class _BatchSet(ctypes.Structure):
@@ -69,7 +70,8 @@ class _BatchPlan(ctypes.Structure):
                 ("lds", ctypes.c_int64), ("ws_bytes", ctypes.c_int64), ("order_off", ctypes.c_int64 * 6),
                 ("order_cnt", ctypes.c_int64 * 6), ("search_off", ctypes.c_int64 * 8),
                 ("search_cnt", ctypes.c_int64 * 8), ("reserved", ctypes.c_int64 * 4),
-                ("helpers", ctypes.c_int32), ("share_shapes", ctypes.c_uint32), ("share_off", ctypes.c_int64)]
+                ("helpers", ctypes.c_int32), ("share_shapes", ctypes.c_uint32), ("share_off", ctypes.c_int64),
+                ("order_rank", ctypes.c_int32), ("order_nmax", ctypes.c_int32)]
 
 
 _P, _I32, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -347,11 +349,12 @@ class RefSet:
         return self._view(which, (self.L, self.desc.pitch))[:, : self.n]
 
 
-def _opts(V, cascade, R, eps, init_ub, cpl, waves=0, engine="auto", helpers=0):
+def _opts(V, cascade, R, eps, init_ub, cpl, waves=0, engine="auto", helpers=0, order="auto"):
     o = _SearchOpts()
     o.V, o.cascade, o.R, o.eps = int(V), CASCADES[cascade], int(R), float(eps)
     o.init_ub, o.cpl, o.waves, o.engine = int(bool(init_ub)), int(cpl), int(waves), ENGINES[engine]
     o.helpers = int(helpers)
+    o.order = ORDERS[order] if isinstance(order, str) else int(order)
     return o
 
 
@@ -360,10 +363,10 @@ class Searcher:
 
     def __init__(self, refset: RefSet, nQ: int, V: int = 5, cascade: str = "keogh_enh", R: int = 0,
                  eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0, engine: str = "auto",
-                 helpers: int = 0):
+                 helpers: int = 0, order: str = "auto"):
         self.refset = refset
         self.nQ = int(nQ)
-        self.opts = _opts(V, cascade, R, eps, init_ub, cpl, waves, engine, helpers)
+        self.opts = _opts(V, cascade, R, eps, init_ub, cpl, waves, engine, helpers, order)
         nbytes = ctypes.c_size_t(0)
         _check(lib().nndtw_search_workspace_bytes(ctypes.byref(refset.desc), self.nQ, ctypes.byref(self.opts),
                                                   ctypes.byref(nbytes)))
@@ -420,10 +423,11 @@ class BatchSearcher:
     Each set's result equals ``search`` on that set with the R and cpl
     reported in ``self.R`` / ``self.cpl``.  ``helpers``: the most idle
     workgroups that may join one query at a search kernel's end (0 = the
-    library default, -1 = none); the result does not depend on it."""
+    library default, -1 = none); ``order``: "auto", "sort" or "rank", how the
+    visiting orders are found.  The result depends on neither."""
 
     def __init__(self, sets, V: int = 5, cascade: str = "keogh_enh", R=None, cpl=None, eps: float = 0.0,
-                 init_ub: bool = True, waves: int = 0, helpers: int = 0):
+                 init_ub: bool = True, waves: int = 0, helpers: int = 0, order: str = "auto"):
         n = len(sets)
         if n == 0:
             raise ValueError("empty batch")
@@ -446,7 +450,7 @@ class BatchSearcher:
             b.R = 0 if R is None else int(R[d])
             b.cpl = 0 if cpl is None else int(cpl[d])
         self.sets = arr
-        self.opts = _opts(V, cascade, 0, eps, init_ub, 0, waves, helpers=helpers)
+        self.opts = _opts(V, cascade, 0, eps, init_ub, 0, waves, helpers=helpers, order=order)
         nbytes = ctypes.c_size_t(0)
         _check(lib().nndtw_batch_workspace_bytes(arr, n, ctypes.byref(self.opts), ctypes.byref(nbytes)))
         self.ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)
@@ -461,6 +465,11 @@ class BatchSearcher:
         """Most helper workgroups per query the plan allows (0: none)."""
         return int(self.plan.helpers)
 
+    @property
+    def order_rank(self) -> bool:
+        """True when the plan finds the visiting orders by ranking."""
+        return bool(self.plan.order_rank)
+
     def __call__(self):
         _check(lib().nndtw_search_batch(ctypes.byref(self.plan), _ptr(self.ws), _stream()))
         return self.out
@@ -468,10 +477,10 @@ class BatchSearcher:
 
 def search(refset: RefSet, Q: torch.Tensor, V: int = 5, cascade: str = "keogh_enh", R: int = 0,
            eps: float = 0.0, init_ub: bool = True, cpl: int = 0, waves: int = 0, engine: str = "auto",
-           helpers: int = 0):
+           helpers: int = 0, order: str = "auto"):
     """One-shot NN-DTW search: returns (nn_idx int64, nn_dist float64, counts int64[nQ][8], R used)."""
     Q = _series(Q, "Q")
-    s = Searcher(refset, Q.shape[0], V, cascade, R, eps, init_ub, cpl, waves, engine, helpers)
+    s = Searcher(refset, Q.shape[0], V, cascade, R, eps, init_ub, cpl, waves, engine, helpers, order)
     idx, dist, counts = s(Q)
     return idx.clone(), dist.clone(), counts.clone(), s.R
 

@@ -322,6 +322,8 @@ static int check_opts(const nndtw_search_opts *o)
     REQUIRE(o->engine >= NNDTW_ENGINE_AUTO && o->engine <= NNDTW_ENGINE_STRIP, "engine=%d unknown", o->engine);
     REQUIRE(o->helpers >= -1 && o->helpers <= NNDTW_SEARCH_MAX_HELPERS, "helpers=%d must be in -1..%d", o->helpers,
             NNDTW_SEARCH_MAX_HELPERS);
+    REQUIRE(o->order >= NNDTW_ORDER_AUTO && o->order <= NNDTW_ORDER_RANK, "order=%d is not an NNDTW_ORDER_* value",
+            o->order);
     return NNDTW_OK;
 }
 

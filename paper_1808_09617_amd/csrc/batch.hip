@@ -199,7 +199,17 @@ int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, 
             }
         scnt[sh] = (int64_t)items.size() - soff[sh];
     }
-    // ordering items grouped by sort width
+    // ordering: by ranking in one launch, or items grouped by sort width
+    double rank_work = 0.0;
+    int64_t nmax = 0;
+    for (int d = 0; d < nsets; ++d)
+        if (sets[d].nQ > 0) {
+            const double n = (double)sets[d].refset->n;
+            rank_work += (double)sets[d].nQ * n * n;
+            nmax = std::max<int64_t>(nmax, sets[d].refset->n);
+        }
+    bool rank = false;
+    if (int r = order_by_rank(o->order, rank_work, nmax, (int64_t)items.size(), &rank)) return r;
     int64_t ooff[N_WIDTHS] = {0}, ocnt[N_WIDTHS] = {0};
     for (int s = 0; s < N_WIDTHS; ++s) {
         ooff[s] = (int64_t)oitems.size();
@@ -263,6 +273,8 @@ int batch_prepare(nndtw_batch_set *sets, int nsets, const nndtw_search_opts *o, 
         for (int sh = 0; sh < BATCH_SHAPES; ++sh)
             if (scnt[sh] > 0) plan->share_shapes |= 1u << sh;
     plan->share_off = H > 0 ? (int64_t)y.share : 0;
+    plan->order_rank = rank ? 1 : 0;
+    plan->order_nmax = (int32_t)nmax;
     return NNDTW_OK;
 }
 
@@ -279,9 +291,15 @@ int batch_launch(const nndtw_batch_plan *plan, void *ws, hipStream_t st)
     QueryShare *share = plan->share_shapes != 0u ? (QueryShare *)(base + plan->share_off) : nullptr;
     if (int r = launch_batch_bounds(sets, plan->nsets, tstart, plan->tiles, hdr, share, share ? plan->items : 0, st))
         return r;
-    for (int s = 0; s < N_WIDTHS; ++s)
-        if (plan->order_cnt[s] > 0)
-            if (int r = launch_batch_order(1 << s, sets, oitems + plan->order_off[s], plan->order_cnt[s], st)) return r;
+    if (plan->order_rank) {
+        // oitems holds every item (the width groups are consecutive from 0)
+        if (int r = launch_batch_rank(sets, oitems, plan->items, plan->order_nmax, st)) return r;
+    } else {
+        for (int s = 0; s < N_WIDTHS; ++s)
+            if (plan->order_cnt[s] > 0)
+                if (int r = launch_batch_order(1 << s, sets, oitems + plan->order_off[s], plan->order_cnt[s], st))
+                    return r;
+    }
     for (int sh = 0; sh < BATCH_SHAPES; ++sh) {
         const int64_t cnt = plan->search_cnt[sh];
         if (cnt == 0) continue;

@@ -123,6 +123,8 @@ WsLayout ws_layout(int64_t nQ, int64_t n, int L, bool share = true);
 int launch_cells_prefix(int L, int Wp, uint32_t *prefix, hipStream_t s);
 int order_width(int64_t n);     // visiting-order sort size class: npow = 256 * width
 int launch_batch_order(int E, const BatchSet *sets, const int64_t *items, int64_t nitems, hipStream_t s);
+int launch_batch_rank(const BatchSet *sets, const int64_t *items, int64_t nitems, int64_t nmax, hipStream_t s);
+int order_by_rank(int order, double work, int64_t nmax, int64_t nitems, bool *rank);
 // helpers > 0: the kernel lends idle workgroups to running queries, at most
 // `helpers` per query (their QueryShare headers cleared by the bound pass)
 int launch_batch_search(int C, bool exact, const BatchSet *sets, const int64_t *items, int64_t nitems,

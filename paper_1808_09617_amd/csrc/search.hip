@@ -230,6 +230,83 @@ __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *
     }
 }
 
+// ----------------------------------------------------- order by ranking
+// With few queries the sort above leaves most of the chip idle: one
+// workgroup per query, whose time is the latency of its dependent
+// compare-exchange steps (78 of them at 4096 positions).  Ranking finds the
+// same order with no dependent steps, spread over many workgroups: the place
+// of reference i in the visiting order is the number of references whose
+// (ED^2, index) pair precedes its own,
+//     rank(i) = #{j : d_j < d_i} + #{j < i : d_j = d_i},
+// at the price of n^2 comparisons per query.  The pairs are distinct, so the
+// ranks are a permutation of 0 .. n-1 and the order is the sort's.  The
+// distances are compared as FP64 bit patterns, which order non-negative
+// values as the values do (-0 maps to +0, a NaN above +inf).
+constexpr int RANK_BLOCK = 64;                // references per workgroup, one per lane
+constexpr int RANK_WAVES = 16;                // waves per workgroup: wave w counts over the w-th slice of the keys
+constexpr int64_t RANK_MAX_WORK = 1ll << 26;  // library choice: rank while the sum of n^2 stays below this
+constexpr int64_t RANK_MAX_BLOCKS = 1ll << 20;
+constexpr int RANK_MAX_N = 8192;              // references per query (all keys staged in LDS)
+
+__device__ __forceinline__ uint64_t rank_key(double v)
+{
+    return v > 0.0 ? (uint64_t)__double_as_longlong(v) : (v == 0.0 ? 0ull : 0x7FF8000000000000ull);
+}
+
+// Places of references blk*RANK_BLOCK .. +RANK_BLOCK-1 of query q (n <=
+// RANK_MAX_N references): every key of the query is staged in LDS, each wave counts the
+// keys of its slice that precede each lane's reference, and the first wave
+// adds the counts and writes the reference's index and bounds at its place.
+// Whole-workgroup call.
+__device__ __forceinline__ void rank_block(int n, int64_t q, int blk, const double *__restrict__ ed2,
+                                           const double *__restrict__ lbk, const double *__restrict__ lbeb,
+                                           const double *__restrict__ lbe, uint32_t *__restrict__ sk,
+                                           double *__restrict__ slbk, double *__restrict__ slbeb,
+                                           double *__restrict__ slbe, unsigned char *smem)
+{
+    uint64_t *key = reinterpret_cast<uint64_t *>(smem);
+    uint32_t *part = reinterpret_cast<uint32_t *>(key + n);   // [RANK_WAVES][RANK_BLOCK]
+    const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+    const double *e2 = ed2 + q * n;
+    // every load in flight at once (n <= RANK_MAX_N): RANK_LOADS per thread
+    constexpr int NT = RANK_WAVES * WAVE, RANK_LOADS = RANK_MAX_N / NT;
+    double v[RANK_LOADS];
+#pragma unroll
+    for (int r = 0; r < RANK_LOADS; ++r) v[r] = t + r * NT < n ? e2[t + r * NT] : 0.0;
+#pragma unroll
+    for (int r = 0; r < RANK_LOADS; ++r)
+        if (t + r * NT < n) key[t + r * NT] = rank_key(v[r]);
+    __syncthreads();
+    const int b0 = blk * RANK_BLOCK, i = b0 + lane;
+    const uint64_t ki = i < n ? key[i] : 0ull;
+    const uint64_t upto = ki + 1u;             // for j < i: d_j <= d_i precedes (no overflow: ki <= a NaN's)
+    const int S = (n + RANK_WAVES - 1) / RANK_WAVES;
+    const int lo = min(n, w * S), hi = min(n, lo + S);
+    uint32_t c = 0;
+    int j = lo;
+    const int e1 = min(hi, max(lo, b0));       // keys before the block: j < i on every lane
+#pragma unroll 8
+    for (; j < e1; ++j) c += key[j] < upto ? 1u : 0u;
+    const int e2x = min(hi, max(lo, b0 + RANK_BLOCK));
+    for (; j < e2x; ++j) c += key[j] < (j < i ? upto : ki) ? 1u : 0u;
+#pragma unroll 8
+    for (; j < hi; ++j) c += key[j] < ki ? 1u : 0u;   // keys after the block: j > i on every lane
+    part[w * RANK_BLOCK + lane] = c;
+    __syncthreads();
+    if (w == 0 && i < n) {
+        uint32_t r = 0;
+#pragma unroll
+        for (int v = 0; v < RANK_WAVES; ++v) r += part[v * RANK_BLOCK + lane];
+        const int64_t o = q * n + r, src = q * n + i;
+        sk[o] = (uint32_t)i;
+        slbk[o] = lbk[src];
+        slbeb[o] = lbeb[src];
+        slbe[o] = lbe[src];
+    }
+}
+
+static size_t rank_lds(int64_t n) { return (size_t)n * 8 + (size_t)RANK_WAVES * RANK_BLOCK * 4; }
+
 // ------------------------------------------------------- large reference sets
 // Above the on-chip size (8192 references) the visiting order is sorted in
 // chunks of 8192 on chip, then the sorted runs are merged pairwise in global
@@ -375,6 +452,39 @@ batch_order_kernel(const BatchSet *__restrict__ sets, const int64_t *__restrict_
         cells_prefix_wave(b.a.geo.L, b.a.geo.Wp, const_cast<uint32_t *>(b.a.prefix), threadIdx.x);
 }
 
+// Ordering by ranking, one workgroup per RANK_BLOCK references of a query
+// (workgroup x: query x / nblk, block x % nblk).
+__global__ void __launch_bounds__(RANK_WAVES * WAVE)
+rank_order_kernel(int n, int nblk, const double *__restrict__ ed2, const double *__restrict__ lbk,
+                  const double *__restrict__ lbeb, const double *__restrict__ lbe, uint32_t *__restrict__ sk,
+                  double *__restrict__ slbk, double *__restrict__ slbeb, double *__restrict__ slbe, int L, int Wp,
+                  uint32_t *__restrict__ prefix)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t q = blockIdx.x / (unsigned)nblk;
+    const int blk = (int)(blockIdx.x % (unsigned)nblk);
+    rank_block(n, q, blk, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, smem);
+    if (blockIdx.x == 0 && threadIdx.x < WAVE) cells_prefix_wave(L, Wp, prefix, threadIdx.x);
+}
+
+// ... of a batch: nblk workgroups per item, the first ceil(n / RANK_BLOCK)
+// of them work (the item's set decides n).
+__global__ void __launch_bounds__(RANK_WAVES * WAVE)
+batch_rank_kernel(const BatchSet *__restrict__ sets, const int64_t *__restrict__ items, int nblk)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t it = items[blockIdx.x / (unsigned)nblk];
+    const int blk = (int)(blockIdx.x % (unsigned)nblk);
+    const int d = __builtin_amdgcn_readfirstlane((int)(it >> 32));
+    const int64_t q = it & 0xFFFFFFFF;
+    const BatchSet &b = sets[d];
+    const int n = (int)b.a.n;
+    if (blk * RANK_BLOCK >= n) return;        // the whole workgroup, before any barrier
+    rank_block(n, q, blk, b.ed2w, b.lbk, b.lbeb, b.lbe, b.skw, b.slbkw, b.slbebw, b.slbew, smem);
+    if (q == 0 && blk == 0 && threadIdx.x < WAVE)
+        cells_prefix_wave(b.a.geo.L, b.a.geo.Wp, const_cast<uint32_t *>(b.a.prefix), threadIdx.x);
+}
+
 int order_width(int64_t n)
 {
     int E = 1;
@@ -403,6 +513,37 @@ int launch_batch_order(int Wd, const BatchSet *sets, const int64_t *items, int64
         return fail(NNDTW_EUNSUP, "order: sort width %d not supported", Wd);
     }
     NNDTW_LAUNCH_CHECK("batch order kernel launch");
+    return NNDTW_OK;
+}
+
+// The ordering of a batch by ranking (one launch for every item; oitems as
+// for launch_batch_order, nmax the largest n of their sets).
+int launch_batch_rank(const BatchSet *sets, const int64_t *items, int64_t nitems, int64_t nmax, hipStream_t st)
+{
+    if (nitems == 0) return NNDTW_OK;
+    const int64_t nblk = ceil_div(nmax, RANK_BLOCK);
+    if (nmax > RANK_MAX_N || nitems * nblk > RANK_MAX_BLOCKS)
+        return fail(NNDTW_EUNSUP, "ordering by ranking: %lld items of up to %lld references", (long long)nitems,
+                    (long long)nmax);
+    hipLaunchKernelGGL(batch_rank_kernel, dim3((unsigned)(nitems * nblk)), dim3(RANK_WAVES * WAVE), rank_lds(nmax),
+                       st, sets, items, (int)nblk);
+    NNDTW_LAUNCH_CHECK("batch rank kernel launch");
+    return NNDTW_OK;
+}
+
+// Ranking (rather than the per-query sort) for nitems queries of at most
+// nmax references, sum of n^2 over the queries `work`: the option's choice,
+// else while work <= RANK_MAX_WORK.  EUNSUP when ranking is asked for beyond
+// RANK_MAX_N references or RANK_MAX_BLOCKS workgroups.
+int order_by_rank(int order, double work, int64_t nmax, int64_t nitems, bool *rank)
+{
+    if (order < NNDTW_ORDER_AUTO || order > NNDTW_ORDER_RANK)
+        return fail(NNDTW_EINVAL, "order=%d is not an NNDTW_ORDER_* value", order);
+    const bool fits = nmax <= RANK_MAX_N && nitems * ceil_div(nmax, RANK_BLOCK) <= RANK_MAX_BLOCKS;
+    if (order == NNDTW_ORDER_RANK && !fits)
+        return fail(NNDTW_EUNSUP, "ordering by ranking: %lld queries of up to %lld references",
+                    (long long)nitems, (long long)nmax);
+    *rank = order == NNDTW_ORDER_RANK || (order == NNDTW_ORDER_AUTO && fits && work <= (double)RANK_MAX_WORK);
     return NNDTW_OK;
 }
 
@@ -446,10 +587,17 @@ static int launch_order_large(int64_t n, int64_t nQ, const double *ed2, const do
     return launch_cells_prefix(L, Wp, prefix, st);
 }
 
-static int launch_order(int64_t n, int64_t nQ, const double *ed2, const double *lbk, const double *lbeb,
-                        const double *lbe, uint32_t *sk, double *slbk, double *slbeb, double *slbe, int L, int Wp,
-                        uint32_t *prefix, hipStream_t st)
+static int launch_order(bool rank, int64_t n, int64_t nQ, const double *ed2, const double *lbk,
+                        const double *lbeb, const double *lbe, uint32_t *sk, double *slbk, double *slbeb,
+                        double *slbe, int L, int Wp, uint32_t *prefix, hipStream_t st)
 {
+    if (rank) {
+        const int64_t nblk = ceil_div(n, RANK_BLOCK);
+        hipLaunchKernelGGL(rank_order_kernel, dim3((unsigned)(nQ * nblk)), dim3(RANK_WAVES * WAVE), rank_lds(n), st,
+                           (int)n, (int)nblk, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, L, Wp, prefix);
+        NNDTW_LAUNCH_CHECK("rank order kernel launch");
+        return NNDTW_OK;
+    }
     if (n > CHUNK) return launch_order_large(n, nQ, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, L, Wp, prefix, st);
     const int Wd = order_width(n);
     const size_t lds = (size_t)ORDER_THREADS * Wd * ORDER_LDS_PER_POSITION;
@@ -1202,6 +1350,8 @@ static int plan_eps(int L, const nndtw_search_opts *o, SearchPlan *plan)
 
 int plan_search(const nndtw_refset *rs, const nndtw_search_opts *o, SearchPlan *plan, bool batched)
 {
+    if (o->order < NNDTW_ORDER_AUTO || o->order > NNDTW_ORDER_RANK)
+        return fail(NNDTW_EINVAL, "order=%d is not an NNDTW_ORDER_* value", o->order);
     const int L = rs->L;
     const int Wp = rs->W < L - 1 ? rs->W : L - 1;
     int engine = o->engine;
@@ -1317,6 +1467,8 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     double *slbe = (double *)(base + w.slbe);
     uint32_t *prefix = (uint32_t *)(base + w.prefix);
 
+    bool rank = false;                        // decided before anything is enqueued
+    if (int r = order_by_rank(o->order, (double)nQ * (double)n * (double)n, n, nQ, &rank)) return r;
     hipEvent_t *ev = o->events ? (hipEvent_t *)o->events : nullptr;
     auto mark = [&](int i) -> int {
         if (!ev) return NNDTW_OK;
@@ -1343,7 +1495,7 @@ int launch_search(const nndtw_refset *rs, const float *Qy, int64_t nQ, const nnd
     if ((r = mark(1))) return r;
     // (the cells table is filled by the ordering kernel: events 1 and 2 mark the same point)
     if ((r = mark(2))) return r;
-    if ((r = launch_order(n, nQ, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, L, plan.Wp, prefix, st))) return r;
+    if ((r = launch_order(rank, n, nQ, ed2, lbk, lbeb, lbe, sk, slbk, slbeb, slbe, L, plan.Wp, prefix, st))) return r;
     if ((r = mark(3))) return r;
 
     SearchArgs a;

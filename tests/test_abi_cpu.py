@@ -58,7 +58,7 @@ def test_struct_layouts():
     assert nd._SearchOpts.eps.offset == 16 and nd._SearchOpts.events.offset == 32
     assert nd._SearchOpts.waves.offset == 40 and nd._SearchOpts.engine.offset == 44
     assert nd._SearchOpts.nq_hint.offset == 48
-    assert nd._SearchOpts.helpers.offset == 56 and nd._SearchOpts.reserved.offset == 60
+    assert nd._SearchOpts.helpers.offset == 56 and nd._SearchOpts.order.offset == 60
 
 
 def _err(status, fragment):
@@ -137,6 +137,18 @@ def test_refset_and_search_validation():
     bad = nd._opts(0, "keogh_enh", 0, 0.0, True, 0)
     assert _err(lib.nndtw_search_workspace_bytes(ctypes.byref(desc), 10, ctypes.byref(bad),
                                                  ctypes.byref(nbytes)), "V=0") == nd.EINVAL
+    bad = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, order=-1)
+    assert _err(lib.nndtw_search_workspace_bytes(ctypes.byref(desc), 10, ctypes.byref(bad),
+                                                 ctypes.byref(nbytes)), "order=-1") == nd.EINVAL
+    # ranking asked for beyond its 8192 references: refused before anything is enqueued
+    big = nd._Refset()
+    big.magic, big.L, big.n, big.W = nd.REFSET_MAGIC, 64, 9000, 6
+    big.pitch, big.padl, big.ppitch = 9024, 1024, 2112
+    rank = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, order="rank")
+    nb_big = ctypes.c_size_t(0)
+    assert lib.nndtw_search_workspace_bytes(ctypes.byref(big), 2, ctypes.byref(rank), ctypes.byref(nb_big)) == 0
+    assert _err(lib.nndtw_search(ctypes.byref(big), FAKE, 2, ctypes.byref(rank), FAKE, FAKE, NULL, FAKE,
+                                 nb_big.value, NULL), "ordering by ranking") == nd.EUNSUP
     bad = nd._opts(2, "keogh_enh", -1, 0.0, True, 0)
     assert _err(lib.nndtw_search(ctypes.byref(desc), FAKE, 10, ctypes.byref(bad), FAKE, FAKE, NULL, FAKE,
                                  nbytes.value, NULL), "R=-1") == nd.EINVAL
@@ -149,11 +161,12 @@ def test_refset_and_search_validation():
 def test_batch_struct_layouts():
     assert ctypes.sizeof(nd._BatchSet) == 64
     assert nd._BatchSet.R.offset == 48 and nd._BatchSet.cpl.offset == 56
-    assert ctypes.sizeof(nd._BatchPlan) == 320
+    assert ctypes.sizeof(nd._BatchPlan) == 328
     assert nd._BatchPlan.order_off.offset == 48 and nd._BatchPlan.search_off.offset == 144
     assert nd._BatchPlan.reserved.offset == 272
     assert nd._BatchPlan.helpers.offset == 304 and nd._BatchPlan.share_shapes.offset == 308
     assert nd._BatchPlan.share_off.offset == 312
+    assert nd._BatchPlan.order_rank.offset == 320 and nd._BatchPlan.order_nmax.offset == 324
 
 
 def test_batch_validation_and_workspace_size():
@@ -180,6 +193,9 @@ def test_batch_validation_and_workspace_size():
     bad = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, helpers=8)
     assert _err(lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(bad), ctypes.byref(nb2)),
                 "helpers=8") == nd.EINVAL
+    bad = nd._opts(5, "keogh_enh", 0, 0.0, True, 0, order=3)
+    assert _err(lib.nndtw_batch_workspace_bytes(sets, 3, ctypes.byref(bad), ctypes.byref(nb2)),
+                "order=3") == nd.EINVAL
     assert _err(lib.nndtw_batch_workspace_bytes(sets, 0, ctypes.byref(opts), ctypes.byref(nbytes)),
                 "nsets=0") == nd.EINVAL
     assert _err(lib.nndtw_batch_workspace_bytes(None, 3, ctypes.byref(opts), ctypes.byref(nbytes)),

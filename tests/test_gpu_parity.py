@@ -109,6 +109,25 @@ def test_cascade_bounds_bit_exact(name, W, V):
     assert np.array_equal(f, oracle.lb_enhanced(wl.queries, wl.refs, U, Lo, W, V))
 
 
+@pytest.mark.parametrize("L,W,V", [(2, 1, 1), (5, 2, 2), (17, 3, 5), (128, 13, 5), (129, 13, 5), (300, 30, 5),
+                                   (1024, 102, 5)])
+def test_cascade_bounds_one_query_bit_exact(L, W, V):
+    """One query across lengths around the 8-point prefetch ring and the
+    128-point staging chunk, and reference counts around the 256-reference
+    tile."""
+    for n in (1, 255, 257):
+        refs = series(n, L, seed=1500 + L + n)
+        q = series(1, L, seed=1600 + L)
+        say("cascade_bounds one query", L, W, V, n)
+        rs = nd.RefSet(dev(refs), W)
+        e, k, b, f = (host(x) for x in nd.cascade_bounds(rs, dev(q), V))
+        U, Lo = oracle.envelopes(refs, W)
+        assert np.array_equal(e, oracle.ed2(q, refs))
+        assert np.array_equal(k, oracle.lb_keogh(q, U, Lo))
+        assert np.array_equal(b, oracle.lb_enhanced(q, refs, U, Lo, W, V, variant="bands"))
+        assert np.array_equal(f, oracle.lb_enhanced(q, refs, U, Lo, W, V))
+
+
 # ------------------------------------------------------------------ a5
 DTW_CASES = [(2, 0), (2, 1), (3, 1), (3, 5), (8, 0), (8, 3), (8, 7), (24, 2), (64, 6), (64, 63), (97, 13),
              (256, 26), (256, 255), (512, 5), (512, 51), (512, 128), (512, 256), (512, 511), (1000, 100),
@@ -195,17 +214,17 @@ def test_dtw_tightness_pairs_zip():
 
 # ------------------------------------------------------------------ search
 def run_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, waves=0, engine="auto",
-               helpers=0):
+               helpers=0, order="auto"):
     rs = nd.RefSet(dev(refs), W)
     idx, dist, counts, R_used = nd.search(rs, dev(queries), V=V, cascade=cascade, R=R, init_ub=init_ub, cpl=cpl,
-                                          waves=waves, engine=engine, helpers=helpers)
+                                          waves=waves, engine=engine, helpers=helpers, order=order)
     return host(idx), host(dist), host(counts), R_used
 
 
 def check_search(refs, queries, W, V, cascade="keogh_enh", R=0, init_ub=True, cpl=0, brute=True, waves=0,
-                 engine="auto", helpers=0):
-    say("search", refs.shape, queries.shape, W, V, cascade, R, init_ub, cpl, waves, engine, helpers)
-    gi, gd, gc, R_used = run_search(refs, queries, W, V, cascade, R, init_ub, cpl, waves, engine, helpers)
+                 engine="auto", helpers=0, order="auto"):
+    say("search", refs.shape, queries.shape, W, V, cascade, R, init_ub, cpl, waves, engine, helpers, order)
+    gi, gd, gc, R_used = run_search(refs, queries, W, V, cascade, R, init_ub, cpl, waves, engine, helpers, order)
     oi, od, oc = oracle.search(refs, queries, W, V, cascade, R_used, init_ub)
     assert np.array_equal(gi, oi), ("nn_idx", np.nonzero(gi != oi))
     assert np.array_equal(gd, od), ("nn_dist", np.max(np.abs(gd - od)))
@@ -280,6 +299,60 @@ def test_search_reference_counts(n):
     refs = series(n, 24, seed=900 + n % 97, kind="sin5")
     queries = series(5, 24, seed=901, kind="sin5")
     check_search(refs, queries, 3, 2, "keogh_enh", 0, True, 0, brute=n <= 2049)
+
+
+def _al256(x):
+    return (x + 255) // 256 * 256
+
+
+def _ordered_region(searcher, n):
+    """The visiting order and the bounds gathered in it, as the search's
+    workspace holds them after a call (squared ED, LB_Keogh, both LB_Enhanced
+    parts, then the sorted indices and the three gathered bounds)."""
+    m = searcher.nQ * n
+    sk = 4 * _al256(m * 8)
+    slbk = sk + _al256(m * 4)
+    parts = [searcher.ws[sk:sk + m * 4]] + [searcher.ws[o:o + m * 8] for o in
+                                            (slbk, slbk + _al256(m * 8), slbk + 2 * _al256(m * 8))]
+    return host(torch.cat(parts))           # (the 256-byte alignment gaps between them hold nothing)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 1000, 4100, 8192])
+def test_search_order_by_rank_equals_sort(n):
+    """The two ways of finding the visiting order give the same order and the
+    same gathered bounds, byte for byte, and the same search result, which is
+    the oracle's.  Duplicated references give equal squared distances (ties
+    broken by index), and a query equal to a reference a distance of 0."""
+    base = series(max(1, n // 3), 40, seed=1300 + n, kind="sin5")
+    refs = np.ascontiguousarray(np.resize(base, (n, 40)))        # every row repeated about three times
+    queries = np.ascontiguousarray(np.concatenate([refs[n // 2:n // 2 + 1], series(3, 40, seed=1301)], 0))
+    rs = nd.RefSet(dev(refs), 4)
+    region, results = [], []
+    for order in ("sort", "rank"):
+        say("order", order, "n", n)
+        s = nd.Searcher(rs, queries.shape[0], V=2, order=order)
+        idx, dist, counts = s(dev(queries))
+        torch.cuda.synchronize()
+        region.append(_ordered_region(s, n))
+        results.append((host(idx), host(dist), host(counts)))
+    assert np.array_equal(region[0], region[1])
+    (i0, d0, c0), (i1, d1, c1) = results
+    assert np.array_equal(i0, i1) and np.array_equal(d0, d1) and np.array_equal(c0[:, :5], c1[:, :5])
+    sk = region[1][: queries.shape[0] * n * 4].view(np.uint32).reshape(queries.shape[0], n)
+    assert np.array_equal(np.sort(sk, 1), np.tile(np.arange(n, dtype=np.uint32), (queries.shape[0], 1)))
+    check_search(refs, queries, 4, 2, "keogh_enh", 0, True, 0, brute=n <= 1000, order="rank")
+
+
+def test_search_order_choice_and_limits():
+    """The library ranks while nQ n^2 <= 2^26 (the result is the same either
+    way); ranking is refused above 8192 references."""
+    refs = series(300, 24, seed=1400, kind="sin5")
+    queries = series(4, 24, seed=1401, kind="sin5")
+    for order in ("auto", "sort", "rank"):
+        check_search(refs, queries, 3, 2, "keogh_enh", 0, True, 0, brute=True, order=order)
+    big = nd.RefSet(dev(series(8193, 24, seed=1402, kind="sin5")), 3)
+    with pytest.raises(RuntimeError, match="ordering by ranking"):
+        nd.search(big, dev(queries[:1]), V=2, order="rank")
 
 
 @pytest.mark.parametrize("n", [8193, 16384, 16385, 40000])
@@ -478,9 +551,9 @@ def test_search_eps_floor_with_duplicates():
 
 
 # ------------------------------------------------------------------ batching
-def run_batch(datasets, V=5, R=None, cpl=None, waves=0, helpers=0):
+def run_batch(datasets, V=5, R=None, cpl=None, waves=0, helpers=0, order="auto"):
     pairs = [(nd.RefSet(dev(ds.refs), ds.W), dev(ds.queries)) for ds in datasets]
-    bsr = nd.BatchSearcher(pairs, V=V, R=R, cpl=cpl, waves=waves, helpers=helpers)
+    bsr = nd.BatchSearcher(pairs, V=V, R=R, cpl=cpl, waves=waves, helpers=helpers, order=order)
     out = bsr()
     return bsr, pairs, [(host(i), host(d), host(c)) for i, d, c in out]
 
@@ -505,6 +578,52 @@ def test_batch_matches_single_search_and_oracle(waves):
         oi, od, oc = oracle.search(ds.refs, ds.queries[:3], ds.W, 5, "keogh_enh", bsr.R[d], True)
         assert np.array_equal(gi[:3], oi) and np.array_equal(gd[:3], od)
         assert np.array_equal(gc[:3, :5], oc[:, :5])
+
+
+@pytest.mark.parametrize("n_sets,q_frac,helpers", [(4, 0.002, 0), (8, 0.05, -1)])
+def test_batch_order_by_rank_equals_sort(n_sets, q_frac, helpers):
+    """A batch ordered by ranking (one launch for all its sets) and by the
+    per-width sorts gives every set the same result; the library's choice
+    ranks a batch of a few queries and sorts a large one."""
+    sets = synth.batch_workload(n_sets=n_sets, L_range=(24, 700), N_range=(50, 3000), q_frac=q_frac)
+    res, Rs = {}, {}
+    for order in ("sort", "rank", "auto"):
+        say("batch order", order, "queries", sum(ds.queries.shape[0] for ds in sets))
+        bsr, _, res[order] = run_batch(sets, helpers=helpers, order=order)
+        Rs[order] = bsr.R
+        assert bsr.order_rank == (order == "rank" or (order == "auto" and sum(
+            ds.queries.shape[0] * ds.refs.shape[0] ** 2 for ds in sets) <= 1 << 26))
+    for d, ds in enumerate(sets):
+        for order in ("rank", "auto"):
+            (gi, gd, gc), (si, sd, sc) = res[order][d], res["sort"][d]
+            assert np.array_equal(gi, si) and np.array_equal(gd, sd) and np.array_equal(gc[:, :5], sc[:, :5])
+    ds = sets[-1]
+    nq = min(3, ds.queries.shape[0])
+    if nq:
+        assert Rs["rank"] == Rs["sort"]
+        oi, od, oc = oracle.search(ds.refs, ds.queries[:nq], ds.W, 5, "keogh_enh", Rs["rank"][-1], True)
+        gi, gd, gc = res["rank"][-1]
+        assert np.array_equal(gi[:nq], oi) and np.array_equal(gd[:nq], od) and np.array_equal(gc[:nq, :5], oc[:, :5])
+
+
+def test_batch_one_query_per_set():
+    """A batch in which no set has more than one query (a serving batch: the
+    bound pass runs its one-query body on every tile, the order is ranked);
+    every set's result is the single search's and the oracle's."""
+    sets = synth.batch_workload(n_sets=6, L_range=(24, 1100), N_range=(50, 2500), q_frac=0.1)
+    sets = [synth.BatchDataset(ds.refs, ds.queries[:1], ds.W, ds.V) for ds in sets]
+    sets[2] = synth.BatchDataset(sets[2].refs, sets[2].queries[:0], sets[2].W, sets[2].V)   # and one with none
+    bsr, pairs, res = run_batch(sets)
+    for d, ds in enumerate(sets):
+        gi, gd, gc = res[d]
+        if ds.queries.shape[0] == 0:
+            assert gi.shape == (0,)
+            continue
+        si, sd, sc, _ = nd.search(pairs[d][0], pairs[d][1], V=5, R=bsr.R[d], cpl=bsr.cpl[d])
+        assert np.array_equal(gi, host(si)) and np.array_equal(gd, host(sd))
+        assert np.array_equal(gc[:, :5], host(sc)[:, :5])
+        oi, od, oc = oracle.search(ds.refs, ds.queries, ds.W, 5, "keogh_enh", bsr.R[d], True)
+        assert np.array_equal(gi, oi) and np.array_equal(gd, od) and np.array_equal(gc[:, :5], oc[:, :5])
 
 
 def test_batch_rounds_and_shapes_per_set():
