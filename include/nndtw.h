@@ -326,9 +326,10 @@ typedef struct nndtw_search_opts {
  * of pairs that precede it, over many workgroups per query (n^2 comparisons
  * per query, but no step depends on another; at most 8192 references and
  * 2^20 workgroups of 64 references, else EUNSUP).  The library's choice
- * (AUTO): RANK while the sum of n^2 over the queries is at most 2^26, else
- * SORT.  Both give the same order, so the same results and counts; any
- * other value is EINVAL. */
+ * (AUTO): RANK while the sum of n^2 over the queries is at most 2^16 npow,
+ * npow the power of two >= max(n, 256) (2^26 at 1000 references, 2^28 at
+ * 4000), else SORT.  Both give the same order, so the same results and
+ * counts; any other value is EINVAL. */
 #define NNDTW_ORDER_AUTO 0
 #define NNDTW_ORDER_SORT 1
 #define NNDTW_ORDER_RANK 2
@@ -487,8 +488,7 @@ int nndtw_batch_workspace_bytes(const nndtw_batch_set *sets, int32_t nsets,
  * released by the stream once copied); run nndtw_search_batch on the same
  * stream, or ordered after it.  Options (V, cascade, eps, init_ub, waves,
  * helpers, order) are common to all sets, opts->order deciding for the
- * batch as a whole (AUTO: RANK while the sum of n^2 over its queries is at
- * most 2^26); opts->R and opts->cpl are ignored (per set
+ * batch as a whole (AUTO as above, n the largest set's); opts->R and opts->cpl are ignored (per set
  * instead); opts->engine must be AUTO or DIAGONAL; opts->events must be
  * NULL. */
 int nndtw_batch_prepare(nndtw_batch_set *sets, int32_t nsets, const nndtw_search_opts *opts,

@@ -244,7 +244,14 @@ __device__ __forceinline__ void order_query(int64_t n, int64_t q, const double *
 // values as the values do (-0 maps to +0, a NaN above +inf).
 constexpr int RANK_BLOCK = 64;                // references per workgroup, one per lane
 constexpr int RANK_WAVES = 16;                // waves per workgroup: wave w counts over the w-th slice of the keys
-constexpr int64_t RANK_MAX_WORK = 1ll << 26;  // library choice: rank while the sum of n^2 stays below this
+// The library's choice: rank while the sum of n^2 over the queries is at
+// most RANK_WORK_PER_POSITION times the sort's padded size npow (the power of
+// two >= max(n, 256)).  Measured at W = 6, L = 64 (order stage, us, sort /
+// rank): n = 1000, 64 queries 27 / 20; n = 4000, 16 queries 79 / 43 and 32
+// queries 80 / 76; n = 8192, 8 queries 161 / 74 and 16 queries 161 / 135.
+// The sort's time grows with npow and hardly with the query count (its
+// workgroups run side by side); ranking's with the comparisons.
+constexpr int64_t RANK_WORK_PER_POSITION = 1ll << 16;
 constexpr int64_t RANK_MAX_BLOCKS = 1ll << 20;
 constexpr int RANK_MAX_N = 8192;              // references per query (all keys staged in LDS)
 
@@ -533,8 +540,8 @@ int launch_batch_rank(const BatchSet *sets, const int64_t *items, int64_t nitems
 
 // Ranking (rather than the per-query sort) for nitems queries of at most
 // nmax references, sum of n^2 over the queries `work`: the option's choice,
-// else while work <= RANK_MAX_WORK.  EUNSUP when ranking is asked for beyond
-// RANK_MAX_N references or RANK_MAX_BLOCKS workgroups.
+// else while work <= RANK_WORK_PER_POSITION * npow.  EUNSUP when ranking is
+// asked for beyond RANK_MAX_N references or RANK_MAX_BLOCKS workgroups.
 int order_by_rank(int order, double work, int64_t nmax, int64_t nitems, bool *rank)
 {
     if (order < NNDTW_ORDER_AUTO || order > NNDTW_ORDER_RANK)
@@ -543,7 +550,10 @@ int order_by_rank(int order, double work, int64_t nmax, int64_t nitems, bool *ra
     if (order == NNDTW_ORDER_RANK && !fits)
         return fail(NNDTW_EUNSUP, "ordering by ranking: %lld queries of up to %lld references",
                     (long long)nitems, (long long)nmax);
-    *rank = order == NNDTW_ORDER_RANK || (order == NNDTW_ORDER_AUTO && fits && work <= (double)RANK_MAX_WORK);
+    int64_t npow = ORDER_THREADS;
+    while (npow < nmax) npow <<= 1;
+    *rank = order == NNDTW_ORDER_RANK ||
+            (order == NNDTW_ORDER_AUTO && fits && work <= (double)RANK_WORK_PER_POSITION * (double)npow);
     return NNDTW_OK;
 }
 
