@@ -261,10 +261,10 @@ __device__ __forceinline__ uint64_t rank_key(double v)
 }
 
 // Places of references blk*RANK_BLOCK .. +RANK_BLOCK-1 of query q (n <=
-// RANK_MAX_N references): every key of the query is staged in LDS, each wave counts the
-// keys of its slice that precede each lane's reference, and the first wave
-// adds the counts and writes the reference's index and bounds at its place.
-// Whole-workgroup call.
+// RANK_MAX_N references): every key of the query is staged in LDS, each
+// wave counts the keys of its slice that precede each lane's reference, and
+// the first wave adds the counts and writes the reference's index and bounds
+// at its place.  Whole-workgroup call.
 __device__ __forceinline__ void rank_block(int n, int64_t q, int blk, const double *__restrict__ ed2,
                                            const double *__restrict__ lbk, const double *__restrict__ lbeb,
                                            const double *__restrict__ lbe, uint32_t *__restrict__ sk,
@@ -303,7 +303,7 @@ __device__ __forceinline__ void rank_block(int n, int64_t q, int blk, const doub
     if (w == 0 && i < n) {
         uint32_t r = 0;
 #pragma unroll
-        for (int v = 0; v < RANK_WAVES; ++v) r += part[v * RANK_BLOCK + lane];
+        for (int u = 0; u < RANK_WAVES; ++u) r += part[u * RANK_BLOCK + lane];
         const int64_t o = q * n + r, src = q * n + i;
         sk[o] = (uint32_t)i;
         slbk[o] = lbk[src];
