@@ -230,11 +230,11 @@ def backward_bench(nd, synth, torch, dev, reps=5, cpu=True):
     return res
 
 
-def one_request_latency(nd, synth, torch, dev, serve, rss, Ls, R, cpl, reps=30):
+def one_request_latency(nd, synth, torch, dev, serve, rss, Ls, R, cpl, helpers=0, reps=30):
     """GPU time of a batch holding one request, per serving set (HIP events
     around the batch's launch on its stream; median and maximum over `reps`
     requests), with the server's own buffers and plan."""
-    server = serve.Server(rss, n_streams=1, R=R, cpl=cpl)
+    server = serve.Server(rss, n_streams=1, R=R, cpl=cpl, helpers=helpers)
     slot = server.slots[0]
     out = {}
     for s, L in enumerate(Ls):
@@ -277,17 +277,23 @@ def serving_bench(nd, synth, torch, dev, rate=2000.0, duration=3.0):
     sample = [(rs, torch.stack([torch.from_numpy(synth.serving_query(s, Ls[s], 2 * 10 ** 6 + k)).to(dev)
                                 for k in range(16)])) for s, rs in enumerate(rss)]
     R, cpl, _ = tune.autotune(sample, V=5)
+    # at 2000 requests/s a batch holds one request or two: the round size and
+    # the helper workgroups per set tuned for one request on its own
+    R_lat, helpers, _ = tune.tune_latency(sample, cpl, V=5)
     # the same stream without helper workgroups, for comparison
-    server = serve.Server(rss, n_streams=3, R=R, cpl=cpl, helpers=-1)
+    server = serve.Server(rss, n_streams=3, R=R_lat, cpl=cpl, helpers=-1)
     server.run(warm)
     _, nohelp = server.run(reqs)
     del server
-    server = serve.Server(rss, n_streams=3, R=R, cpl=cpl)
+    server = serve.Server(rss, n_streams=3, R=R_lat, cpl=cpl, helpers=helpers)
     server.run(warm)
     _, summary = server.run(reqs)
+    del server
     summary.update({"offered_rps": rate, "sets": len(sets), "refs_per_set": sets[0][0].shape[0],
-                    "lengths": Ls, "R": R, "cpl": cpl,
+                    "lengths": Ls, "R": R_lat, "cpl": cpl, "helpers": helpers, "R_saturation": R,
                     "without_helpers": {"mean_batch": nohelp["mean_batch"], "latency_ms": nohelp["latency_ms"]}})
+    # saturation runs with the round sizes tuned for batches of many queries
+    server = serve.Server(rss, n_streams=3, R=R, cpl=cpl)
     # saturation: 4000 requests present at the start, served as fast as the
     # server admits them (batches of up to 512 within the 1 GiB budget)
     sat = serve.poisson_requests(Ls, rate=float("inf"), duration=4000, seed=3, device=dev,
@@ -297,7 +303,7 @@ def serving_bench(nd, synth, torch, dev, rate=2000.0, duration=3.0):
     summary["saturation"] = {k: ssum[k] for k in ("requests", "batches", "mean_batch", "wall_s", "throughput_rps",
                                                   "max_batches_in_flight", "max_workspace_bytes", "budget_bytes")}
     del server
-    summary["one_request"] = one_request_latency(nd, synth, torch, dev, serve, rss, Ls, R, cpl)
+    summary["one_request"] = one_request_latency(nd, synth, torch, dev, serve, rss, Ls, R_lat, cpl, helpers)
     del rss
     torch.cuda.empty_cache()
     return summary
@@ -736,11 +742,13 @@ def main():
         sets = synth.serving_sets()
         rss = [nd.RefSet(torch.from_numpy(refs).to(dev), W) for refs, W in sets]
         Ls = [refs.shape[1] for refs, _ in sets]
-        # the round size and shape the serving benchmark's tuner picks on this workload
+        # the round size, shape and helper workgroups the serving benchmark's
+        # tuners pick on this workload
         R = [512, 512, 256, 256, 256, 256, 256, 256]
         cpl = [3, 3, 3, 2, 2, 2, 2, 2]
-        print(json.dumps({"one_request": one_request_latency(nd, synth, torch, dev, serve, rss, Ls, R, cpl)}),
-              flush=True)
+        helpers = [-1, -1, -1, 0, 0, 0, 0, 0]
+        print(json.dumps({"one_request": one_request_latency(nd, synth, torch, dev, serve, rss, Ls, R, cpl,
+                                                             helpers)}), flush=True)
         return
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(nd, synth, torch, torch.device("cuda:0"))}), flush=True)

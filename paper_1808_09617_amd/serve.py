@@ -124,8 +124,11 @@ class Server:
     """Continuous batching over ``refsets`` (a list of RefSet) on
     ``n_streams`` streams; each batch holds at most ``max_batch`` requests,
     and the workspaces of all batches in flight fit in ``budget_bytes``.
-    ``R`` and ``cpl`` (per set or None) are passed to every batch;
-    ``helpers`` too (idle workgroups that join a batch's running queries)."""
+    ``R`` and ``cpl`` (per set or None) are passed to every batch.
+    ``helpers`` (idle workgroups that join a batch's running queries: 0 the
+    library default, -1 none, or a count) is one value or one per set; a
+    batch runs without helpers when every set in it asks for none, else with
+    the most any of its sets asks for (0 counting as the default 7)."""
 
     def __init__(self, refsets, n_streams: int = 3, max_batch: int = 512, budget_bytes: int = 1 << 30,
                  V: int = 5, R=None, cpl=None, helpers: int = 0):
@@ -133,10 +136,14 @@ class Server:
         dev = self.refsets[0].device
         self.max_batch = max_batch
         self.V = V
-        self.helpers = helpers
+        hs = list(helpers) if isinstance(helpers, (list, tuple)) else [helpers] * len(self.refsets)
+        if len(hs) != len(self.refsets):
+            raise ValueError(f"{len(hs)} helper counts for {len(self.refsets)} sets")
+        self.set_helpers = [int(h) for h in hs]
         # workspace of one query per set: an upper bound of what each query
-        # adds to a batch (it includes the batch's fixed part once more)
-        self.per_query = [batch_bytes([rs], [1], V, helpers=helpers) for rs in self.refsets]
+        # adds to a batch (it includes the batch's fixed part once more, and
+        # the helper header whether or not its batch uses helpers)
+        self.per_query = [batch_bytes([rs], [1], V, helpers=0) for rs in self.refsets]
         if max(self.per_query) > budget_bytes:
             raise ValueError(f"budget of {budget_bytes} bytes below one query's workspace {max(self.per_query)}")
         self.arena = Arena(budget_bytes, dev)
@@ -150,8 +157,16 @@ class Server:
         self.plan_R, self.plan_cpl = list(probe.R), list(probe.cpl)
         del probe
         torch.cuda.synchronize(dev)
-        self.opts = _opts(V, "keogh_enh", 0, 0.0, True, 0, helpers=helpers)
+        self.opts = {h: _opts(V, "keogh_enh", 0, 0.0, True, 0, helpers=h) for h in set(self.set_helpers) | {0, -1}}
         self.stats = {}
+
+    def _helpers(self, sets):
+        """The helper count of a batch over `sets` (set ids)."""
+        hs = [self.set_helpers[s] for s in sets]
+        if all(h == -1 for h in hs):
+            return -1
+        hmax = max(h if h > 0 else 7 for h in hs if h != -1)
+        return 0 if hmax == 7 else hmax
 
     def _launch(self, reqs, slot: _Slot, block):
         """Enqueue one batched search over `reqs` on the slot's stream, its
@@ -183,7 +198,11 @@ class Server:
                 row += n
             st = ctypes.c_void_p(slot.stream.cuda_stream)
             ws = self.arena.ptr(block[0])
-            _check(lib().nndtw_batch_prepare(arr, len(sets), ctypes.byref(self.opts), ws, block[1],
+            hb = self._helpers(sets)
+            if hb not in self.opts:
+                self.opts[hb] = _opts(self.V, "keogh_enh", 0, 0.0, True, 0, helpers=hb)
+            opts = self.opts[hb]
+            _check(lib().nndtw_batch_prepare(arr, len(sets), ctypes.byref(opts), ws, block[1],
                                              ctypes.byref(slot.plan), st))
             _check(lib().nndtw_search_batch(ctypes.byref(slot.plan), ws, st))
             end = 2 * self.max_batch + 8 * row      # through the batch's last counts row
@@ -196,7 +215,8 @@ class Server:
         for r in reqs:
             counts[r.set_id] = counts.get(r.set_id, 0) + 1
         sets = sorted(counts)
-        return batch_bytes([self.refsets[s] for s in sets], [counts[s] for s in sets], self.V, helpers=self.helpers)
+        return batch_bytes([self.refsets[s] for s in sets], [counts[s] for s in sets], self.V,
+                           helpers=self._helpers(sets))
 
     def run(self, requests, poll_sleep: float = 0.0):
         """Serve `requests` (sorted by arrival time) in real time; returns

@@ -15,6 +15,12 @@ L and of W'+1).  For each bucket the set with the most (query, reference)
 pairs is searched on the GPU with every candidate (cpl, R), each timed with
 events on the current stream (median of a few runs, after one warm-up run),
 and the fastest pair is used for every set of the bucket.
+
+``tune_latency`` tunes for the other regime, a request searched on its own
+(a serving batch at low load): per set, the round size and whether idle
+workgroups help the query, each timed on single-query batches.  Helpers pay
+off where one DTW is long (their joining and the shared rounds cost a few
+microseconds each) and cost time where it is short.
 """
 from __future__ import annotations
 
@@ -22,7 +28,7 @@ import math
 
 import torch
 
-from . import Searcher
+from . import BatchSearcher, Searcher
 
 BATCH_MAX_CPL = 4
 
@@ -77,3 +83,33 @@ def autotune(pairs, V: int = 5, waves: int = 0, R_candidates=(64, 128, 256, 512)
         report[f"L{rs.L}_W{rs.W}"] = {"sets": len(members), "cpl": c_best, "R": r_best, "ms": ms_best,
                                       "trials": {f"C{c}_R{r}": round(t, 3) for (c, r), t in trials.items()}}
     return R, cpl, report
+
+
+def tune_latency(pairs, cpl, V: int = 5, R_candidates=(128, 256, 512), helper_candidates=(-1, 0), reps: int = 5):
+    """pairs: list of (RefSet, sample queries [k][L]); cpl: the engine shape
+    per set.  Each set's (R, helpers) is the pair with the smallest median
+    GPU time of a batch holding one of its sample queries (after one
+    untimed batch per pair).  Returns (R list, helpers list, report)."""
+    R, H, report = [], [], {}
+    for d, (rs, Q) in enumerate(pairs):
+        trials = {}
+        for r in R_candidates:
+            for h in helper_candidates:
+                times = []
+                for k in range(reps + 1):
+                    q = Q[k % Q.shape[0]:k % Q.shape[0] + 1]
+                    b = BatchSearcher([(rs, q)], V=V, R=[r], cpl=[cpl[d]], helpers=h)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    b()
+                    e1.record()
+                    e1.synchronize()
+                    if k > 0:
+                        times.append(e0.elapsed_time(e1))
+                trials[(r, h)] = sorted(times)[len(times) // 2]
+        (r_best, h_best), ms = min(trials.items(), key=lambda kv: kv[1])
+        R.append(r_best)
+        H.append(h_best)
+        report[f"L{rs.L}_W{rs.W}"] = {"R": r_best, "helpers": h_best, "ms": round(ms, 3),
+                                      "trials": {f"R{r}_h{h}": round(t, 3) for (r, h), t in trials.items()}}
+    return R, H, report

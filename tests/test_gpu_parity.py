@@ -975,10 +975,12 @@ def test_dtw_backward_deterministic():
 
 
 # ------------------------------------------------------------------ serving
-def test_serving_results_equal_alone():
+@pytest.mark.parametrize("helpers", [0, [-1, -1, 0, 3, -1, 7]])
+def test_serving_results_equal_alone(helpers):
     """Requests served in the mix (continuous batching on several streams)
     give exactly the result of each query searched alone; a sample is also
-    checked against the oracle."""
+    checked against the oracle.  With helper workgroups per set, batches
+    whose sets all ask for none run without them."""
     from paper_1808_09617_amd import serve
     sets = synth.serving_sets(n_sets=6, n_refs=300, L_range=(48, 256))
     rss = [nd.RefSet(dev(refs), W) for refs, W in sets]
@@ -987,7 +989,7 @@ def test_serving_results_equal_alone():
                                   make_query=lambda s, L, k: synth.serving_query(s, L, k))
     torch.cuda.synchronize()
     say("serving", len(reqs), "requests")
-    server = serve.Server(rss, n_streams=3, max_batch=64)
+    server = serve.Server(rss, n_streams=3, max_batch=64, helpers=helpers)
     done, summary = server.run(reqs)
     assert summary["batches"] > 1
     # every batch runs each set at the server's round size and shape (the

@@ -86,3 +86,14 @@ def test_poisson_requests_saturation_mode():
     reqs = serve.poisson_requests([8, 8], rate=float("inf"), duration=37, seed=1, device="cpu", make_query=mk)
     assert len(reqs) == 37 and all(r.arrival == 0.0 for r in reqs)
     assert [r.rid for r in reqs] == list(range(37))
+
+
+def test_server_helpers_per_batch():
+    """A batch runs without helper workgroups only when every set in it asks
+    for none; otherwise with the most any of its sets asks for (0, the
+    library default, counting as 7)."""
+    srv = serve.Server.__new__(serve.Server)          # the resolution only, no device state
+    srv.set_helpers = [-1, -1, 0, 3, 5, -1]
+    assert srv._helpers([0]) == -1 and srv._helpers([0, 1, 5]) == -1
+    assert srv._helpers([3]) == 3 and srv._helpers([0, 3]) == 3 and srv._helpers([3, 4]) == 5
+    assert srv._helpers([2]) == 0 and srv._helpers([2, 4]) == 0 and srv._helpers([1, 2, 3]) == 0
