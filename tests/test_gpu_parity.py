@@ -629,6 +629,32 @@ def test_batch_one_query_per_set():
         assert np.array_equal(gi, oi) and np.array_equal(gd, od) and np.array_equal(gc[:, :5], oc[:, :5])
 
 
+def test_tuners_pick_valid_schedules():
+    """Both tuners return, per set, a schedule from their candidates (the
+    throughput tuner one per (L, W) bucket); a batch run with the tuned round
+    sizes and shapes gives each set the oracle's result, and a single-query
+    batch with the latency tuner's helper choice the same result."""
+    from paper_1808_09617_amd import tune
+    sets = synth.batch_workload(n_sets=3, L_range=(40, 400), N_range=(200, 600), q_frac=0.02)
+    pairs = [(nd.RefSet(dev(ds.refs), ds.W), dev(ds.queries)) for ds in sets]
+    R, cpl, report = tune.autotune(pairs, V=5, R_candidates=(64, 256), reps=1)
+    assert all(r in (64, 256) for r in R) and all(1 <= c <= 4 for c in cpl)
+    assert sum(v["sets"] for v in report.values()) == len(sets)
+    R_lat, helpers, lat = tune.tune_latency(pairs, cpl, V=5, R_candidates=(128, 256), reps=2)
+    assert all(r in (128, 256) for r in R_lat) and all(h in (-1, 0) for h in helpers) and len(lat) == len(sets)
+    bsr = nd.BatchSearcher(pairs, V=5, R=R, cpl=cpl)
+    out = bsr()
+    for d, ds in enumerate(sets):
+        gi, gd, gc = (host(x) for x in out[d])
+        oi, od, oc = oracle.search(ds.refs, ds.queries, ds.W, 5, "keogh_enh", bsr.R[d], True)
+        assert np.array_equal(gi, oi) and np.array_equal(gd, od) and np.array_equal(gc[:, :5], oc[:, :5])
+        one = nd.BatchSearcher([(pairs[d][0], pairs[d][1][:1])], V=5, R=[R_lat[d]], cpl=[cpl[d]],
+                               helpers=helpers[d])
+        i1, d1, c1 = (host(x) for x in one()[0])
+        oi, od, oc = oracle.search(ds.refs, ds.queries[:1], ds.W, 5, "keogh_enh", one.R[0], True)
+        assert i1[0] == oi[0] and d1[0] == od[0] and np.array_equal(c1[:, :5], oc[:, :5])
+
+
 def test_batch_rounds_and_shapes_per_set():
     """Per-set R and engine shape overrides (as an autotuner sets them)."""
     sets = synth.batch_workload(n_sets=5, L_range=(30, 200), N_range=(60, 300), q_frac=0.05)
