@@ -85,11 +85,14 @@ def autotune(pairs, V: int = 5, waves: int = 0, R_candidates=(64, 128, 256, 512)
     return R, cpl, report
 
 
-def tune_latency(pairs, cpl, V: int = 5, R_candidates=(128, 256, 512), helper_candidates=(-1, 0), reps: int = 5):
+def tune_latency(pairs, cpl, V: int = 5, R_candidates=(128, 256, 512), helper_candidates=(-1, 0), reps: int = 8):
     """pairs: list of (RefSet, sample queries [k][L]); cpl: the engine shape
-    per set.  Each set's (R, helpers) is the pair with the smallest median
-    GPU time of a batch holding one of its sample queries (after one
-    untimed batch per pair).  Returns (R list, helpers list, report)."""
+    per set.  Each set's (R, helpers) is the pair with the smallest mean GPU
+    time over single-query batches of its first `reps` sample queries (the
+    same queries for every pair, after one untimed batch per pair; queries
+    differ in cost far more than the runs of one query do, so the mean over
+    several of them, not one query's median, decides).  Returns (R list,
+    helpers list, report)."""
     R, H, report = [], [], {}
     for d, (rs, Q) in enumerate(pairs):
         trials = {}
@@ -106,7 +109,7 @@ def tune_latency(pairs, cpl, V: int = 5, R_candidates=(128, 256, 512), helper_ca
                     e1.synchronize()
                     if k > 0:
                         times.append(e0.elapsed_time(e1))
-                trials[(r, h)] = sorted(times)[len(times) // 2]
+                trials[(r, h)] = sum(times) / len(times)
         (r_best, h_best), ms = min(trials.items(), key=lambda kv: kv[1])
         R.append(r_best)
         H.append(h_best)
