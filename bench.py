@@ -746,7 +746,7 @@ def main():
         # tuners pick on this workload
         R = [512, 512, 256, 256, 256, 256, 256, 256]
         cpl = [3, 3, 3, 2, 2, 2, 2, 2]
-        helpers = [-1, -1, -1, 0, 0, 0, 0, 0]
+        helpers = [-1, -1, 0, 0, 0, 0, 0, 0]
         print(json.dumps({"one_request": one_request_latency(nd, synth, torch, dev, serve, rss, Ls, R, cpl,
                                                              helpers)}), flush=True)
         return
